@@ -1,0 +1,478 @@
+// CPU oracle for RNS-CKKS evaluation of a dense network with square activations.
+//
+// TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+// leg of the benchmark may load this library.  It shares no code, header,
+// table or constant generator with the GPU library in paper_2104_09164_amd/.
+//
+// Plain and slow on purpose: every residue operation is an unsigned 128-bit
+// product reduced with '%'; the only fast primitive is a textbook
+// radix-2 number-theoretic transform used as a library step to multiply two
+// polynomials modulo (X^N + 1, q).  Everything is in coefficient form.
+//
+// Paper: Methods, "Algorithmic and cryptographic optimizations" (RNS variant
+// of CKKS [CHK+18b]; baby-step/giant-step [HS18]; hoisting; lazy rescaling),
+// "Single-channel homomorphic convolutions" (rotation rho = left slot rotation,
+// MultPlain), "Non-convolutional layers" (collapsed bias + polynomial
+// activation), "Data encryption" (N/2 slots, replicated copies).
+//
+// Array conventions: a polynomial over several primes is limb-major,
+// [limb][N], each residue in [0, q).  A ciphertext at level l is
+// [2][l+1][N].  Primes are numbered q_0..q_L then p_0..p_{K-1}.
+#include <cstdint>
+#include <cstring>
+#include <cmath>
+#include <vector>
+#include <stdexcept>
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------- arithmetic
+static u64 mulmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a * b) % q); }
+static u64 addmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a + b) % q); }
+static u64 submod(u64 a, u64 b, u64 q) { return (u64)(((u128)a + q - (b % q)) % q); }
+static u64 powmod(u64 a, u64 e, u64 q) {
+  u64 r = 1 % q; a %= q;
+  while (e) { if (e & 1) r = mulmod(r, a, q); a = mulmod(a, a, q); e >>= 1; }
+  return r;
+}
+static u64 invmod(u64 a, u64 q) { return powmod(a, q - 2, q); }   // q prime
+static u64 from_signed(i64 v, u64 q) {
+  i64 r = v % (i64)q; if (r < 0) r += (i64)q; return (u64)r;
+}
+
+// ------------------------------------------------------------------- context
+struct NttTables {            // textbook cyclic NTT of length N with a twist by psi
+  u64 q, psi, psi_inv, n_inv;
+  std::vector<u64> psi_pow, psi_inv_pow;   // psi^i, psi^-i for i < N
+  std::vector<u64> w_pow, w_inv_pow;       // omega^i, omega^-i for i < N/2 (omega = psi^2)
+};
+
+struct Ctx {
+  int logN, N;
+  int nq, np, alpha;                       // L+1 = nq, K = np, digit size alpha
+  std::vector<u64> primes;                 // q_0..q_{nq-1}, p_0..p_{np-1}
+  std::vector<NttTables> tab;
+};
+
+// Smallest generator of the order-2N subgroup: x^((q-1)/2N) with x^((q-1)/2) != 1.
+static u64 find_psi(u64 q, int N) {
+  for (u64 x = 2; x < q; ++x) {
+    u64 g = powmod(x, (q - 1) / (2 * (u64)N), q);
+    if (powmod(g, (u64)N, q) == q - 1) return g;   // order exactly 2N
+  }
+  throw std::runtime_error("no 2N-th root");
+}
+
+static void build_tables(NttTables& t, u64 q, int N) {
+  t.q = q; t.psi = find_psi(q, N); t.psi_inv = invmod(t.psi, q); t.n_inv = invmod((u64)N, q);
+  t.psi_pow.resize(N); t.psi_inv_pow.resize(N);
+  t.psi_pow[0] = 1; t.psi_inv_pow[0] = 1;
+  for (int i = 1; i < N; ++i) {
+    t.psi_pow[i] = mulmod(t.psi_pow[i - 1], t.psi, q);
+    t.psi_inv_pow[i] = mulmod(t.psi_inv_pow[i - 1], t.psi_inv, q);
+  }
+  u64 w = mulmod(t.psi, t.psi, q), wi = mulmod(t.psi_inv, t.psi_inv, q);
+  t.w_pow.resize(N / 2); t.w_inv_pow.resize(N / 2);
+  t.w_pow[0] = 1; t.w_inv_pow[0] = 1;
+  for (int i = 1; i < N / 2; ++i) {
+    t.w_pow[i] = mulmod(t.w_pow[i - 1], w, q);
+    t.w_inv_pow[i] = mulmod(t.w_inv_pow[i - 1], wi, q);
+  }
+}
+
+// In-place iterative Cooley-Tukey cyclic transform: bit-reverse, then log N
+// stages of butterflies; 'wp' holds powers of the chosen N-th root.
+static void cyclic_ntt(std::vector<u64>& a, const std::vector<u64>& wp, u64 q, int N, int logN) {
+  for (int i = 0; i < N; ++i) {
+    int r = 0; for (int b = 0; b < logN; ++b) if (i >> b & 1) r |= 1 << (logN - 1 - b);
+    if (i < r) std::swap(a[i], a[r]);
+  }
+  for (int len = 2; len <= N; len <<= 1) {
+    int step = N / len;
+    for (int s = 0; s < N; s += len)
+      for (int k = 0; k < len / 2; ++k) {
+        u64 u = a[s + k], v = mulmod(a[s + k + len / 2], wp[k * step], q);
+        a[s + k] = addmod(u, v, q);
+        a[s + k + len / 2] = submod(u, v, q);
+      }
+  }
+}
+
+// out = a * b mod (X^N + 1, q): twist by psi^i, cyclic convolution, untwist.
+static void polymul(const Ctx& c, int pi, const u64* a, const u64* b, u64* out) {
+  const NttTables& t = c.tab[pi]; const int N = c.N; const u64 q = t.q;
+  std::vector<u64> A(N), B(N);
+  for (int i = 0; i < N; ++i) { A[i] = mulmod(a[i], t.psi_pow[i], q); B[i] = mulmod(b[i], t.psi_pow[i], q); }
+  cyclic_ntt(A, t.w_pow, q, N, c.logN);
+  cyclic_ntt(B, t.w_pow, q, N, c.logN);
+  for (int i = 0; i < N; ++i) A[i] = mulmod(A[i], B[i], q);
+  cyclic_ntt(A, t.w_inv_pow, q, N, c.logN);
+  for (int i = 0; i < N; ++i) out[i] = mulmod(mulmod(A[i], t.n_inv, q), t.psi_inv_pow[i], q);
+}
+
+// Prime index of limb 'i' in a basis "q_0..q_l then p_0..p_{K-1}".
+static int ext_prime(const Ctx& c, int l, int i) { return i <= l ? i : c.nq + (i - l - 1); }
+
+// ------------------------------------------------------------------ sampling
+// SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden gamma,
+// output is the variant-13 finaliser of the new state.
+struct SplitMix64 {
+  u64 s;
+  explicit SplitMix64(u64 seed) : s(seed) {}
+  u64 next() {
+    s += 0x9E3779B97F4A7C15ULL;
+    u64 z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+};
+// Sub-seed for one sampled object: first output of SplitMix64 seeded with master ^ tag.
+static u64 derive_seed(u64 master, u64 tag) { SplitMix64 g(master ^ tag); return g.next(); }
+
+static u64 uniform_mod(SplitMix64& g, u64 q) {
+  u64 lim = (u64)((((u128)1 << 64) / q) * q);      // largest multiple of q not above 2^64
+  for (;;) { u64 w = g.next(); if ((u128)w < (u128)lim || lim == 0) return w % q; }
+}
+static i64 ternary(SplitMix64& g) {
+  for (;;) { u64 v = g.next() & 3; if (v != 3) return (i64)v - 1; }
+}
+// Rounded Gaussian, sigma = 3.2, Box-Muller (one output per pair), |e| <= 19.
+static i64 gaussian(SplitMix64& g) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (;;) {
+    double u1 = (double)((g.next() >> 11) + 1) * 0x1.0p-53;    // (0, 1]
+    double u2 = (double)(g.next() >> 11) * 0x1.0p-53;          // [0, 1)
+    double x = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2) * 3.2;
+    double r = x < 0 ? -std::floor(-x + 0.5) : std::floor(x + 0.5);
+    if (std::fabs(r) <= 19.0) return (i64)r;
+  }
+}
+
+extern "C" {
+
+// --------------------------------------------------------------- lifecycle
+void* orc_ctx_new(int logN, const u64* q, int nq, const u64* p, int np, int alpha) {
+  Ctx* c = new Ctx;
+  c->logN = logN; c->N = 1 << logN; c->nq = nq; c->np = np; c->alpha = alpha;
+  for (int i = 0; i < nq; ++i) c->primes.push_back(q[i]);
+  for (int i = 0; i < np; ++i) c->primes.push_back(p[i]);
+  c->tab.resize(c->primes.size());
+  #pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < (int)c->primes.size(); ++i) build_tables(c->tab[i], c->primes[i], c->N);
+  return c;
+}
+void orc_ctx_free(void* h) { delete (Ctx*)h; }
+u64 orc_psi(void* h, int prime_index) { return ((Ctx*)h)->tab[prime_index].psi; }
+
+// ---------------------------------------------------------------- sampling
+void orc_sample_ternary(u64 seed, int n, i64* out) { SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = ternary(g); }
+void orc_sample_gaussian(u64 seed, int n, i64* out) { SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = gaussian(g); }
+// Uniform residues for the listed primes, limb by limb, coefficient by coefficient.
+void orc_sample_uniform(void* h, u64 seed, int nl, const int* prime_idx, u64* out) {
+  Ctx& c = *(Ctx*)h; SplitMix64 g(seed);
+  for (int l = 0; l < nl; ++l) { u64 q = c.primes[prime_idx[l]]; for (int k = 0; k < c.N; ++k) out[(size_t)l * c.N + k] = uniform_mod(g, q); }
+}
+u64 orc_derive_seed(u64 master, u64 tag) { return derive_seed(master, tag); }
+u64 orc_splitmix_first(u64 seed) { SplitMix64 g(seed); return g.next(); }
+
+// --------------------------------------------------- polynomial primitives
+// Negacyclic product, limb by limb, over prime indices prime_idx[0..nl).
+void orc_polymul(void* h, int nl, const int* prime_idx, const u64* a, const u64* b, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N;
+  #pragma omp parallel for schedule(dynamic)
+  for (int l = 0; l < nl; ++l) polymul(c, prime_idx[l], a + l * N, b + l * N, out + l * N);
+}
+// Galois automorphism a(X) -> a(X^g), g odd: coefficient j moves to j*g mod 2N,
+// negated when it wraps past N (X^N = -1).
+void orc_automorph(void* h, int nl, const int* prime_idx, u64 g, const u64* a, u64* out) {
+  Ctx& c = *(Ctx*)h; const u64 N = c.N;
+  for (int l = 0; l < nl; ++l) {
+    u64 q = c.primes[prime_idx[l]];
+    for (u64 j = 0; j < N; ++j) {
+      u64 t = (j * g) % (2 * N); u64 v = a[l * N + j];
+      if (t < N) out[l * N + t] = v; else out[l * N + t - N] = (q - v) % q;
+    }
+  }
+}
+
+// ------------------------------------------------------- keys, enc, dec
+// s: ternary coefficients (int64).  Residues of s for the listed primes.
+static void signed_to_rns(const Ctx& c, const i64* s, int nl, const int* prime_idx, u64* out) {
+  for (int l = 0; l < nl; ++l) for (int k = 0; k < c.N; ++k) out[(size_t)l * c.N + k] = from_signed(s[k], c.primes[prime_idx[l]]);
+}
+
+// Public key over Q_L: a <- U, e <- chi, b = -a*s + e.  pk = [2][L+1][N] = (b, a).
+void orc_keygen_public(void* h, const i64* s, u64 seed, u64* pk) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = c.nq;
+  std::vector<int> idx(nl); for (int i = 0; i < nl; ++i) idx[i] = i;
+  u64* b = pk; u64* a = pk + nl * N;
+  orc_sample_uniform(h, derive_seed(seed, 0x11), nl, idx.data(), a);
+  std::vector<i64> e(N); orc_sample_gaussian(derive_seed(seed, 0x12), c.N, e.data());
+  std::vector<u64> sr(nl * N), as(nl * N);
+  signed_to_rns(c, s, nl, idx.data(), sr.data());
+  orc_polymul(h, nl, idx.data(), a, sr.data(), as.data());
+  for (int l = 0; l < nl; ++l) { u64 q = c.primes[l];
+    for (size_t k = 0; k < N; ++k) b[l * N + k] = addmod(submod(0, as[l * N + k], q), from_signed(e[k], q), q); }
+}
+
+// Key-switching key from s' (given as residues over all L+1+K primes) to s.
+// For digit j with D_j = {j*alpha, ..., min((j+1)alpha, L+1) - 1}:
+//   a_j <- U(Q_L P), e_j <- chi,
+//   b_j = -a_j s + e_j + [limb in D_j] * (P mod q_i) * s'   (P-limbs carry no s' term).
+// Layout: [dnum][2 = (b, a)][L+1+K][N].
+void orc_keygen_switch(void* h, const i64* s, const u64* s_prime, u64 seed, u64* ksk) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nt = c.nq + c.np;
+  const int dnum = (c.nq + c.alpha - 1) / c.alpha;
+  std::vector<int> idx(nt); for (int i = 0; i < nt; ++i) idx[i] = i;
+  std::vector<u64> sr(nt * N); signed_to_rns(c, s, nt, idx.data(), sr.data());
+  for (int j = 0; j < dnum; ++j) {
+    u64* b = ksk + (size_t)j * 2 * nt * N; u64* a = b + nt * N;
+    orc_sample_uniform(h, derive_seed(seed, 0x100 + 2 * j), nt, idx.data(), a);
+    std::vector<i64> e(N); orc_sample_gaussian(derive_seed(seed, 0x101 + 2 * j), c.N, e.data());
+    std::vector<u64> as(nt * N); orc_polymul(h, nt, idx.data(), a, sr.data(), as.data());
+    for (int l = 0; l < nt; ++l) {
+      u64 q = c.primes[l];
+      bool in_digit = l < c.nq && l / c.alpha == j;
+      u64 Pmod = 1; for (int k = 0; k < c.np; ++k) Pmod = mulmod(Pmod, c.primes[c.nq + k] % q, q);
+      for (size_t k = 0; k < N; ++k) {
+        u64 v = addmod(submod(0, as[l * N + k], q), from_signed(e[k], q), q);
+        if (in_digit) v = addmod(v, mulmod(Pmod, s_prime[l * N + k], q), q);
+        b[l * N + k] = v;
+      }
+    }
+  }
+}
+
+// Public-key encryption of plaintext residues m ([L+1][N]) at the top level:
+// v <- ternary, e0, e1 <- chi;  ct = (v*b + e0 + m, v*a + e1).
+void orc_encrypt(void* h, const u64* pk, const u64* m, u64 seed, u64* ct) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = c.nq;
+  std::vector<int> idx(nl); for (int i = 0; i < nl; ++i) idx[i] = i;
+  std::vector<i64> v(N), e0(N), e1(N);
+  orc_sample_ternary(derive_seed(seed, 0x21), c.N, v.data());
+  orc_sample_gaussian(derive_seed(seed, 0x22), c.N, e0.data());
+  orc_sample_gaussian(derive_seed(seed, 0x23), c.N, e1.data());
+  std::vector<u64> vr(nl * N); signed_to_rns(c, v.data(), nl, idx.data(), vr.data());
+  orc_polymul(h, nl, idx.data(), vr.data(), pk, ct);
+  orc_polymul(h, nl, idx.data(), vr.data(), pk + nl * N, ct + nl * N);
+  for (int l = 0; l < nl; ++l) { u64 q = c.primes[l];
+    for (size_t k = 0; k < N; ++k) {
+      ct[l * N + k] = addmod(addmod(ct[l * N + k], from_signed(e0[k], q), q), m[l * N + k], q);
+      ct[(nl + l) * N + k] = addmod(ct[(nl + l) * N + k], from_signed(e1[k], q), q);
+    } }
+}
+
+// m = c0 + c1 * s over Q_l.
+void orc_decrypt(void* h, const i64* s, const u64* ct, int level, u64* m) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = level + 1;
+  std::vector<int> idx(nl); for (int i = 0; i < nl; ++i) idx[i] = i;
+  std::vector<u64> sr(nl * N); signed_to_rns(c, s, nl, idx.data(), sr.data());
+  orc_polymul(h, nl, idx.data(), ct + nl * N, sr.data(), m);
+  for (int l = 0; l < nl; ++l) for (size_t k = 0; k < N; ++k) m[l * N + k] = addmod(m[l * N + k], ct[l * N + k], c.primes[l]);
+}
+
+// ------------------------------------------------------ evaluation ops
+// Limb-wise add of two ciphertexts (or any [2][l+1][N] arrays) at level l.
+void orc_add(void* h, const u64* a, const u64* b, int level, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N;
+  for (int p = 0; p < 2; ++p) for (int l = 0; l <= level; ++l)
+    for (size_t k = 0; k < N; ++k) { size_t o = ((size_t)p * (level + 1) + l) * N + k; out[o] = addmod(a[o], b[o], c.primes[l]); }
+}
+// ct + pt (pt: [l+1][N]) adds to c0 only.
+void orc_add_plain(void* h, const u64* ct, const u64* pt, int level, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, n1 = (size_t)(level + 1) * N;
+  for (int l = 0; l <= level; ++l) for (size_t k = 0; k < N; ++k) out[l * N + k] = addmod(ct[l * N + k], pt[l * N + k], c.primes[l]);
+  std::memmove(out + n1, ct + n1, n1 * sizeof(u64));
+}
+// MultPlain: both ciphertext polynomials times the plaintext polynomial.
+void orc_mult_plain(void* h, const u64* ct, const u64* pt, int level, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = level + 1;
+  std::vector<int> idx(nl); for (int i = 0; i < nl; ++i) idx[i] = i;
+  orc_polymul(h, nl, idx.data(), ct, pt, out);
+  orc_polymul(h, nl, idx.data(), ct + nl * N, pt, out + nl * N);
+}
+// Rescale by the last prime (floor form of the RNS variant):
+//   c'_i = (c_i - (c_l mod q_i)) * q_l^{-1} mod q_i,  i < l.
+void orc_rescale(void* h, const u64* ct, int level, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const u64 ql = c.primes[level];
+  for (int p = 0; p < 2; ++p) {
+    const u64* in = ct + (size_t)p * (level + 1) * N; u64* o = out + (size_t)p * level * N;
+    const u64* last = in + (size_t)level * N;
+    for (int i = 0; i < level; ++i) {
+      u64 q = c.primes[i]; u64 inv = invmod(ql % q, q);
+      for (size_t k = 0; k < N; ++k) o[i * N + k] = mulmod(submod(in[i * N + k], last[k] % q, q), inv, q);
+    }
+  }
+}
+
+// Fast base conversion of one decomposition digit (ModUp).  x: [l+1][N] over Q_l.
+// D = D_j cap [0, l].  For each target prime t of Q_l u P outside D:
+//   y_t = sum_{i in D} [x_i * (Q_D/q_i)^{-1}]_{q_i} * ((Q_D/q_i) mod t)  mod t.
+// Limbs inside D are copied.  Output: [l+1+K][N] over q_0..q_l, p_0..p_{K-1}.
+void orc_modup(void* h, const u64* x, int level, int digit, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int ne = level + 1 + c.np;
+  int lo = digit * c.alpha, hi = std::min((digit + 1) * c.alpha, level + 1);
+  for (int t = 0; t < ne; ++t) {
+    int pt = ext_prime(c, level, t); u64 qt = c.primes[pt];
+    if (t >= lo && t < hi) { std::memcpy(out + t * N, x + t * N, N * sizeof(u64)); continue; }
+    for (size_t k = 0; k < N; ++k) {
+      u64 acc = 0;
+      for (int i = lo; i < hi; ++i) {
+        u64 qi = c.primes[i];
+        u64 hat_inv = 1, hat_t = 1;                  // (Q_D/q_i)^{-1} mod q_i, (Q_D/q_i) mod t
+        for (int i2 = lo; i2 < hi; ++i2) if (i2 != i) {
+          hat_inv = mulmod(hat_inv, invmod(c.primes[i2] % qi, qi), qi);
+          hat_t = mulmod(hat_t, c.primes[i2] % qt, qt);
+        }
+        u64 v = mulmod(x[i * N + k], hat_inv, qi);
+        acc = addmod(acc, mulmod(v % qt, hat_t, qt), qt);
+      }
+      out[t * N + k] = acc;
+    }
+  }
+}
+
+// ModDown: y over Q_l u P ([l+1+K][N]) -> [l+1][N] over Q_l:
+//   c'_i = (y_i - sum_k [y_{p_k} (P/p_k)^{-1}]_{p_k} * ((P/p_k) mod q_i)) * P^{-1}  mod q_i.
+void orc_moddown(void* h, const u64* y, int level, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int K = c.np;
+  for (int i = 0; i <= level; ++i) {
+    u64 qi = c.primes[i];
+    u64 Pinv = 1; for (int k = 0; k < K; ++k) Pinv = mulmod(Pinv, invmod(c.primes[c.nq + k] % qi, qi), qi);
+    for (size_t n = 0; n < N; ++n) {
+      u64 conv = 0;
+      for (int k = 0; k < K; ++k) {
+        u64 pk = c.primes[c.nq + k];
+        u64 hat_inv = 1, hat_q = 1;
+        for (int k2 = 0; k2 < K; ++k2) if (k2 != k) {
+          u64 p2 = c.primes[c.nq + k2];
+          hat_inv = mulmod(hat_inv, invmod(p2 % pk, pk), pk);
+          hat_q = mulmod(hat_q, p2 % qi, qi);
+        }
+        u64 v = mulmod(y[(size_t)(level + 1 + k) * N + n], hat_inv, pk);
+        conv = addmod(conv, mulmod(v % qi, hat_q, qi), qi);
+      }
+      out[i * N + n] = mulmod(submod(y[i * N + n], conv, qi), Pinv, qi);
+    }
+  }
+}
+
+// Key switching of d ([l+1][N]) with key ksk ([dnum][2][L+1+K][N]).  Every
+// non-empty digit is extended by ModUp, optionally permuted by the
+// automorphism g (g == 1: none), multiplied by (b_j, a_j) restricted to
+// Q_l u P, summed over digits, then brought down by ModDown.  out: [2][l+1][N].
+static void keyswitch_core(Ctx& c, const u64* d, int level, const u64* ksk, u64 g, u64* out) {
+  const size_t N = c.N; const int ne = level + 1 + c.np, nt = c.nq + c.np;
+  const int ndig = (level + 1 + c.alpha - 1) / c.alpha;
+  std::vector<int> eidx(ne); for (int t = 0; t < ne; ++t) eidx[t] = ext_prime(c, level, t);
+  std::vector<u64> ub(ne * N, 0), ua(ne * N, 0), ext(ne * N), tmp(ne * N), prod(ne * N), kb(ne * N), ka(ne * N);
+  for (int j = 0; j < ndig; ++j) {
+    orc_modup(&c, d, level, j, ext.data());
+    if (g != 1) { orc_automorph(&c, ne, eidx.data(), g, ext.data(), tmp.data()); ext.swap(tmp); }
+    const u64* kbj = ksk + (size_t)j * 2 * nt * N; const u64* kaj = kbj + (size_t)nt * N;
+    for (int t = 0; t < ne; ++t) {
+      std::memcpy(&kb[t * N], kbj + (size_t)eidx[t] * N, N * sizeof(u64));
+      std::memcpy(&ka[t * N], kaj + (size_t)eidx[t] * N, N * sizeof(u64));
+    }
+    orc_polymul(&c, ne, eidx.data(), ext.data(), kb.data(), prod.data());
+    for (int t = 0; t < ne; ++t) for (size_t k = 0; k < N; ++k) ub[t * N + k] = addmod(ub[t * N + k], prod[t * N + k], c.primes[eidx[t]]);
+    orc_polymul(&c, ne, eidx.data(), ext.data(), ka.data(), prod.data());
+    for (int t = 0; t < ne; ++t) for (size_t k = 0; k < N; ++k) ua[t * N + k] = addmod(ua[t * N + k], prod[t * N + k], c.primes[eidx[t]]);
+  }
+  orc_moddown(&c, ub.data(), level, out);
+  orc_moddown(&c, ua.data(), level, out + (size_t)(level + 1) * N);
+}
+
+void orc_keyswitch(void* h, const u64* d, int level, const u64* ksk, u64* out) {
+  keyswitch_core(*(Ctx*)h, d, level, ksk, 1, out);
+}
+
+// Galois element of a left slot rotation by r: 5^(r mod N/2) mod 2N.
+u64 orc_galois_elt(void* h, i64 r) {
+  Ctx& c = *(Ctx*)h; const i64 half = c.N / 2;
+  i64 rr = ((r % half) + half) % half;
+  return powmod(5, (u64)rr, 2 * (u64)c.N);
+}
+
+// Rotation rho^r, hoisted order: ModUp(c1) first, then the automorphism on every
+// extended digit, key inner product, ModDown; output = (sigma(c0) + u_b, u_a).
+// r == 0 (mod N/2) is a copy.
+void orc_rotate(void* h, const u64* ct, int level, i64 r, const u64* ksk, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1;
+  u64 g = orc_galois_elt(h, r);
+  if (g == 1) { std::memcpy(out, ct, 2 * nl * N * sizeof(u64)); return; }
+  std::vector<u64> ks(2 * nl * N), c0r(nl * N);
+  keyswitch_core(c, ct + nl * N, level, ksk, g, ks.data());
+  std::vector<int> idx(nl); for (size_t i = 0; i < nl; ++i) idx[i] = (int)i;
+  orc_automorph(h, (int)nl, idx.data(), g, ct, c0r.data());
+  for (size_t l = 0; l < nl; ++l) for (size_t k = 0; k < N; ++k) {
+    out[l * N + k] = addmod(c0r[l * N + k], ks[l * N + k], c.primes[l]);
+    out[(nl + l) * N + k] = ks[(nl + l) * N + k];
+  }
+}
+
+// Square with relinearisation: d0 = c0^2, d1 = 2 c0 c1, d2 = c1^2;
+// (u_b, u_a) = KeySwitch(d2, rlk); output (d0 + u_b, d1 + u_a).
+void orc_square(void* h, const u64* ct, int level, const u64* rlk, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1;
+  std::vector<int> idx(nl); for (size_t i = 0; i < nl; ++i) idx[i] = (int)i;
+  std::vector<u64> d0(nl * N), d1(nl * N), d2(nl * N), ks(2 * nl * N);
+  orc_polymul(h, (int)nl, idx.data(), ct, ct, d0.data());
+  orc_polymul(h, (int)nl, idx.data(), ct, ct + nl * N, d1.data());
+  orc_polymul(h, (int)nl, idx.data(), ct + nl * N, ct + nl * N, d2.data());
+  keyswitch_core(c, d2.data(), level, rlk, 1, ks.data());
+  for (size_t l = 0; l < nl; ++l) { u64 q = c.primes[l];
+    for (size_t k = 0; k < N; ++k) {
+      out[l * N + k] = addmod(d0[l * N + k], ks[l * N + k], q);
+      out[(nl + l) * N + k] = addmod(addmod(d1[l * N + k], d1[l * N + k], q), ks[(nl + l) * N + k], q);
+    } }
+}
+
+// Dense layer y = W x + b on a ciphertext whose slots hold x with period n.
+// Baby-step form (paper: "Algorithmic and cryptographic optimizations", the
+// baby-step rewriting of the convolution sum): diagonal k = n1*j + i of W,
+// pre-rotated by -n1*j, is plaintext pts[k] ([m][l+1][N]).
+//   r_i = rho^i(ct), i < n1                    (baby steps; r_0 = ct)
+//   s_j = sum_i MultPlain(r_i, pts[n1 j + i])  (inner sums)
+//   z   = s_0 + sum_{j >= 1} rho^{n1 j}(s_j)   (giant steps, increasing j)
+//   z  += rho^t(z) for t = n/2, n/4, ..., m    (rotate-and-sum)
+//   z  += bias (AddPlain) if given.            No rescale.
+// Rotation keys: steps[u] -> keys[u] ([dnum][2][L+1+K][N]).
+static const u64* find_key(int nrot, const i64* steps, const u64* const* keys, i64 r) {
+  for (int u = 0; u < nrot; ++u) if (steps[u] == r) return keys[u];
+  throw std::runtime_error("missing rotation key");
+}
+int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+              int nrot, const i64* steps, const u64* const* keys, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, csz = 2 * nl * N;
+  if (m <= 0 || n <= 0 || n1 <= 0 || n % m || m % n1 || (c.N / 2) % n) return -1;
+  const int n2 = m / n1;
+  try {
+    std::vector<std::vector<u64>> baby(n1, std::vector<u64>(csz));
+    std::memcpy(baby[0].data(), ct, csz * sizeof(u64));
+    for (int i = 1; i < n1; ++i) orc_rotate(h, ct, level, i, find_key(nrot, steps, keys, i), baby[i].data());
+    std::vector<u64> z(csz, 0), s(csz), prod(csz), rot(csz);
+    for (int j = 0; j < n2; ++j) {
+      std::fill(s.begin(), s.end(), 0);
+      for (int i = 0; i < n1; ++i) {
+        orc_mult_plain(h, baby[i].data(), pts + (size_t)(n1 * j + i) * nl * N, level, prod.data());
+        orc_add(h, s.data(), prod.data(), level, s.data());
+      }
+      if (j == 0) { z = s; continue; }
+      orc_rotate(h, s.data(), level, (i64)n1 * j, find_key(nrot, steps, keys, (i64)n1 * j), rot.data());
+      orc_add(h, z.data(), rot.data(), level, z.data());
+    }
+    for (int t = n / 2; t >= m; t /= 2) {
+      orc_rotate(h, z.data(), level, t, find_key(nrot, steps, keys, t), rot.data());
+      orc_add(h, z.data(), rot.data(), level, z.data());
+    }
+    if (bias) orc_add_plain(h, z.data(), bias, level, z.data());
+    std::memcpy(out, z.data(), csz * sizeof(u64));
+  } catch (const std::exception&) { return -3; }
+  return 0;
+}
+
+}  // extern "C"
