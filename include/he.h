@@ -1,0 +1,209 @@
+/* he.h -- C ABI of the MI355X library for encrypted dense-network inference
+ * over RNS-CKKS (homomorphic evaluation of y = W x + b and x^2 on slot-packed
+ * ciphertexts).
+ *
+ * Paper: "Secure Human Action Recognition by Encrypted Neural Network
+ * Inference", Methods.  The cloud holds only evaluation keys and the
+ * cleartext model, receives encrypted inputs and returns one encrypted result;
+ * it never holds the secret key and never decrypts (Methods, "Threat model";
+ * Results, the three-party protocol).  Hence no call here takes a secret key,
+ * samples randomness, encrypts or decrypts: those belong to the client.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Return value: 0 (HE_OK) or a negative HE_E* code; he_strerror() names it.
+ * Argument checks run synchronously on the host before anything is enqueued;
+ * a failed check enqueues nothing and leaves every output untouched.
+ *
+ * Ring: R_Q = Z_Q[X]/(X^N + 1), N = 2^log_n, 2^10 <= N <= 2^17, N/2 slots.
+ * Primes: q_0..q_L (ciphertext modulus chain) and p_0..p_{K-1} (special
+ * primes of hybrid key switching), all distinct, prime, = 1 mod 2N, < 2^61.
+ * Decomposition: digits of alpha consecutive q-primes starting at q_0,
+ * dnum = ceil((L+1)/alpha), alpha <= K.
+ *
+ * Interchange format (host <-> library): COEFFICIENT form, limb-major, every
+ * residue in [0, q).  A polynomial over primes r_0..r_{m-1} is
+ * uint64[m][N]; a ciphertext at level l is uint64[2][l+1][N] = (c0, c1) with
+ * decryption c0 + c1*s mod Q_l.  Coefficient form is the unique
+ * representation, so outputs can be compared bit for bit with any other
+ * implementation of the same steps.
+ *
+ * Device format: ciphertexts live in caller-owned device memory (he_ct.dev)
+ * in the library's internal NTT (evaluation) form, same [2][l+1][N] shape.
+ * The caller owns ALL device memory (ciphertexts, key storage, plaintext
+ * storage, workspace); the library owns only its host tables and small
+ * device tables allocated by he_ctx_create and freed by he_ctx_destroy.
+ *
+ * Streams: every evaluation call enqueues on the context's HIP stream and
+ * returns without waiting; device faults surface at he_sync / he_ct_export.
+ *
+ * Rotations: rho^r rotates the slot vector LEFT by r (Methods,
+ * "Single-channel homomorphic convolutions"); slot j sits at the root
+ * zeta^(5^j mod 2N), so rho^r is the automorphism X -> X^(5^(r mod N/2)).
+ * Key switching is the hybrid RNS method: ModUp of each digit, inner product
+ * with the key, ModDown (Methods, "Algorithmic and cryptographic
+ * optimizations": RNS variant of CKKS, hoisting).
+ *
+ * Not thread-safe per context: calls on one he_ctx must not overlap.
+ */
+#ifndef HE_H_
+#define HE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HE_OK        0
+#define HE_EINVAL   (-1)   /* null pointer, bad shape (m does not divide n, ...) */
+#define HE_EPARAM   (-2)   /* bad ring parameters */
+#define HE_ENOKEY   (-3)   /* missing rotation key / relinearisation key */
+#define HE_ELEVEL   (-4)   /* rescale at level 0, operands at different levels */
+#define HE_ESCALE   (-5)   /* operand scales differ by more than 2^-30 relative */
+#define HE_ENOMEM   (-6)   /* workspace, key or plaintext buffer too small */
+#define HE_EDEVICE  (-7)   /* HIP runtime error */
+#define HE_ESTATE   (-8)   /* context not bound to a workspace / keys not loaded */
+
+#define HE_MAX_BATCH 64    /* ciphertexts per batched call */
+#define HE_MAX_PRIMES 64   /* L+1+K */
+
+typedef struct he_ctx he_ctx;
+typedef struct he_dense he_dense;
+
+/* A ciphertext handle.  dev: caller-owned device buffer of at least
+ * he_ct_bytes(ctx, level) bytes holding [2][level+1][N] words in NTT form.
+ * scale: the CKKS scaling factor (IEEE double), tracked by every call. */
+typedef struct {
+  uint64_t* dev;
+  uint32_t level;
+  double scale;
+} he_ct;
+
+typedef struct {
+  uint32_t log_n;         /* N = 2^log_n */
+  uint32_t n_q;           /* L + 1 */
+  const uint64_t* q;      /* q_0..q_L */
+  uint32_t n_p;           /* K */
+  const uint64_t* p;      /* p_0..p_{K-1} */
+  uint32_t alpha;         /* primes per digit (1 <= alpha <= K) */
+} he_params;
+
+const char* he_strerror(int code);
+
+/* Prime selection helper (parameter set-up, host only): the `count` largest
+ * primes 2^bits + 1 - k*2N (k >= 1) that are not listed in taken[0..n_taken),
+ * in descending order, written to out[0..count).  bits in [20, 61]. */
+int he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uint64_t* taken, uint32_t n_taken,
+                  uint64_t* out);
+
+/* Validates params (HE_EPARAM on failure), builds NTT, base-conversion and
+ * rescale tables, uploads them.  hip_stream: a hipStream_t (NULL = default
+ * stream).  *out receives the handle. */
+int he_ctx_create(const he_params* params, void* hip_stream, he_ctx** out);
+int he_ctx_destroy(he_ctx* ctx);
+int he_ctx_set_stream(he_ctx* ctx, void* hip_stream);
+
+/* Sizes in bytes of caller-owned device buffers. */
+size_t he_ct_bytes(const he_ctx* ctx, uint32_t level);
+/* Key storage for the relinearisation key plus n_rot rotation keys. */
+size_t he_key_bytes(const he_ctx* ctx, uint32_t n_rot);
+/* Workspace for batched calls of up to max_batch ciphertexts and dense
+ * layers with baby-step count <= max_n1 and giant-step count <= max_n2. */
+size_t he_workspace_bytes(const he_ctx* ctx, uint32_t max_batch, uint32_t max_n1, uint32_t max_n2);
+/* Plaintext storage of one dense layer (m diagonals at `level`, + bias). */
+size_t he_dense_bytes(const he_ctx* ctx, uint32_t level, uint32_t m, int has_bias);
+
+/* Binds caller-owned scratch (device, 256-byte aligned).  No evaluation call
+ * allocates device memory; all temporaries live here.  The limits passed to
+ * he_workspace_bytes are recorded and enforced (HE_ENOMEM beyond them). */
+int he_ctx_bind(he_ctx* ctx, void* workspace_dev, size_t bytes, uint32_t max_batch, uint32_t max_n1,
+                uint32_t max_n2);
+
+/* Uploads evaluation keys (host, coefficient form) into caller-owned device
+ * storage key_dev (>= he_key_bytes(ctx, n_rot)), converting to the internal
+ * form.  Each key: uint64[dnum][2][L+1+K][N] = per digit (b_j, a_j) over
+ * q_0..q_L then p_0..p_{K-1}, with b_j = -a_j s + e_j + g_j s' and gadget
+ * g_j = P (Q/Q_j) [(Q/Q_j)^{-1}]_{Q_j}.  relin (s' = s^2) may be NULL if
+ * he_square is never called.  rot[u] is the key of the left rotation by
+ * steps[u] (s' = s(X^(5^steps[u]))).  Synchronous; replaces earlier keys. */
+int he_load_keys(he_ctx* ctx, const uint64_t* relin, uint32_t n_rot, const int32_t* steps,
+                 const uint64_t* const* rot, void* key_dev, size_t key_bytes);
+
+/* Uploads one dense layer y = W x + b (W: m x n, m | n, n | N/2, powers of
+ * two, n1 | m) in the baby-step/giant-step form (Methods, "Algorithmic and
+ * cryptographic optimizations", baby-step strategy with
+ * rho^(a+b) = rho^a o rho^b):
+ *   pt_diag: host uint64[m][level+1][N], coefficient form; entry k = n1*j + i
+ *            encodes the k-th hybrid diagonal d_k[s] = W[s mod m][(s+k) mod n]
+ *            pre-rotated by -n1*j and replicated with period n, at scale
+ *            pt_scale, over q_0..q_level only (level-aware encoding).
+ *   bias:    host uint64[level+1][N] (the bias replicated with period m, at
+ *            scale bias_scale) or NULL.
+ * dev: caller-owned device storage >= he_dense_bytes(ctx, level, m, bias!=0).
+ * *out receives a host handle (free with he_dense_free). Synchronous. */
+int he_dense_load(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
+                  const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes,
+                  he_dense** out);
+int he_dense_free(he_dense* d);
+
+/* Ciphertext import/export.  *_import: host coefficient form -> inout->dev
+ * (caller sets inout->dev; level and scale are written).  *_export: blocking
+ * (synchronises the stream), writes host coefficient form [2][level+1][N].
+ * The _dev variants take device coefficient buffers and are asynchronous. */
+int he_ct_import(he_ctx* ctx, const uint64_t* coeff_host, uint32_t level, double scale, he_ct* inout);
+int he_ct_export(he_ctx* ctx, const he_ct* ct, uint64_t* coeff_host);
+int he_ct_from_coeff_dev(he_ctx* ctx, const uint64_t* coeff_dev, uint32_t level, double scale, he_ct* inout);
+int he_ct_to_coeff_dev(he_ctx* ctx, const he_ct* ct, uint64_t* coeff_dev);
+
+/* Dense layer: baby steps rho^i(in) for i < n1 with ONE shared ModUp
+ * (hoisting), inner sums s_j = sum_i MultPlain(rho^i(in), pt_{n1 j + i}),
+ * giant steps z = s_0 + sum_{j>=1} rho^(n1 j)(s_j) in increasing j,
+ * rotate-and-sum z += rho^t(z) for t = n/2, n/4, ..., m, then + bias.
+ * No rescale (lazy rescaling: the caller rescales once).
+ * out->scale = in->scale * pt_scale; out->level = in->level.
+ * Needs rotation keys for every step used.  out->dev must not alias in->dev. */
+int he_eval_dense(he_ctx* ctx, const he_ct* in, const he_dense* layer, he_ct* out);
+/* Square with relinearisation: (c0^2, 2 c0 c1, c1^2), key switch of c1^2 with
+ * the relinearisation key, added.  out->scale = scale^2.  No rescale. */
+int he_square(he_ctx* ctx, const he_ct* in, he_ct* out);
+/* Left rotation by step (rho^step): ModUp(c1), automorphism of every digit,
+ * key inner product, ModDown, + automorphism of c0.  step = 0 mod N/2 copies. */
+int he_rotate(he_ctx* ctx, const he_ct* in, int32_t step, he_ct* out);
+/* Hoisted rotations of one ciphertext by steps[0..n_steps): one ModUp shared
+ * by all (Methods, hoisting); out[u] = rho^steps[u](in), bit-identical to
+ * he_rotate(in, steps[u]). */
+int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, uint32_t n_steps, const int32_t* steps, he_ct* out);
+/* Rescale by q_level: c_i <- (c_i - (c_level mod q_i)) q_level^{-1} mod q_i
+ * (floor form), level - 1, scale / q_level.  out may alias in. */
+int he_rescale(he_ctx* ctx, const he_ct* in, he_ct* out);
+/* Limb-wise sum of two ciphertexts at equal level and scale. */
+int he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out);
+
+/* Batched forms: n <= HE_MAX_BATCH independent ciphertexts (e.g. from
+ * different requests) in one set of launches; keys and plaintexts are read
+ * once per batch.  in[i], out[i] obey the single-call rules; all in[i] share
+ * one level and one scale.  Results are bit-identical to n single calls. */
+int he_eval_dense_batch(he_ctx* ctx, uint32_t n, const he_ct* in, const he_dense* layer, he_ct* out);
+int he_square_batch(he_ctx* ctx, uint32_t n, const he_ct* in, he_ct* out);
+int he_rescale_batch(he_ctx* ctx, uint32_t n, const he_ct* in, he_ct* out);
+/* out[i * n_steps + u] = rho^steps[u](in[i]). */
+int he_rotate_hoisted_batch(he_ctx* ctx, uint32_t n, const he_ct* in, uint32_t n_steps, const int32_t* steps,
+                            he_ct* out);
+
+/* Kernel-level entry: negacyclic NTT (inverse != 0: INTT) in place on
+ * n_items device buffers, each holding `limbs` consecutive limb-polys for
+ * primes first_prime .. first_prime + limbs - 1 (indices into q_0..q_L,
+ * p_0..p_{K-1}).  Forward output is the library's NTT order; the inverse
+ * maps it back to coefficients.  items: host array of device pointers. */
+int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first_prime, uint32_t limbs,
+           int inverse);
+
+/* Waits for all work enqueued on the context's stream. */
+int he_sync(he_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_H_ */

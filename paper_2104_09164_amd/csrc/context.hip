@@ -1,0 +1,438 @@
+// Context set-up, table generation, device uploads and the non-evaluation
+// entry points of include/he.h.
+#include <cstring>
+#include <new>
+#include <algorithm>
+#include "rns_kernels.hpp"
+
+typedef unsigned __int128 u128;
+
+namespace {
+
+// ---------------------------------------------------------- host number theory
+u64 mul_mod(u64 a, u64 b, u64 m) { return (u64)((u128)a * b % m); }
+u64 pow_mod(u64 b, u64 e, u64 m) {
+  u64 r = 1 % m;
+  for (b %= m; e; e >>= 1, b = mul_mod(b, b, m))
+    if (e & 1) r = mul_mod(r, b, m);
+  return r;
+}
+u64 inv_mod(u64 a, u64 m) { return pow_mod(a % m, m - 2, m); }   // m prime
+u64 shoup_of(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+// Deterministic Miller-Rabin for 64-bit integers (first twelve prime bases).
+bool is_prime64(u64 n) {
+  if (n < 2) return false;
+  static const u64 small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (u64 p : small) {
+    if (n % p == 0) return n == p;
+  }
+  u64 d = n - 1;
+  int s = 0;
+  while (!(d & 1)) { d >>= 1; ++s; }
+  for (u64 a : small) {
+    u64 x = pow_mod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool composite = true;
+    for (int r = 1; r < s; ++r) {
+      x = mul_mod(x, x, n);
+      if (x == n - 1) { composite = false; break; }
+    }
+    if (composite) return false;
+  }
+  return true;
+}
+
+// A primitive 2N-th root of unity mod q: the (q-1)/2N-th power of a quadratic
+// non-residue (Euler's criterion) has order exactly 2N since 2N is a power of two.
+u64 root_2n(u64 q, u32 N) {
+  for (u64 x = 3;; ++x) {
+    if (pow_mod(x, (q - 1) / 2, q) != q - 1) continue;
+    return pow_mod(x, (q - 1) / (2 * (u64)N), q);
+  }
+}
+
+u32 bitrev(u32 x, u32 bits) {
+  u32 r = 0;
+  for (u32 i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// -q^{-1} mod 2^64 by Newton iteration (each step doubles the correct bits).
+u64 neg_inv64(u64 q) {
+  u64 x = q;
+  for (int i = 0; i < 6; ++i) x *= 2 - q * x;
+  return (u64)0 - x;
+}
+
+PrimeConst make_pc(u64 q, u32 N) {
+  PrimeConst p;
+  p.q = q;
+  p.qneg = neg_inv64(q);
+  p.mu = ~(u64)0 / q;
+  p.rmod = (u64)(((u128)1 << 64) % q);
+  p.rmod_sh = shoup_of(p.rmod, q);
+  p.r2 = mul_mod(p.rmod, p.rmod, q);
+  p.ninv = inv_mod(N, q);
+  p.ninv_sh = shoup_of(p.ninv, q);
+  return p;
+}
+// x 2^64 mod m (Montgomery form of a host constant)
+u64 to_mont_host(u64 x, u64 m) { return (u64)(((u128)(x % m) << 64) % m); }
+
+template <class T>
+int upload(he_ctx* c, T** dptr, const std::vector<T>& h) {
+  if (hipMalloc((void**)dptr, h.size() * sizeof(T)) != hipSuccess) return HE_EDEVICE;
+  if (hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return HE_EDEVICE;
+  return HE_OK;
+}
+
+int build_tables(he_ctx* c) {
+  const u32 N = c->N, nt = nt_of(c);
+  c->h_pc.resize(nt);
+  std::vector<u64> tw((size_t)nt * 4 * N);
+  for (u32 i = 0; i < nt; ++i) {
+    const u64 q = c->primes[i];
+    c->h_pc[i] = make_pc(q, N);
+    const u64 psi = root_2n(q, N), ipsi = inv_mod(psi, q);
+    std::vector<u64> pw(N), ipw(N);
+    pw[0] = ipw[0] = 1;
+    for (u32 k = 1; k < N; ++k) { pw[k] = mul_mod(pw[k - 1], psi, q); ipw[k] = mul_mod(ipw[k - 1], ipsi, q); }
+    u64* t = tw.data() + (size_t)i * 4 * N;
+    for (u32 k = 0; k < N; ++k) {
+      const u32 e = bitrev(k, c->log_n);
+      t[k] = pw[e];
+      t[N + k] = shoup_of(pw[e], q);
+      t[2 * N + k] = ipw[e];
+      t[3 * N + k] = shoup_of(ipw[e], q);
+    }
+  }
+  int rc;
+  if ((rc = upload(c, &c->d_pc, c->h_pc))) return rc;
+  if ((rc = upload(c, &c->d_tw, tw))) return rc;
+
+  // ModUp: for every level l and digit j, D = [j alpha, min((j+1) alpha, l+1)).
+  const u32 nq = c->nq, np = c->np, A = c->alpha, dn = c->dnum;
+  std::vector<u64> hinv((size_t)nq * dn * A * 2, 0), hmod((size_t)nq * dn * A * nt, 0);
+  for (u32 l = 0; l < nq; ++l)
+    for (u32 j = 0; j < dn; ++j) {
+      const u32 lo = j * A, hi = std::min((j + 1) * A, l + 1);
+      for (u32 i = lo; i < hi; ++i) {
+        const u64 qi = c->primes[i];
+        u64 inv = 1;
+        for (u32 i2 = lo; i2 < hi; ++i2)
+          if (i2 != i) inv = mul_mod(inv, inv_mod(c->primes[i2] % qi, qi), qi);
+        const size_t e = ((size_t)l * dn + j) * A + (i - lo);
+        hinv[2 * e] = inv;
+        hinv[2 * e + 1] = shoup_of(inv, qi);
+        for (u32 t = 0; t < nt; ++t) {
+          const u64 m = c->primes[t];
+          u64 h = 1 % m;
+          for (u32 i2 = lo; i2 < hi; ++i2)
+            if (i2 != i) h = mul_mod(h, c->primes[i2] % m, m);
+          hmod[e * nt + t] = to_mont_host(h, m);
+        }
+      }
+    }
+  if ((rc = upload(c, &c->d_modup_hatinv, hinv))) return rc;
+  if ((rc = upload(c, &c->d_modup_hatmod, hmod))) return rc;
+
+  // ModDown.
+  std::vector<u64> md((size_t)np * 2 + (size_t)np * nq + (size_t)nq * 2);
+  for (u32 k = 0; k < np; ++k) {
+    const u64 pk = c->primes[nq + k];
+    u64 inv = 1;
+    for (u32 k2 = 0; k2 < np; ++k2)
+      if (k2 != k) inv = mul_mod(inv, inv_mod(c->primes[nq + k2] % pk, pk), pk);
+    md[2 * k] = inv;
+    md[2 * k + 1] = shoup_of(inv, pk);
+    for (u32 i = 0; i < nq; ++i) {
+      const u64 qi = c->primes[i];
+      u64 h = 1;
+      for (u32 k2 = 0; k2 < np; ++k2)
+        if (k2 != k) h = mul_mod(h, c->primes[nq + k2] % qi, qi);
+      md[2 * np + (size_t)k * nq + i] = to_mont_host(h, qi);
+    }
+  }
+  for (u32 i = 0; i < nq; ++i) {
+    const u64 qi = c->primes[i];
+    u64 P = 1;
+    for (u32 k = 0; k < np; ++k) P = mul_mod(P, c->primes[nq + k] % qi, qi);
+    const u64 pinv = inv_mod(P, qi);
+    md[2 * np + (size_t)np * nq + 2 * i] = pinv;
+    md[2 * np + (size_t)np * nq + 2 * i + 1] = shoup_of(pinv, qi);
+  }
+  if ((rc = upload(c, &c->d_moddown, md))) return rc;
+
+  // Rescale: q_l^{-1} mod q_i for i < l.
+  std::vector<u64> rs((size_t)nq * nq * 2, 0);
+  for (u32 l = 1; l < nq; ++l)
+    for (u32 i = 0; i < l; ++i) {
+      const u64 qi = c->primes[i], inv = inv_mod(c->primes[l] % qi, qi);
+      rs[((size_t)l * nq + i) * 2] = inv;
+      rs[((size_t)l * nq + i) * 2 + 1] = shoup_of(inv, qi);
+    }
+  return upload(c, &c->d_rescale, rs);
+}
+
+void free_tables(he_ctx* c) {
+  hipFree(c->d_pc);
+  hipFree(c->d_tw);
+  hipFree(c->d_modup_hatinv);
+  hipFree(c->d_modup_hatmod);
+  hipFree(c->d_moddown);
+  hipFree(c->d_rescale);
+}
+
+PolyBatch one_item(u64* p, u32 npoly, u32 period, u32 first_prime) {
+  PolyBatch pb;
+  std::memset(&pb, 0, sizeof(pb));
+  pb.src[0] = pb.dst[0] = p;
+  pb.nitems = 1;
+  pb.npoly = npoly;
+  for (u32 r = 0; r < npoly; ++r) pb.prime[r] = (uint8_t)(first_prime + r % period);
+  return pb;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* he_strerror(int code) {
+  switch (code) {
+    case HE_OK: return "ok";
+    case HE_EINVAL: return "invalid argument or shape";
+    case HE_EPARAM: return "invalid ring parameters";
+    case HE_ENOKEY: return "missing evaluation key";
+    case HE_ELEVEL: return "level mismatch or rescale at level 0";
+    case HE_ESCALE: return "scale mismatch";
+    case HE_ENOMEM: return "buffer too small";
+    case HE_EDEVICE: return "HIP runtime error";
+    case HE_ESTATE: return "context not ready (workspace not bound or keys not loaded)";
+    default: return "unknown error";
+  }
+}
+
+int he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uint64_t* taken, uint32_t n_taken,
+                  uint64_t* out) {
+  if (!out || (n_taken && !taken) || bits < 20 || bits > 61 || log_n < 1 || log_n > 17) return HE_EINVAL;
+  const u64 two_n = 2ull << log_n;
+  u64 c = (1ull << bits) + 1;
+  for (u32 got = 0; got < count;) {
+    if (c <= two_n) return HE_EPARAM;
+    c -= two_n;
+    bool used = false;
+    for (u32 i = 0; i < n_taken; ++i) used |= taken[i] == c;
+    for (u32 i = 0; i < got; ++i) used |= out[i] == c;
+    if (!used && is_prime64(c)) out[got++] = c;
+  }
+  return HE_OK;
+}
+
+int he_ctx_create(const he_params* pr, void* stream, he_ctx** out) {
+  if (!pr || !out || !pr->q || (pr->n_p && !pr->p)) return HE_EINVAL;
+  if (pr->log_n < 10 || pr->log_n > 17) return HE_EPARAM;
+  if (pr->n_q < 1 || pr->n_p < 1 || pr->n_q + pr->n_p > HE_MAX_PRIMES) return HE_EPARAM;
+  if (pr->alpha < 1 || pr->alpha > pr->n_p || pr->alpha > 8 || pr->n_p > 8) return HE_EPARAM;
+  const u32 dnum = (pr->n_q + pr->alpha - 1) / pr->alpha;
+  if (dnum > 8 || dnum * (pr->n_q + pr->n_p) > HE_MAX_POLYS) return HE_EPARAM;
+  const u64 two_n = 2ull << pr->log_n;
+  std::vector<u64> primes(pr->q, pr->q + pr->n_q);
+  primes.insert(primes.end(), pr->p, pr->p + pr->n_p);
+  for (size_t i = 0; i < primes.size(); ++i) {
+    const u64 q = primes[i];
+    if (q >= (1ull << 61) || q % two_n != 1 || !is_prime64(q)) return HE_EPARAM;
+    for (size_t j = 0; j < i; ++j)
+      if (primes[j] == q) return HE_EPARAM;
+  }
+  he_ctx* c = new (std::nothrow) he_ctx;
+  if (!c) return HE_ENOMEM;
+  c->log_n = pr->log_n;
+  c->N = 1u << pr->log_n;
+  c->nq = pr->n_q;
+  c->np = pr->n_p;
+  c->alpha = pr->alpha;
+  c->dnum = dnum;
+  c->primes = primes;
+  c->stream = (hipStream_t)stream;
+  hipGetDevice(&c->device);
+  int rc = build_tables(c);
+  if (rc) {
+    free_tables(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return HE_OK;
+}
+
+int he_ctx_destroy(he_ctx* c) {
+  if (!c) return HE_EINVAL;
+  hipStreamSynchronize(c->stream);
+  free_tables(c);
+  delete c;
+  return HE_OK;
+}
+
+int he_ctx_set_stream(he_ctx* c, void* stream) {
+  if (!c) return HE_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return HE_OK;
+}
+
+size_t he_ct_bytes(const he_ctx* c, uint32_t level) {
+  return c ? (size_t)2 * (level + 1) * c->N * sizeof(u64) : 0;
+}
+
+size_t he_key_bytes(const he_ctx* c, uint32_t n_rot) {
+  return c ? (size_t)(1 + n_rot) * c->dnum * 2 * nt_of(c) * c->N * sizeof(u64) : 0;
+}
+
+size_t he_dense_bytes(const he_ctx* c, uint32_t level, uint32_t m, int has_bias) {
+  return c ? ((size_t)m + (has_bias ? 1 : 0)) * (level + 1) * c->N * sizeof(u64) : 0;
+}
+
+int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t* steps, const uint64_t* const* rot,
+                 void* key_dev, size_t key_bytes) {
+  if (!c || !key_dev || (n_rot && (!steps || !rot))) return HE_EINVAL;
+  if (key_bytes < he_key_bytes(c, n_rot)) return HE_ENOMEM;
+  for (u32 u = 0; u < n_rot; ++u)
+    if (!rot[u]) return HE_EINVAL;
+  const size_t words = (size_t)c->dnum * 2 * nt_of(c) * c->N;
+  const u32 npoly = c->dnum * 2 * nt_of(c);
+  u64* base = (u64*)key_dev;
+  c->have_relin = false;
+  c->relin_dev = nullptr;
+  c->rot.clear();
+  auto put = [&](u64* dst, const u64* src) -> int {
+    if (hipMemcpyAsync(dst, src, words * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
+    PolyBatch pb = one_item(dst, npoly, nt_of(c), 0);
+    int rc = launch_ntt(c, pb, false);
+    if (rc) return rc;
+    return launch_to_mont(c, pb);
+  };
+  int rc;
+  if (relin) {
+    if ((rc = put(base, relin))) return rc;
+    c->relin_dev = base;
+    c->have_relin = true;
+  }
+  const u64 two_n = 2ull * c->N;
+  for (u32 u = 0; u < n_rot; ++u) {
+    u64* dst = base + (size_t)(1 + u) * words;
+    if ((rc = put(dst, rot[u]))) return rc;
+    const int64_t half = c->N / 2;
+    const u64 r = (u64)(((steps[u] % half) + half) % half);
+    c->rot.push_back({steps[u], (u32)pow_mod(5, r, two_n), dst});
+  }
+  return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
+                  const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes, he_dense** out) {
+  if (!c || !pt_diag || !dev || !out) return HE_EINVAL;
+  auto pow2 = [](u32 v) { return v && !(v & (v - 1)); };
+  if (level >= c->nq) return HE_ELEVEL;
+  if (!pow2(m) || !pow2(n) || !pow2(n1) || n % m || m % n1 || (c->N / 2) % n) return HE_EINVAL;
+  if (bytes < he_dense_bytes(c, level, m, bias != nullptr)) return HE_ENOMEM;
+  const size_t limb = c->N, per = (size_t)(level + 1) * limb;
+  u64* d = (u64*)dev;
+  if (hipMemcpyAsync(d, pt_diag, (size_t)m * per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return HE_EDEVICE;
+  for (u32 k0 = 0; k0 < m; k0 += HE_MAXB) {
+    PolyBatch pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.nitems = std::min<u32>(HE_MAXB, m - k0);
+    pb.npoly = level + 1;
+    for (u32 b = 0; b < pb.nitems; ++b) pb.src[b] = pb.dst[b] = d + (size_t)(k0 + b) * per;
+    for (u32 r = 0; r <= level; ++r) pb.prime[r] = (uint8_t)r;
+    int rc = launch_ntt(c, pb, false);
+    if (!rc) rc = launch_to_mont(c, pb);
+    if (rc) return rc;
+  }
+  u64* db = nullptr;
+  if (bias) {
+    db = d + (size_t)m * per;
+    if (hipMemcpyAsync(db, bias, per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
+    PolyBatch pb = one_item(db, level + 1, level + 1, 0);
+    int rc = launch_ntt(c, pb, false);
+    if (rc) return rc;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
+  he_dense* h = new (std::nothrow) he_dense;
+  if (!h) return HE_ENOMEM;
+  *h = he_dense{c, level, m, n, n1, m / n1, pt_scale, bias_scale, d, db};
+  *out = h;
+  return HE_OK;
+}
+
+int he_dense_free(he_dense* d) {
+  if (!d) return HE_EINVAL;
+  delete d;
+  return HE_OK;
+}
+
+int he_ct_from_coeff_dev(he_ctx* c, const uint64_t* coeff, uint32_t level, double scale, he_ct* ct) {
+  if (!c || !coeff || !ct || !ct->dev) return HE_EINVAL;
+  if (level >= c->nq) return HE_ELEVEL;
+  PolyBatch pb = one_item(ct->dev, 2 * (level + 1), level + 1, 0);
+  pb.src[0] = (u64*)coeff;
+  int rc = launch_ntt(c, pb, false);
+  if (rc) return rc;
+  ct->level = level;
+  ct->scale = scale;
+  return HE_OK;
+}
+
+int he_ct_to_coeff_dev(he_ctx* c, const he_ct* ct, uint64_t* coeff) {
+  if (!c || !coeff || !ct || !ct->dev) return HE_EINVAL;
+  if (ct->level >= c->nq) return HE_ELEVEL;
+  PolyBatch pb = one_item(coeff, 2 * (ct->level + 1), ct->level + 1, 0);
+  pb.src[0] = ct->dev;
+  return launch_ntt(c, pb, true);
+}
+
+int he_ct_import(he_ctx* c, const uint64_t* host, uint32_t level, double scale, he_ct* ct) {
+  if (!c || !host || !ct || !ct->dev) return HE_EINVAL;
+  if (level >= c->nq) return HE_ELEVEL;
+  if (hipMemcpyAsync(ct->dev, host, he_ct_bytes(c, level), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return HE_EDEVICE;
+  int rc = he_ct_from_coeff_dev(c, ct->dev, level, scale, ct);
+  if (rc) return rc;
+  return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+int he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* host) {
+  if (!c || !host || !ct || !ct->dev) return HE_EINVAL;
+  if (!c->ws) return HE_ESTATE;
+  if (ct->level >= c->nq) return HE_ELEVEL;
+  u64* tmp = (u64*)c->ws;   // the first region of the workspace is at least one ciphertext
+  int rc = he_ct_to_coeff_dev(c, ct, tmp);
+  if (rc) return rc;
+  if (hipMemcpyAsync(host, tmp, he_ct_bytes(c, ct->level), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return HE_EDEVICE;
+  return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+int he_ntt(he_ctx* c, uint32_t n_items, uint64_t* const* items, uint32_t first_prime, uint32_t limbs, int inverse) {
+  if (!c || !items || n_items > HE_MAXB || limbs == 0 || limbs > HE_MAX_POLYS) return HE_EINVAL;
+  if (first_prime + limbs > nt_of(c)) return HE_EINVAL;
+  PolyBatch pb;
+  std::memset(&pb, 0, sizeof(pb));
+  pb.nitems = n_items;
+  pb.npoly = limbs;
+  for (u32 b = 0; b < n_items; ++b) {
+    if (!items[b]) return HE_EINVAL;
+    pb.src[b] = pb.dst[b] = items[b];
+  }
+  for (u32 r = 0; r < limbs; ++r) pb.prime[r] = (uint8_t)(first_prime + r);
+  return launch_ntt(c, pb, inverse != 0);
+}
+
+int he_sync(he_ctx* c) {
+  if (!c) return HE_EINVAL;
+  return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+}  // extern "C"

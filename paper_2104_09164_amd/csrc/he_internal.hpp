@@ -1,0 +1,100 @@
+// Internal structures of the HIP library behind include/he.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <map>
+#include <vector>
+#include "../../include/he.h"
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+#define HE_MAXB HE_MAX_BATCH
+#define HE_MAXP HE_MAX_PRIMES
+#define HE_MAX_POLYS 256      // limb-polys per item in one transform launch
+
+// Per-prime constants, device resident (one array indexed by prime number:
+// 0..L for q_i, L+1..L+K for p_k).
+struct PrimeConst {
+  u64 q;
+  u64 qneg;        // -q^{-1} mod 2^64 (Montgomery)
+  u64 mu;          // floor(2^64 / q) (Barrett-style reduce64)
+  u64 r2;          // 2^128 mod q: REDC(x * r2) = x 2^64 mod q
+  u64 ninv, ninv_sh;   // N^{-1} mod q and its Shoup companion
+  u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
+};
+
+// Twiddle tables of prime i at tw + i * 4N:
+//   [0,N)   psi^brev(k)        forward Cooley-Tukey twiddles (bit-reversed)
+//   [N,2N)  Shoup companions of the above
+//   [2N,3N) psi^-brev(k)       inverse Gentleman-Sande twiddles
+//   [3N,4N) Shoup companions
+// Forward output order: position k holds the evaluation at psi^(2 brev(k) + 1).
+
+// A batch of limb-poly transforms: item b, poly r (0 <= r < npoly) reads
+// src[b] + (src_off + r) * N and writes dst[b] + (dst_off + r) * N with prime
+// prime[r]; prime[r] == 0xFF skips the poly.
+struct PolyBatch {
+  u64* src[HE_MAXB];
+  u64* dst[HE_MAXB];
+  u32 src_off, dst_off, npoly, nitems;
+  uint8_t prime[HE_MAX_POLYS];
+};
+
+struct KeySlot {
+  int32_t step;
+  u32 galois;
+  u64* dev;         // [dnum][2][L+1+K][N], NTT form, Montgomery form
+};
+
+struct he_ctx {
+  u32 log_n, N;
+  u32 nq, np, alpha, dnum;   // L+1, K
+  std::vector<u64> primes;    // q_0..q_L, p_0..p_{K-1}
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // device tables (library-owned)
+  PrimeConst* d_pc = nullptr;
+  u64* d_tw = nullptr;
+  // ModUp conversion: for level l, digit j, source i (< alpha), target prime t:
+  //   hatinv[l][j][i] (+ shoup): (Q_D / q_i)^{-1} mod q_i
+  //   hatmod[l][j][i][t]: ((Q_D / q_i) mod t) * 2^64 mod t (Montgomery form)
+  u64* d_modup_hatinv = nullptr;   // [nq][dnum][alpha][2]
+  u64* d_modup_hatmod = nullptr;   // [nq][dnum][alpha][nt]
+  // ModDown: phatinv[k] (+shoup) = (P/p_k)^{-1} mod p_k; phatmod[k][i] = ((P/p_k) mod q_i) 2^64 mod q_i;
+  // pinv[i] (+shoup) = P^{-1} mod q_i
+  u64* d_moddown = nullptr;        // [np][2] | [np][nq] | [nq][2]
+  // Rescale: qlinv[l][i] (+shoup) = q_l^{-1} mod q_i, i < l
+  u64* d_rescale = nullptr;        // [nq][nq][2]
+  std::vector<PrimeConst> h_pc;
+
+  // workspace
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  u32 ws_batch = 0, ws_n1 = 0, ws_n2 = 0;
+
+  // keys
+  bool have_relin = false;
+  u64* relin_dev = nullptr;
+  std::vector<KeySlot> rot;
+};
+
+struct he_dense {
+  he_ctx* ctx;
+  u32 level, m, n, n1, n2;
+  double pt_scale, bias_scale;
+  u64* pts;    // [m][level+1][N], NTT + Montgomery form
+  u64* bias;   // [level+1][N], NTT form, or null
+};
+
+// ---------------------------------------------------------------- helpers
+static inline u32 nt_of(const he_ctx* c) { return c->nq + c->np; }
+static inline size_t limb_bytes(const he_ctx* c) { return (size_t)c->N * sizeof(u64); }
+// prime index of extended limb t in basis q_0..q_l, p_0..p_{K-1}
+static inline u32 ext_prime(const he_ctx* c, u32 l, u32 t) { return t <= l ? t : c->nq + (t - l - 1); }
+static inline u32 digits_at(const he_ctx* c, u32 l) { return (l + 1 + c->alpha - 1) / c->alpha; }
+
+// kernel launchers (ntt.hip)
+int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse);
+// kernel launchers (rns_kernels.hip) are declared in rns_kernels.hpp

@@ -1,0 +1,50 @@
+// Exact 64-bit modular arithmetic for CDNA4 (gfx950) device code.
+//
+// Residues are uint64 words for primes q < 2^61.  gfx950 has no 64x64-bit
+// multiply; the compiler builds 64-bit products from v_mad_u64_u32 /
+// v_mul_lo_u32 / v_mul_hi_u32, which run at or near full VALU rate there.
+//
+//  * Shoup multiplication by a constant w with companion w' = floor(w 2^64/q):
+//    x*w - mulhi(x, w')*q lies in [0, 2q) for any 64-bit x.  Used for NTT
+//    twiddles and every per-prime constant.
+//  * Montgomery reduction (R = 2^64) of 128-bit sums of products: keys,
+//    plaintexts and base-conversion constants are stored premultiplied by R,
+//    so a lazily accumulated sum of up to floor((2^64-1)/q) products needs one
+//    reduction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+struct u128v { u64 lo, hi; };
+
+__device__ __forceinline__ u128v mul_wide(u64 a, u64 b) {
+  u128v r; r.lo = a * b; r.hi = __umul64hi(a, b); return r;
+}
+__device__ __forceinline__ void acc_wide(u128v& s, u64 a, u64 b) {
+  u64 lo = a * b, hi = __umul64hi(a, b);
+  s.lo += lo; s.hi += hi + (s.lo < lo);
+}
+// x in [0, 2q) -> [0, q)
+__device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return csub(a + b, q); }          // a, b < q
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }  // a, b < q
+// Shoup: [0, 2q) for any x
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 wsh, u64 q) {
+  return x * w - __umul64hi(x, wsh) * q;
+}
+__device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 wsh, u64 q) { return csub(shoup_lazy(x, w, wsh, q), q); }
+// Montgomery REDC of s < q 2^64: s 2^-64 mod q in [0, q).  qneg = -q^{-1} mod 2^64.
+__device__ __forceinline__ u64 redc(u128v s, u64 q, u64 qneg) {
+  u64 m = s.lo * qneg;
+  u64 t = s.hi + __umul64hi(m, q) + (s.lo != 0);
+  return csub(t, q);
+}
+// x mod q for any 64-bit x, with mu = floor(2^64 / q) (q >= 2^20).
+__device__ __forceinline__ u64 reduce64(u64 x, u64 q, u64 mu) {
+  u64 r = x - __umul64hi(x, mu) * q;   // in [0, 3q) at most: floor error <= 2
+  r = csub(r, q);
+  return csub(r, q);
+}

@@ -1,0 +1,443 @@
+// Evaluation entry points of include/he.h: rotation (hybrid key switching,
+// hoisted), square with relinearisation, rescale, add and the dense layer in
+// baby-step/giant-step form.  Host code only: every step below is one or more
+// kernel launches on the context stream; nothing is computed on the CPU.
+#include <cmath>
+#include <cstring>
+#include "rns_kernels.hpp"
+
+namespace {
+
+// Workspace regions for a batch of up to B ciphertexts (sizes in limb-polys,
+// computed at the top level L so that the layout does not depend on the level).
+struct WS {
+  u64 *rtmp, *coef, *ext, *u, *conv, *d01, *d2, *red, *baby, *giant, *z0, *z1;
+};
+
+size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
+  const size_t N = c->N, L1 = c->nq, E = c->nq + c->np;
+  const size_t csz = 2 * L1 * N;
+  size_t off = 0;
+  auto take = [&](u64** p, size_t words) {
+    if (w) *p = (u64*)(c->ws) + off;
+    off += (words + 31) & ~(size_t)31;   // keep 256-byte alignment
+  };
+  WS dummy;
+  WS& x = w ? *w : dummy;
+  take(&x.rtmp, B * csz);
+  take(&x.coef, B * L1 * N);
+  take(&x.ext, B * c->dnum * E * N);
+  take(&x.u, B * 2 * E * N);
+  take(&x.conv, B * csz);
+  take(&x.d01, B * csz);
+  take(&x.d2, B * L1 * N);
+  take(&x.red, B * csz);
+  take(&x.baby, B * (n1 > 1 ? n1 - 1 : 0) * csz);
+  take(&x.giant, B * (n2 ? n2 : 1) * csz);
+  take(&x.z0, B * csz);
+  take(&x.z1, B * csz);
+  return off;
+}
+
+WS carve(he_ctx* c) {
+  WS w;
+  ws_words(c, c->ws_batch, c->ws_n1, c->ws_n2, &w);
+  return w;
+}
+
+bool same_scale(double a, double b) { return std::fabs(a - b) <= std::ldexp(std::fabs(a), -30); }
+
+const KeySlot* find_rot(const he_ctx* c, u32 galois) {
+  for (const KeySlot& k : c->rot)
+    if (k.galois == galois) return &k;
+  return nullptr;
+}
+
+u32 galois_of(const he_ctx* c, int64_t step) {
+  const int64_t half = c->N / 2;
+  u64 r = (u64)(((step % half) + half) % half);
+  u64 g = 1, b = 5, m = 2ull * c->N;
+  for (; r; r >>= 1, b = b * b % m)
+    if (r & 1) g = g * b % m;
+  return (u32)g;
+}
+
+PolyBatch batch_of(u32 nitems) {
+  PolyBatch pb;
+  std::memset(&pb, 0, sizeof(pb));
+  pb.nitems = nitems;
+  return pb;
+}
+
+// ModUp of the c1 polynomials (NTT form) of B items at level l into w.ext
+// (all digits, NTT form): INTT to coefficients, fast base conversion of each
+// digit, the digit's own limbs copied unchanged, NTT of the converted limbs.
+int modup(he_ctx* c, u32 l, u32 B, u64* const* c1, const WS& w) {
+  const size_t N = c->N;
+  const u32 ne = l + 1 + c->np, beta = digits_at(c, l);
+  PolyBatch pb = batch_of(B);
+  pb.npoly = l + 1;
+  for (u32 b = 0; b < B; ++b) {
+    pb.src[b] = c1[b];
+    pb.dst[b] = w.coef + (size_t)b * (l + 1) * N;
+  }
+  for (u32 r = 0; r <= l; ++r) pb.prime[r] = (uint8_t)r;
+  int rc = launch_ntt(c, pb, true);
+  if (!rc) rc = launch_modup_conv(c, l, B, w.coef, w.ext);
+  for (u32 j = 0; !rc && j < beta; ++j) {
+    const u32 lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
+    PolyBatch cp = batch_of(B);
+    cp.npoly = hi - lo;
+    cp.src_off = cp.dst_off = lo;
+    for (u32 b = 0; b < B; ++b) {
+      cp.src[b] = c1[b];
+      cp.dst[b] = w.ext + ((size_t)b * c->dnum + j) * ne * N;
+    }
+    for (u32 r = 0; r < cp.npoly; ++r) cp.prime[r] = (uint8_t)(lo + r);
+    rc = launch_copy_polys(c, cp);
+  }
+  if (rc) return rc;
+  PolyBatch nt = batch_of(B);
+  nt.npoly = beta * ne;
+  for (u32 b = 0; b < B; ++b) nt.src[b] = nt.dst[b] = w.ext + (size_t)b * c->dnum * ne * N;
+  for (u32 j = 0; j < beta; ++j) {
+    const u32 lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
+    for (u32 t = 0; t < ne; ++t)
+      nt.prime[j * ne + t] = (t >= lo && t < hi) ? 0xFF : (uint8_t)ext_prime(c, l, t);
+  }
+  return launch_ntt(c, nt, false);
+}
+
+// Key switch of the digits in w.ext with `key` (automorphism `galois` on the
+// digits), ModDown, combined into fa.out.
+int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, const u64* key, u32 galois, const FinalArgs& fa, const u64* bias) {
+  const size_t N = c->N;
+  const u32 ne = l + 1 + c->np;
+  int rc = launch_ks_inner(c, l, B, w.ext, key, galois, w.u);
+  if (rc) return rc;
+  PolyBatch pi = batch_of(B);
+  pi.npoly = 2 * ne;
+  for (u32 b = 0; b < B; ++b) pi.src[b] = pi.dst[b] = w.u + (size_t)b * 2 * ne * N;
+  for (u32 r = 0; r < 2 * ne; ++r) pi.prime[r] = (r % ne) > l ? (uint8_t)ext_prime(c, l, r % ne) : 0xFF;
+  if ((rc = launch_ntt(c, pi, true))) return rc;
+  if ((rc = launch_moddown_conv(c, l, B, w.u, w.conv))) return rc;
+  PolyBatch pf = batch_of(B);
+  pf.npoly = 2 * (l + 1);
+  for (u32 b = 0; b < B; ++b) pf.src[b] = pf.dst[b] = w.conv + (size_t)b * 2 * (l + 1) * N;
+  for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
+  if ((rc = launch_ntt(c, pf, false))) return rc;
+  return launch_ks_final(c, l, B, w.u, w.conv, galois, fa, bias);
+}
+
+FinalArgs no_final() {
+  FinalArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  return fa;
+}
+
+int check_batch(const he_ctx* c, u32 n, const he_ct* in, const he_ct* out, u32 n_out) {
+  if (!c || !in || !out || n == 0 || n > HE_MAXB) return HE_EINVAL;
+  if (!c->ws) return HE_ESTATE;
+  if (n > c->ws_batch) return HE_ENOMEM;
+  for (u32 b = 0; b < n; ++b) {
+    if (!in[b].dev) return HE_EINVAL;
+    if (in[b].level >= c->nq || in[b].level != in[0].level) return HE_ELEVEL;
+    if (!same_scale(in[b].scale, in[0].scale)) return HE_ESCALE;
+  }
+  for (u32 b = 0; b < n_out; ++b)
+    if (!out[b].dev) return HE_EINVAL;
+  return HE_OK;
+}
+
+int copy_ct(he_ctx* c, u32 l, const u64* src, u64* dst) {
+  if (src == dst) return HE_OK;
+  return hipMemcpyAsync(dst, src, (size_t)2 * (l + 1) * c->N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) ==
+                 hipSuccess
+             ? HE_OK
+             : HE_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t he_workspace_bytes(const he_ctx* c, uint32_t max_batch, uint32_t max_n1, uint32_t max_n2) {
+  if (!c) return 0;
+  return ws_words(c, max_batch ? max_batch : 1, max_n1, max_n2, nullptr) * sizeof(u64);
+}
+
+int he_ctx_bind(he_ctx* c, void* ws, size_t bytes, uint32_t max_batch, uint32_t max_n1, uint32_t max_n2) {
+  if (!c || !ws || max_batch == 0 || max_batch > HE_MAXB || ((uintptr_t)ws & 255)) return HE_EINVAL;
+  if (bytes < he_workspace_bytes(c, max_batch, max_n1, max_n2)) return HE_ENOMEM;
+  c->ws = (uint8_t*)ws;
+  c->ws_bytes = bytes;
+  c->ws_batch = max_batch;
+  c->ws_n1 = max_n1;
+  c->ws_n2 = max_n2;
+  return HE_OK;
+}
+
+int he_rotate_hoisted_batch(he_ctx* c, uint32_t n, const he_ct* in, uint32_t n_steps, const int32_t* steps,
+                            he_ct* out) {
+  int rc = check_batch(c, n, in, out, n * n_steps);
+  if (rc) return rc;
+  if (n_steps && !steps) return HE_EINVAL;
+  const u32 l = in[0].level;
+  std::vector<const KeySlot*> keys(n_steps);
+  for (u32 s = 0; s < n_steps; ++s) {
+    const u32 g = galois_of(c, steps[s]);
+    keys[s] = g == 1 ? nullptr : find_rot(c, g);
+    if (g != 1 && !keys[s]) return HE_ENOKEY;
+    for (u32 b = 0; b < n; ++b)
+      if (g != 1 && out[b * n_steps + s].dev == in[b].dev) return HE_EINVAL;
+  }
+  const WS w = carve(c);
+  const size_t N = c->N;
+  bool need_modup = false;
+  for (u32 s = 0; s < n_steps; ++s) need_modup |= keys[s] != nullptr;
+  if (need_modup) {
+    u64* c1[HE_MAXB];
+    for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
+    if ((rc = modup(c, l, n, c1, w))) return rc;
+  }
+  for (u32 s = 0; s < n_steps; ++s) {
+    for (u32 b = 0; b < n; ++b) {
+      out[b * n_steps + s].level = l;
+      out[b * n_steps + s].scale = in[b].scale;
+    }
+    if (!keys[s]) {
+      for (u32 b = 0; b < n; ++b)
+        if ((rc = copy_ct(c, l, in[b].dev, out[b * n_steps + s].dev))) return rc;
+      continue;
+    }
+    FinalArgs fa = no_final();
+    for (u32 b = 0; b < n; ++b) {
+      fa.out[b] = out[b * n_steps + s].dev;
+      fa.add0[b] = in[b].dev;
+    }
+    if ((rc = ks_core(c, l, n, w, keys[s]->dev, keys[s]->galois, fa, nullptr))) return rc;
+  }
+  return HE_OK;
+}
+
+int he_rotate_hoisted(he_ctx* c, const he_ct* in, uint32_t n_steps, const int32_t* steps, he_ct* out) {
+  return he_rotate_hoisted_batch(c, 1, in, n_steps, steps, out);
+}
+
+int he_rotate(he_ctx* c, const he_ct* in, int32_t step, he_ct* out) {
+  return he_rotate_hoisted_batch(c, 1, in, 1, &step, out);
+}
+
+int he_square_batch(he_ctx* c, uint32_t n, const he_ct* in, he_ct* out) {
+  int rc = check_batch(c, n, in, out, n);
+  if (rc) return rc;
+  if (!c->have_relin) return HE_ENOKEY;
+  const u32 l = in[0].level;
+  const size_t N = c->N;
+  const WS w = carve(c);
+  Items it;
+  it.n = n;
+  for (u32 b = 0; b < n; ++b) it.p[b] = in[b].dev;
+  if ((rc = launch_tensor(c, l, it, w.d01, w.d2))) return rc;
+  u64* c1[HE_MAXB];
+  for (u32 b = 0; b < n; ++b) c1[b] = w.d2 + (size_t)b * (l + 1) * N;
+  if ((rc = modup(c, l, n, c1, w))) return rc;
+  FinalArgs fa = no_final();
+  for (u32 b = 0; b < n; ++b) {
+    fa.out[b] = out[b].dev;
+    fa.add0[b] = w.d01 + (size_t)b * 2 * (l + 1) * N;
+    fa.add1[b] = w.d01 + (size_t)b * 2 * (l + 1) * N + (size_t)(l + 1) * N;
+  }
+  if ((rc = ks_core(c, l, n, w, c->relin_dev, 1, fa, nullptr))) return rc;
+  for (u32 b = 0; b < n; ++b) {
+    out[b].level = l;
+    out[b].scale = in[b].scale * in[b].scale;
+  }
+  return HE_OK;
+}
+
+int he_square(he_ctx* c, const he_ct* in, he_ct* out) { return he_square_batch(c, 1, in, out); }
+
+int he_rescale_batch(he_ctx* c, uint32_t n, const he_ct* in, he_ct* out) {
+  int rc = check_batch(c, n, in, out, n);
+  if (rc) return rc;
+  const u32 l = in[0].level;
+  if (l == 0) return HE_ELEVEL;
+  const size_t N = c->N;
+  const WS w = carve(c);
+  // INTT of the last limb of both polynomials into rtmp ([B][2][l+1][N] layout).
+  PolyBatch pb = batch_of(n);
+  pb.npoly = 2 * (l + 1);
+  for (u32 b = 0; b < n; ++b) {
+    pb.src[b] = in[b].dev;
+    pb.dst[b] = w.rtmp + (size_t)b * 2 * (l + 1) * N;
+  }
+  for (u32 r = 0; r < 2 * (l + 1); ++r) pb.prime[r] = (r % (l + 1)) == l ? (uint8_t)l : 0xFF;
+  if ((rc = launch_ntt(c, pb, true))) return rc;
+  if ((rc = launch_rescale_reduce(c, l, n, w.rtmp, w.red))) return rc;
+  PolyBatch pr = batch_of(n);
+  pr.npoly = 2 * l;
+  for (u32 b = 0; b < n; ++b) pr.src[b] = pr.dst[b] = w.red + (size_t)b * 2 * l * N;
+  for (u32 r = 0; r < 2 * l; ++r) pr.prime[r] = (uint8_t)(r % l);
+  if ((rc = launch_ntt(c, pr, false))) return rc;
+  Items ii, oo;
+  ii.n = oo.n = n;
+  bool alias = false;
+  for (u32 b = 0; b < n; ++b) {
+    ii.p[b] = in[b].dev;
+    alias |= out[b].dev == in[b].dev;
+  }
+  // An in-place rescale moves c1 down by one limb: stage through the workspace.
+  for (u32 b = 0; b < n; ++b) oo.p[b] = alias ? w.z0 + (size_t)b * 2 * l * N : out[b].dev;
+  if ((rc = launch_rescale_final(c, l, ii, w.red, oo))) return rc;
+  if (alias)
+    for (u32 b = 0; b < n; ++b)
+      if (hipMemcpyAsync(out[b].dev, oo.p[b], (size_t)2 * l * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
+          hipSuccess)
+        return HE_EDEVICE;
+  for (u32 b = 0; b < n; ++b) {
+    out[b].level = l - 1;
+    out[b].scale = in[b].scale / (double)c->primes[l];
+  }
+  return HE_OK;
+}
+
+int he_rescale(he_ctx* c, const he_ct* in, he_ct* out) { return he_rescale_batch(c, 1, in, out); }
+
+int he_add(he_ctx* c, const he_ct* a, const he_ct* b, he_ct* out) {
+  if (!c || !a || !b || !out || !a->dev || !b->dev || !out->dev) return HE_EINVAL;
+  if (a->level != b->level || a->level >= c->nq) return HE_ELEVEL;
+  if (!same_scale(a->scale, b->scale)) return HE_ESCALE;
+  Items x, y, o;
+  x.n = y.n = o.n = 1;
+  x.p[0] = a->dev;
+  y.p[0] = b->dev;
+  o.p[0] = out->dev;
+  int rc = launch_add(c, a->level, x, y, o);
+  if (rc) return rc;
+  out->level = a->level;
+  out->scale = a->scale;
+  return HE_OK;
+}
+
+int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* d, he_ct* out) {
+  int rc = check_batch(c, n, in, out, n);
+  if (rc) return rc;
+  if (!d || d->ctx != c) return HE_EINVAL;
+  const u32 l = d->level;
+  if (in[0].level != l) return HE_ELEVEL;
+  const u32 n1 = d->n1, n2 = d->n2;
+  if (n1 > std::max<u32>(c->ws_n1, 1) || n2 > std::max<u32>(c->ws_n2, 1)) return HE_ENOMEM;
+  const double out_scale = in[0].scale * d->pt_scale;
+  if (d->bias && !same_scale(d->bias_scale, out_scale)) return HE_ESCALE;
+  for (u32 b = 0; b < n; ++b)
+    if (out[b].dev == in[b].dev) return HE_EINVAL;
+  // Rotation keys for every step, looked up before anything is enqueued.
+  std::vector<u32> rs_steps;
+  for (u32 t = d->n / 2; t >= d->m && t > 0; t /= 2) rs_steps.push_back(t);
+  std::vector<const KeySlot*> baby(n1, nullptr), giant(n2, nullptr), rsk(rs_steps.size(), nullptr);
+  for (u32 i = 1; i < n1; ++i)
+    if (galois_of(c, i) != 1 && !(baby[i] = find_rot(c, galois_of(c, i)))) return HE_ENOKEY;
+  for (u32 j = 1; j < n2; ++j)
+    if (galois_of(c, (int64_t)n1 * j) != 1 && !(giant[j] = find_rot(c, galois_of(c, (int64_t)n1 * j)))) return HE_ENOKEY;
+  for (size_t u = 0; u < rs_steps.size(); ++u)
+    if (galois_of(c, rs_steps[u]) != 1 && !(rsk[u] = find_rot(c, galois_of(c, rs_steps[u])))) return HE_ENOKEY;
+
+  const size_t N = c->N, csz = (size_t)2 * (l + 1) * N;
+  const WS w = carve(c);
+  Items inI;
+  inI.n = n;
+  for (u32 b = 0; b < n; ++b) inI.p[b] = in[b].dev;
+
+  // Baby steps: one hoisted ModUp, n1 - 1 key switches.
+  if (n1 > 1) {
+    u64* c1[HE_MAXB];
+    for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
+    if ((rc = modup(c, l, n, c1, w))) return rc;
+    for (u32 i = 1; i < n1; ++i) {
+      FinalArgs fa = no_final();
+      for (u32 b = 0; b < n; ++b) {
+        fa.out[b] = w.baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
+        fa.add0[b] = in[b].dev;
+      }
+      if (!baby[i]) {
+        for (u32 b = 0; b < n; ++b)
+          if ((rc = copy_ct(c, l, in[b].dev, fa.out[b]))) return rc;
+        continue;
+      }
+      if ((rc = ks_core(c, l, n, w, baby[i]->dev, baby[i]->galois, fa, nullptr))) return rc;
+    }
+  }
+  // Inner sums s_j (giant region [B][n2][csz]).
+  if ((rc = launch_multplain_acc(c, l, n1, n2, inI, w.baby, d->pts, w.giant))) return rc;
+
+  // Giant steps then rotate-and-sum, each a full key switch; the last one
+  // writes the caller's output and adds the bias.
+  const u32 total = (n2 - 1) + (u32)rs_steps.size();
+  u64* cur[HE_MAXB];
+  for (u32 b = 0; b < n; ++b) cur[b] = w.giant + (size_t)b * n2 * csz;
+  u32 done = 0;
+  auto step = [&](const KeySlot* key, u64* const* src, bool accumulate_in_place) -> int {
+    ++done;
+    const bool last = done == total;
+    u64* dst[HE_MAXB];
+    for (u32 b = 0; b < n; ++b) {
+      if (last) dst[b] = out[b].dev;
+      else if (accumulate_in_place) dst[b] = cur[b];
+      else dst[b] = (cur[b] == w.z0 + (size_t)b * csz) ? w.z1 + (size_t)b * csz : w.z0 + (size_t)b * csz;
+    }
+    FinalArgs fa = no_final();
+    for (u32 b = 0; b < n; ++b) {
+      fa.out[b] = dst[b];
+      fa.add0[b] = src[b];
+      fa.acc[b] = cur[b];
+    }
+    const u64* bias = last ? d->bias : nullptr;
+    int r;
+    if (key) {
+      u64* c1[HE_MAXB];
+      for (u32 b = 0; b < n; ++b) c1[b] = src[b] + (size_t)(l + 1) * N;
+      if ((r = modup(c, l, n, c1, w))) return r;
+      if ((r = ks_core(c, l, n, w, key->dev, key->galois, fa, bias))) return r;
+    } else {
+      // rotation by a multiple of N/2 is the identity: dst = cur + src
+      Items a, s, o;
+      a.n = s.n = o.n = n;
+      for (u32 b = 0; b < n; ++b) { a.p[b] = cur[b]; s.p[b] = (u64*)src[b]; o.p[b] = dst[b]; }
+      if ((r = launch_add(c, l, a, s, o))) return r;
+      if (bias && (r = launch_add_plain(c, l, o, bias))) return r;
+    }
+    for (u32 b = 0; b < n; ++b) cur[b] = dst[b];
+    return HE_OK;
+  };
+  for (u32 j = 1; j < n2; ++j) {
+    u64* src[HE_MAXB];
+    for (u32 b = 0; b < n; ++b) src[b] = w.giant + ((size_t)b * n2 + j) * csz;
+    if ((rc = step(giant[j], src, true))) return rc;
+  }
+  for (size_t u = 0; u < rs_steps.size(); ++u) {
+    u64* src[HE_MAXB];
+    for (u32 b = 0; b < n; ++b) src[b] = cur[b];
+    if ((rc = step(rsk[u], src, false))) return rc;
+  }
+  if (total == 0) {
+    Items o;
+    o.n = n;
+    for (u32 b = 0; b < n; ++b) {
+      if ((rc = copy_ct(c, l, cur[b], out[b].dev))) return rc;
+      o.p[b] = out[b].dev;
+    }
+    if (d->bias && (rc = launch_add_plain(c, l, o, d->bias))) return rc;
+  }
+  for (u32 b = 0; b < n; ++b) {
+    out[b].level = l;
+    out[b].scale = out_scale;
+  }
+  return HE_OK;
+}
+
+int he_eval_dense(he_ctx* c, const he_ct* in, const he_dense* d, he_ct* out) {
+  return he_eval_dense_batch(c, 1, in, d, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,337 @@
+// RNS kernels of hybrid key switching, BSGS inner sums, squaring and rescale.
+//
+// Every kernel is HBM-streaming: one thread per coefficient index k, 256
+// threads per block, consecutive threads on consecutive words of a limb-poly
+// (limb-major [.][limb][N] layouts), so each wavefront reads and writes
+// contiguous 512-byte runs.  Per-prime constants come from small device tables
+// (broadcast loads).  Arithmetic: Shoup products by constants, lazy 128-bit
+// sums of products closed by one Montgomery reduction.
+#include "rns_kernels.hpp"
+#include "modarith.hpp"
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ u32 brev_n(u32 x, u32 logn) { return __builtin_bitreverse32(x) >> (32 - logn); }
+
+// NTT-domain automorphism X -> X^g: output position k reads input position perm(k).
+__device__ __forceinline__ u32 galois_perm(u32 k, u32 g, u32 logn) {
+  const u32 two_n_mask = (2u << logn) - 1;
+  const u32 e = 2 * brev_n(k, logn) + 1;
+  const u32 e2 = (e * g) & two_n_mask;
+  return brev_n((e2 - 1) >> 1, logn);
+}
+
+__global__ void __launch_bounds__(BS) k_copy_polys(PolyBatch pb, u32 N) {
+  const u32 r = blockIdx.y, b = blockIdx.z;
+  if (pb.prime[r] == 0xFF) return;
+  const u64* src = pb.src[b] + (size_t)(pb.src_off + r) * N;
+  u64* dst = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
+  for (u32 k = blockIdx.x * BS + threadIdx.x; k < N; k += gridDim.x * BS) dst[k] = src[k];
+}
+
+// grid: (N/BS, beta, B)
+__global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef, u64* __restrict__ ext,
+                                                   const PrimeConst* __restrict__ pc, const u64* __restrict__ hatinv,
+                                                   const u64* __restrict__ hatmod, u32 N, u32 l, u32 nq, u32 np,
+                                                   u32 alpha, u32 dnum) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 j = blockIdx.y, b = blockIdx.z;
+  const u32 ne = l + 1 + np, nt = nq + np;
+  const u32 lo = j * alpha, hi = min((j + 1) * alpha, l + 1), cnt = hi - lo;
+  const size_t tab = ((size_t)l * dnum + j) * alpha;
+  u64 v[8];
+  for (u32 i = 0; i < cnt; ++i) {
+    const u64 q = pc[lo + i].q;
+    const u64 x = coef[((size_t)b * (l + 1) + lo + i) * N + k];
+    v[i] = shoup(x, hatinv[(tab + i) * 2], hatinv[(tab + i) * 2 + 1], q);
+  }
+  u64* out = ext + ((size_t)b * dnum + j) * ne * N;
+  // dnum here is the allocation stride of digits per item (maximum digits)
+  for (u32 t = 0; t < ne; ++t) {
+    if (t >= lo && t < hi) continue;
+    const u32 pr = t <= l ? t : nq + (t - l - 1);
+    const u64 q = pc[pr].q, qneg = pc[pr].qneg;
+    u128v s = {0, 0};
+    for (u32 i = 0; i < cnt; ++i) acc_wide(s, v[i], hatmod[(tab + i) * nt + pr]);
+    out[(size_t)t * N + k] = redc(s, q, qneg);
+  }
+}
+
+// grid: (N/BS, ne, 1); loops over items so key words are loaded once per batch.
+template <bool PERM>
+__global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, const u64* __restrict__ key,
+                                                 u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
+                                                 u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
+                                                 u32 nitems, u32 galois) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 t = blockIdx.y;
+  const u32 ne = l + 1 + np, nt = nq + np;
+  const u32 pr = t <= l ? t : nq + (t - l - 1);
+  const u64 q = pc[pr].q, qneg = pc[pr].qneg;
+  const u32 ks = PERM ? galois_perm(k, galois, logn) : k;
+  u64 kb[8], ka[8];
+  for (u32 j = 0; j < beta; ++j) {
+    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + k];
+    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
+  }
+  for (u32 b = 0; b < nitems; ++b) {
+    u128v sb = {0, 0}, sa = {0, 0};
+    const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    for (u32 j = 0; j < beta; ++j) {
+      const u64 x = e[(size_t)j * ne * N];
+      acc_wide(sb, x, kb[j]);
+      acc_wide(sa, x, ka[j]);
+    }
+    u64* o = u + ((size_t)b * 2 * ne + t) * N + k;
+    o[0] = redc(sb, q, qneg);
+    o[(size_t)ne * N] = redc(sa, q, qneg);
+  }
+}
+
+// grid: (N/BS, 2, B)
+__global__ void __launch_bounds__(BS) k_moddown_conv(const u64* __restrict__ u, u64* __restrict__ conv,
+                                                     const PrimeConst* __restrict__ pc,
+                                                     const u64* __restrict__ md, u32 N, u32 l, u32 nq, u32 np) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 p = blockIdx.y, b = blockIdx.z;
+  const u32 ne = l + 1 + np;
+  const u64* phatinv = md;                     // [np][2]
+  const u64* phatmod = md + 2 * np;            // [np][nq]
+  const u64* src = u + ((size_t)b * 2 + p) * ne * N;
+  u64 v[8];
+  for (u32 kk = 0; kk < np; ++kk) {
+    const u64 q = pc[nq + kk].q;
+    v[kk] = shoup(src[(size_t)(l + 1 + kk) * N + k], phatinv[2 * kk], phatinv[2 * kk + 1], q);
+  }
+  u64* dst = conv + ((size_t)b * 2 + p) * (l + 1) * N;
+  for (u32 i = 0; i <= l; ++i) {
+    u128v s = {0, 0};
+    for (u32 kk = 0; kk < np; ++kk) acc_wide(s, v[kk], phatmod[(size_t)kk * nq + i]);
+    dst[(size_t)i * N + k] = redc(s, pc[i].q, pc[i].qneg);
+  }
+}
+
+// grid: (N/BS, l+1, B)
+__global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                 FinalArgs fa, const u64* __restrict__ bias,
+                                                 const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                 u32 N, u32 logn, u32 l, u32 nq, u32 np, u32 galois) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, b = blockIdx.z;
+  const u32 ne = l + 1 + np;
+  const u64 q = pc[i].q;
+  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
+  const size_t ui = ((size_t)b * 2 * ne + i) * N + k;
+  const size_t ci = ((size_t)b * 2 * (l + 1) + i) * N + k;
+  u64 r0 = shoup(u[ui] + q - conv[ci], w, wsh, q);
+  u64 r1 = shoup(u[ui + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q);
+  const size_t o0 = (size_t)i * N + k, o1 = (size_t)(l + 1 + i) * N + k;
+  if (fa.add0[b]) {
+    const u32 ks = galois != 1 ? galois_perm(k, galois, logn) : k;
+    r0 = add_mod(r0, fa.add0[b][(size_t)i * N + ks], q);
+  }
+  if (fa.add1[b]) r1 = add_mod(r1, fa.add1[b][o0], q);
+  if (fa.acc[b]) {
+    r0 = add_mod(r0, fa.acc[b][o0], q);
+    r1 = add_mod(r1, fa.acc[b][o1], q);
+  }
+  if (bias) r0 = add_mod(r0, bias[o0], q);
+  fa.out[b][o0] = r0;
+  fa.out[b][o1] = r1;
+}
+
+// grid: (N/BS, l+1, B * n2/JC)
+template <int JC>
+__global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __restrict__ baby,
+                                                      const u64* __restrict__ pts, u64* __restrict__ s,
+                                                      const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n1,
+                                                      u32 n2) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 li = blockIdx.y;
+  const u32 nch = n2 / JC;
+  const u32 b = blockIdx.z % in.n, jc = blockIdx.z / in.n;
+  const u64 q = pc[li].q, qneg = pc[li].qneg;
+  const size_t csz = (size_t)2 * (l + 1) * N;
+  u64 t0[JC], t1[JC];
+  u128v a0[JC], a1[JC];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) { t0[jj] = t1[jj] = 0; a0[jj] = a1[jj] = {0, 0}; }
+  for (u32 i = 0; i < n1; ++i) {
+    const u64* r = i == 0 ? in.p[b] : baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
+    const u64 r0 = r[(size_t)li * N + k], r1 = r[(size_t)(l + 1 + li) * N + k];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const u32 kk = n1 * (jc * JC + jj) + i;
+      const u64 pt = pts[((size_t)kk * (l + 1) + li) * N + k];
+      acc_wide(a0[jj], r0, pt);
+      acc_wide(a1[jj], r1, pt);
+    }
+    if ((i & 7) == 7 || i + 1 == n1) {
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj) {
+        t0[jj] = add_mod(t0[jj], redc(a0[jj], q, qneg), q);
+        t1[jj] = add_mod(t1[jj], redc(a1[jj], q, qneg), q);
+        a0[jj] = a1[jj] = {0, 0};
+      }
+    }
+  }
+  (void)nch;
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = s + ((size_t)b * n2 + jc * JC + jj) * csz;
+    o[(size_t)li * N + k] = t0[jj];
+    o[(size_t)(l + 1 + li) * N + k] = t1[jj];
+  }
+}
+
+// grid: (N/BS, l+1, B)
+__global__ void __launch_bounds__(BS) k_tensor(Items in, u64* __restrict__ d01, u64* __restrict__ d2,
+                                               const PrimeConst* __restrict__ pc, u32 N, u32 l) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, b = blockIdx.z;
+  const PrimeConst P = pc[i];
+  const u64 c0 = in.p[b][(size_t)i * N + k], c1 = in.p[b][(size_t)(l + 1 + i) * N + k];
+  const u64 c0m = shoup(c0, P.rmod, P.rmod_sh, P.q), c1m = shoup(c1, P.rmod, P.rmod_sh, P.q);
+  const u64 x00 = redc(mul_wide(c0m, c0), P.q, P.qneg);
+  const u64 x01 = redc(mul_wide(c0m, c1), P.q, P.qneg);
+  const u64 x11 = redc(mul_wide(c1m, c1), P.q, P.qneg);
+  u64* o = d01 + (size_t)b * 2 * (l + 1) * N;
+  o[(size_t)i * N + k] = x00;
+  o[(size_t)(l + 1 + i) * N + k] = add_mod(x01, x01, P.q);
+  d2[((size_t)b * (l + 1) + i) * N + k] = x11;
+}
+
+// grid: (N/BS, l, 2B)
+__global__ void __launch_bounds__(BS) k_rescale_reduce(const u64* __restrict__ last, u64* __restrict__ red,
+                                                       const PrimeConst* __restrict__ pc, u32 N, u32 l) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, bp = blockIdx.z;
+  red[((size_t)bp * l + i) * N + k] = reduce64(last[((size_t)bp * (l + 1) + l) * N + k], pc[i].q, pc[i].mu);
+}
+
+// grid: (N/BS, l, 2B)
+__global__ void __launch_bounds__(BS) k_rescale_final(Items in, const u64* __restrict__ red, Items out,
+                                                      const PrimeConst* __restrict__ pc,
+                                                      const u64* __restrict__ rs, u32 N, u32 l, u32 nq) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, b = blockIdx.z >> 1, p = blockIdx.z & 1;
+  const u64 q = pc[i].q;
+  const u64* w = rs + ((size_t)l * nq + i) * 2;
+  const u64 x = in.p[b][((size_t)p * (l + 1) + i) * N + k];
+  const u64 y = red[(((size_t)b * 2 + p) * l + i) * N + k];
+  out.p[b][((size_t)p * l + i) * N + k] = shoup(x + q - y, w[0], w[1], q);
+}
+
+// grid: (N/BS, 2(l+1), B)
+__global__ void __launch_bounds__(BS) k_add(Items a, Items b_, Items out, const PrimeConst* __restrict__ pc, u32 N,
+                                            u32 l) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 r = blockIdx.y, b = blockIdx.z;
+  const u64 q = pc[r % (l + 1)].q;
+  const size_t o = (size_t)r * N + k;
+  out.p[b][o] = add_mod(a.p[b][o], b_.p[b][o], q);
+}
+
+// grid: (N/BS, l+1, B)
+__global__ void __launch_bounds__(BS) k_add_plain(Items ct, const u64* __restrict__ poly,
+                                                  const PrimeConst* __restrict__ pc, u32 N) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, b = blockIdx.z;
+  const size_t o = (size_t)i * N + k;
+  ct.p[b][o] = add_mod(ct.p[b][o], poly[o], pc[i].q);
+}
+
+// grid: (N/BS, npoly, nitems)
+__global__ void __launch_bounds__(BS) k_to_mont(PolyBatch pb, const PrimeConst* __restrict__ pc, u32 N) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 r = blockIdx.y, b = blockIdx.z;
+  const u32 pr = pb.prime[r];
+  if (pr == 0xFF) return;
+  u64* x = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
+  x[k] = redc(mul_wide(x[k], pc[pr].r2), pc[pr].q, pc[pr].qneg);
+}
+
+inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
+
+}  // namespace
+
+int launch_copy_polys(he_ctx* c, const PolyBatch& pb) {
+  if (!pb.nitems || !pb.npoly) return HE_OK;
+  hipLaunchKernelGGL(k_copy_polys, dim3(c->N / BS / 4, pb.npoly, pb.nitems), dim3(BS), 0, c->stream, pb, c->N);
+  return ok();
+}
+
+int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
+  hipLaunchKernelGGL(k_modup_conv, dim3(c->N / BS, digits_at(c, l), nitems), dim3(BS), 0, c->stream, coef, ext, c->d_pc,
+                     c->d_modup_hatinv, c->d_modup_hatmod, c->N, l, c->nq, c->np, c->alpha, c->dnum);
+  return ok();
+}
+
+int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const u64* key, u32 galois, u64* u) {
+  dim3 grid(c->N / BS, l + 1 + c->np, 1);
+  if (galois != 1)
+    hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(BS), 0, c->stream, ext, key, u, c->d_pc, c->N, c->log_n, l, c->nq,
+                       c->np, digits_at(c, l), c->dnum, nitems, galois);
+  else
+    hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(BS), 0, c->stream, ext, key, u, c->d_pc, c->N, c->log_n, l, c->nq,
+                       c->np, digits_at(c, l), c->dnum, nitems, galois);
+  return ok();
+}
+
+int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv) {
+  hipLaunchKernelGGL(k_moddown_conv, dim3(c->N / BS, 2, nitems), dim3(BS), 0, c->stream, u, conv, c->d_pc, c->d_moddown,
+                     c->N, l, c->nq, c->np);
+  return ok();
+}
+
+int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv, u32 galois, const FinalArgs& fa,
+                    const u64* bias) {
+  hipLaunchKernelGGL(k_ks_final, dim3(c->N / BS, l + 1, nitems), dim3(BS), 0, c->stream, u, conv, fa, bias, c->d_pc,
+                     c->d_moddown, c->N, c->log_n, l, c->nq, c->np, galois);
+  return ok();
+}
+
+int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s) {
+  const u32 jc = n2 >= 4 ? 4 : n2;
+  dim3 grid(c->N / BS, l + 1, in.n * (n2 / jc));
+  switch (jc) {
+    case 4: hipLaunchKernelGGL(k_multplain_acc<4>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    case 2: hipLaunchKernelGGL(k_multplain_acc<2>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    default: hipLaunchKernelGGL(k_multplain_acc<1>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+  }
+  return ok();
+}
+
+int launch_tensor(he_ctx* c, u32 l, const Items& in, u64* d01, u64* d2) {
+  hipLaunchKernelGGL(k_tensor, dim3(c->N / BS, l + 1, in.n), dim3(BS), 0, c->stream, in, d01, d2, c->d_pc, c->N, l);
+  return ok();
+}
+
+int launch_rescale_reduce(he_ctx* c, u32 l, u32 nitems, const u64* last, u64* red) {
+  hipLaunchKernelGGL(k_rescale_reduce, dim3(c->N / BS, l, 2 * nitems), dim3(BS), 0, c->stream, last, red, c->d_pc, c->N, l);
+  return ok();
+}
+
+int launch_rescale_final(he_ctx* c, u32 l, const Items& in, const u64* red, const Items& out) {
+  hipLaunchKernelGGL(k_rescale_final, dim3(c->N / BS, l, 2 * in.n), dim3(BS), 0, c->stream, in, red, out, c->d_pc,
+                     c->d_rescale, c->N, l, c->nq);
+  return ok();
+}
+
+int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& out) {
+  hipLaunchKernelGGL(k_add, dim3(c->N / BS, 2 * (l + 1), a.n), dim3(BS), 0, c->stream, a, b, out, c->d_pc, c->N, l);
+  return ok();
+}
+
+int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
+  hipLaunchKernelGGL(k_add_plain, dim3(c->N / BS, l + 1, ct.n), dim3(BS), 0, c->stream, ct, poly, c->d_pc, c->N);
+  return ok();
+}
+
+int launch_to_mont(he_ctx* c, const PolyBatch& pb) {
+  hipLaunchKernelGGL(k_to_mont, dim3(c->N / BS, pb.npoly, pb.nitems), dim3(BS), 0, c->stream, pb, c->d_pc, c->N);
+  return ok();
+}

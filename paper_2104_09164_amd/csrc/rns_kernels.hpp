@@ -1,0 +1,64 @@
+// Launchers of the RNS kernels (rns_kernels.hip).  All run on c->stream.
+#pragma once
+#include "he_internal.hpp"
+
+// Per-item pointer list (one entry per ciphertext of a batch).
+struct Items {
+  u32 n = 0;
+  u64* p[HE_MAXB];
+};
+
+// Copies polys: item b, poly r: dst[b] + (dst_off + r) N <- src[b] + (src_off + r) N
+// for every r < npoly with prime[r] != 0xFF.
+int launch_copy_polys(he_ctx* c, const PolyBatch& pb);
+
+// ModUp conversion at level l: coef = [B][l+1][N] coefficient form (item
+// stride (l+1) N); ext = [B][beta][l+1+K][N]; writes every limb of every digit
+// except the digit's own limbs (coefficient form).
+int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext);
+
+// Key inner product at level l: for item b and key part p in {b, a}:
+//   u[b][p][t][k] = sum_j ext[b][j][t][perm_g(k)] * key[j][p][prime(t)][k]   (Montgomery)
+// galois == 1: no permutation.  ext = [B][beta][l+1+K][N], u = [B][2][l+1+K][N].
+int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const u64* key, u32 galois, u64* u);
+
+// ModDown conversion: u = [B][2][l+1+K][N] with the P-limbs already in
+// coefficient form; conv = [B][2][l+1][N] coefficient form.
+int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv);
+
+// Final combine of a key switch at level l (NTT domain), item b:
+//   out.c0[i] = acc.c0[i] + add0.c0[perm_g(.)][i] + (u_b[i] - conv_b[i]) P^{-1}
+//   out.c1[i] = acc.c1[i] + add1[i]                + (u_a[i] - conv_a[i]) P^{-1}
+// add0 (a ciphertext whose c0 is permuted by galois), add1 (a polynomial),
+// acc (a ciphertext): null entries are skipped.  bias (one polynomial, shared)
+// is added to c0 when non-null.
+struct FinalArgs {
+  u64* out[HE_MAXB];
+  const u64* add0[HE_MAXB];
+  const u64* add1[HE_MAXB];
+  const u64* acc[HE_MAXB];
+};
+int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv, u32 galois, const FinalArgs& fa,
+                    const u64* bias);
+
+// Inner sums of the baby-step/giant-step product, item b, j < n2:
+//   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
+// r_0(b) = in.p[b]; r_i(b) = baby + ((b (n1-1) + i - 1) * 2 (l+1)) N for i >= 1.
+// s = [B][n2][2][l+1][N].  pts in Montgomery form.
+int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s);
+
+// Tensor for squaring: d01 = [B][2][l+1] (c0^2, 2 c0 c1), d2 = [B][l+1] (c1^2).
+int launch_tensor(he_ctx* c, u32 l, const Items& in, u64* d01, u64* d2);
+
+// Rescale helpers.  last = [B][2][l+1][N] whose limb l holds c_l in coefficient form;
+// red = [B][2][l][N] receives c_l mod q_i (coefficient form).
+int launch_rescale_reduce(he_ctx* c, u32 l, u32 nitems, const u64* last, u64* red);
+// out(b) = (in(b) - red) * q_l^{-1} over limbs i < l (NTT domain).
+int launch_rescale_final(he_ctx* c, u32 l, const Items& in, const u64* red, const Items& out);
+
+// out = a + b (ciphertexts at level l).
+int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& out);
+// c0(b) += poly (a plaintext at level l, NTT form).
+int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly);
+// x <- x 2^64 mod q (Montgomery form) in place, poly r of pb.dst item b with prime pb.prime[r].
+int launch_to_mont(he_ctx* c, const PolyBatch& pb);
