@@ -101,10 +101,10 @@ int build_tables(he_ctx* c) {
     u64* t = tw.data() + (size_t)i * 4 * N;
     for (u32 k = 0; k < N; ++k) {
       const u32 e = bitrev(k, c->log_n);
-      t[k] = pw[e];
-      t[N + k] = shoup_of(pw[e], q);
-      t[2 * N + k] = ipw[e];
-      t[3 * N + k] = shoup_of(ipw[e], q);
+      t[2 * k] = pw[e];
+      t[2 * k + 1] = shoup_of(pw[e], q);
+      t[2 * N + 2 * k] = ipw[e];
+      t[2 * N + 2 * k + 1] = shoup_of(ipw[e], q);
     }
   }
   int rc;

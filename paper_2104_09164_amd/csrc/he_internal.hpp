@@ -24,11 +24,9 @@ struct PrimeConst {
   u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
 };
 
-// Twiddle tables of prime i at tw + i * 4N:
-//   [0,N)   psi^brev(k)        forward Cooley-Tukey twiddles (bit-reversed)
-//   [N,2N)  Shoup companions of the above
-//   [2N,3N) psi^-brev(k)       inverse Gentleman-Sande twiddles
-//   [3N,4N) Shoup companions
+// Twiddle tables of prime i at tw + i * 4N, as (w, Shoup companion) pairs:
+//   [0,2N)   (psi^brev(k), ...)   forward Cooley-Tukey twiddles (bit-reversed)
+//   [2N,4N)  (psi^-brev(k), ...)  inverse Gentleman-Sande twiddles
 // Forward output order: position k holds the evaluation at psi^(2 brev(k) + 1).
 
 // A batch of limb-poly transforms: item b, poly r (0 <= r < npoly) reads

@@ -36,6 +36,22 @@ __device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 wsh, u64 q) {
   return x * w - __umul64hi(x, wsh) * q;
 }
 __device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 wsh, u64 q) { return csub(shoup_lazy(x, w, wsh, q), q); }
+// Shoup product with a three-term quotient estimate: the low x 32-bit
+// partial product and the carries of the middle terms are dropped, so the
+// quotient is low by at most 2 and the result lies in [0, 4q) for any 64-bit
+// x (q < 2^61 keeps 8q below 2^64).  One v_mad_u64_u32 and two v_mul_hi_u32
+// instead of the four-product carry chain of the exact high half.
+__device__ __forceinline__ u64 shoup_lazy4(u64 x, u64 w, u64 wsh, u64 q) {
+  const u32 x0 = (u32)x, x1 = (u32)(x >> 32), s0 = (u32)wsh, s1 = (u32)(wsh >> 32);
+  const u64 mid = (u64)__umulhi(x1, s0) + (u64)__umulhi(x0, s1);
+  const u64 qh = (u64)x1 * s1 + mid;
+  return x * w - qh * q;
+}
+// x < 2m (m <= 2^62): x - m if x >= m, by the sign of the 64-bit difference.
+__device__ __forceinline__ u64 csub_signed(u64 x, u64 m) {
+  const u64 d = x - m;
+  return (int64_t)d < 0 ? x : d;
+}
 // Montgomery REDC of s < q 2^64: s 2^-64 mod q in [0, q).  qneg = -q^{-1} mod 2^64.
 __device__ __forceinline__ u64 redc(u128v s, u64 q, u64 qneg) {
   u64 m = s.lo * qneg;

@@ -4,8 +4,11 @@
 // (position k holds a(psi^(2 brev(k) + 1))); stage s = 0..logN-1 pairs
 // (j, j + N/2^(s+1)) with twiddle psi^brev(2^s + (j >> (logN - s))).
 // Inverse: the Gentleman-Sande mirror image with psi^-brev(.), then N^{-1}.
-// Harvey's lazy butterflies keep values below 4q (forward) / 2q (inverse)
-// between stages; outputs are fully reduced to [0, q).
+// Lazy butterflies in the style of Harvey: the twiddle product uses a
+// three-term Shoup quotient (result in [0, 4q)), values stay below 8q
+// (forward) / 4q (inverse) between stages, and outputs are fully reduced to
+// [0, q) on the way out.  Twiddles are stored as (w, w') pairs so one 16-byte
+// load fetches both.
 //
 // Decomposition.  logN stages split into phases of LP stages.  A phase
 // works on tiles of COLS independent sub-transforms of length 2^LP held in
@@ -51,13 +54,11 @@ struct Phase {
   }
 
   template <int U, int RB>
-  __device__ static __forceinline__ void pass(u64* lds, const u64* __restrict__ tw, const u64* __restrict__ twsh,
-                                              u64 q, u32 sub0) {
+  __device__ static __forceinline__ void pass(u64* lds, const ulonglong2* __restrict__ tw, u64 q, u32 sub0) {
     constexpr int R = 1 << RB;
     constexpr int KL = 1 << (LP - U - RB);
     constexpr int KT = 1 << U;
     constexpr int GROUPS = COLS * KL * KT;
-    const u64 q2 = 2 * q;
     for (int g = threadIdx.x; g < GROUPS; g += NT) {
       u32 kl, col, kt;
       if (!ROWS) { col = g % COLS; u32 t = g / COLS; kl = t % KL; kt = t / KL; }
@@ -66,6 +67,7 @@ struct Phase {
       u64 x[R];
 #pragma unroll
       for (int m = 0; m < R; ++m) x[m] = lds[pidx(local(col, kt * (R * KL) + m * KL + kl))];
+      const u64 q4 = 4 * q;
       if (!INV) {
 #pragma unroll
         for (int uu = 0; uu < RB; ++uu) {
@@ -74,15 +76,14 @@ struct Phase {
 #pragma unroll
           for (int blk = 0; blk < (1 << uu); ++blk) {
             const u32 ti = (1u << s) + (hi << (U + uu)) + (kt << uu) + blk;
-            const u64 w = tw[ti], wsh = twsh[ti];
+            const ulonglong2 wp = tw[ti];
 #pragma unroll
             for (int e = 0; e < half; ++e) {
               const int m0 = blk * 2 * half + e, m1 = m0 + half;
-              u64 X = x[m0];
-              X = X >= q2 ? X - q2 : X;
-              const u64 T = shoup_lazy(x[m1], w, wsh, q);
-              x[m0] = X + T;
-              x[m1] = X - T + q2;
+              const u64 X = csub_signed(x[m0], q4);                 // < 4q
+              const u64 T = shoup_lazy4(x[m1], wp.x, wp.y, q);      // < 4q
+              x[m0] = X + T;                                        // < 8q
+              x[m1] = X + q4 - T;                                   // (0, 8q)
             }
           }
         }
@@ -94,15 +95,13 @@ struct Phase {
 #pragma unroll
           for (int blk = 0; blk < (1 << uu); ++blk) {
             const u32 ti = (1u << s) + (hi << (U + uu)) + (kt << uu) + blk;
-            const u64 w = tw[ti], wsh = twsh[ti];
+            const ulonglong2 wp = tw[ti];
 #pragma unroll
             for (int e = 0; e < half; ++e) {
               const int m0 = blk * 2 * half + e, m1 = m0 + half;
-              const u64 A = x[m0], B = x[m1];
-              u64 S = A + B;
-              S = S >= q2 ? S - q2 : S;
-              x[m0] = S;
-              x[m1] = shoup_lazy(A - B + q2, w, wsh, q);
+              const u64 A = x[m0], B = x[m1];                       // < 4q
+              x[m0] = csub_signed(A + B, q4);                       // < 4q
+              x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);       // < 4q
             }
           }
         }
@@ -113,19 +112,19 @@ struct Phase {
   }
 
   template <int P>
-  __device__ static __forceinline__ void passes_fwd(u64* lds, const u64* tw, const u64* twsh, u64 q, u32 sub0) {
+  __device__ static __forceinline__ void passes_fwd(u64* lds, const ulonglong2* tw, u64 q, u32 sub0) {
     if constexpr (P < npasses(LP)) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, twsh, q, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, q, sub0);
       __syncthreads();
-      passes_fwd<P + 1>(lds, tw, twsh, q, sub0);
+      passes_fwd<P + 1>(lds, tw, q, sub0);
     }
   }
   template <int P>
-  __device__ static __forceinline__ void passes_inv(u64* lds, const u64* tw, const u64* twsh, u64 q, u32 sub0) {
+  __device__ static __forceinline__ void passes_inv(u64* lds, const ulonglong2* tw, u64 q, u32 sub0) {
     if constexpr (P >= 0) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, twsh, q, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, q, sub0);
       __syncthreads();
-      passes_inv<P - 1>(lds, tw, twsh, q, sub0);
+      passes_inv<P - 1>(lds, tw, q, sub0);
     }
   }
 };
@@ -144,29 +143,42 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   if (pr == 0xFF) return;
   const u32 N = 1u << LOGN;
   const u64 q = pc[pr].q;
-  const u64* tw = tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0);
-  const u64* twsh = tw + N;
+  const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
   const u64* src = read_src ? pb.src[b] + (size_t)(pb.src_off + r) * N : pb.dst[b] + (size_t)(pb.dst_off + r) * N;
   u64* dst = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
   const u32 sub0 = tile * COLS;
-  for (u32 i = threadIdx.x; i < (u32)TILE; i += NT) lds[pidx(i)] = src[Ph::gaddr(sub0, i)];
+  // Tile copy in 16-byte pairs (COLS and 2^LP are even, so pairs never straddle a row).
+  for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+    const ulonglong2 v = *(const ulonglong2*)(src + Ph::gaddr(sub0, i));
+    lds[pidx(i)] = v.x;
+    lds[pidx(i + 1)] = v.y;
+  }
   __syncthreads();
-  if (!INV) Ph::template passes_fwd<0>(lds, tw, twsh, q, sub0);
-  else Ph::template passes_inv<npasses(LP) - 1>(lds, tw, twsh, q, sub0);
+  if (!INV) Ph::template passes_fwd<0>(lds, tw, q, sub0);
+  else Ph::template passes_inv<npasses(LP) - 1>(lds, tw, q, sub0);
+  ulonglong2 v;
   if (final_) {
     if (!INV) {
-      const u64 q2 = 2 * q;
-      for (u32 i = threadIdx.x; i < (u32)TILE; i += NT) {
-        u64 x = lds[pidx(i)];
-        x = x >= q2 ? x - q2 : x;
-        dst[Ph::gaddr(sub0, i)] = csub(x, q);
+      const u64 q4 = 4 * q, q2 = 2 * q;
+      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+        v.x = csub_signed(csub_signed(csub_signed(lds[pidx(i)], q4), q2), q);
+        v.y = csub_signed(csub_signed(csub_signed(lds[pidx(i + 1)], q4), q2), q);
+        *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
       }
     } else {
-      const u64 ni = pc[pr].ninv, nish = pc[pr].ninv_sh;
-      for (u32 i = threadIdx.x; i < (u32)TILE; i += NT) dst[Ph::gaddr(sub0, i)] = shoup(lds[pidx(i)], ni, nish, q);
+      const u64 ni = pc[pr].ninv, nish = pc[pr].ninv_sh, q2 = 2 * q;
+      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+        v.x = csub_signed(csub_signed(shoup_lazy4(lds[pidx(i)], ni, nish, q), q2), q);
+        v.y = csub_signed(csub_signed(shoup_lazy4(lds[pidx(i + 1)], ni, nish, q), q2), q);
+        *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
+      }
     }
   } else {
-    for (u32 i = threadIdx.x; i < (u32)TILE; i += NT) dst[Ph::gaddr(sub0, i)] = lds[pidx(i)];
+    for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+      v.x = lds[pidx(i)];
+      v.y = lds[pidx(i + 1)];
+      *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
+    }
   }
 }
 

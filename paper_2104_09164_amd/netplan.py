@@ -1,0 +1,129 @@
+"""Host-side plan of an encrypted dense network (library side).
+
+A network is dense layers y = W x + b with the square activation between
+them (paper, Methods, "Non-convolutional layers": bias and polynomial
+activation collapsed per feature).  Evaluation order with lazy rescaling
+(Methods, "Algorithmic and cryptographic optimizations", lazy rescaling):
+dense -> rescale -> square -> rescale -> ... -> dense -> rescale.
+
+This module only does bookkeeping: levels, scales (IEEE doubles updated by
+*Delta_w, by squaring and by /q_l, in that order), the rotation steps each
+layer needs (baby steps 1..n1-1, giant steps n1*j, rotate-and-sum n/2..m),
+and the per-inference operation counts.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+
+@dataclass
+class LayerPlan:
+    m: int
+    n: int
+    n1: int
+    level: int            # level the layer is evaluated at
+    in_scale: float
+    pt_scale: float
+
+    @property
+    def n2(self) -> int:
+        return self.m // self.n1
+
+    @property
+    def bias_scale(self) -> float:
+        return self.in_scale * self.pt_scale
+
+    def steps(self) -> list[int]:
+        s = list(range(1, self.n1)) + [self.n1 * j for j in range(1, self.n2)]
+        t = self.n // 2
+        while t >= self.m:
+            s.append(t)
+            t //= 2
+        return s
+
+    def rs_count(self) -> int:
+        c, t = 0, self.n // 2
+        while t >= self.m:
+            c += 1
+            t //= 2
+        return c
+
+
+@dataclass
+class NetPlan:
+    log_n: int
+    q: list[int]
+    p: list[int]
+    alpha: int
+    scale: float
+    layers: list[LayerPlan] = field(default_factory=list)
+    out_level: int = 0
+    out_scale: float = 0.0
+
+    @property
+    def slots(self) -> int:
+        return 1 << (self.log_n - 1)
+
+    @property
+    def L(self) -> int:
+        return len(self.q) - 1
+
+    @property
+    def dnum(self) -> int:
+        return -(-len(self.q) // self.alpha)
+
+    def steps(self) -> list[int]:
+        s = set()
+        for lay in self.layers:
+            s.update(lay.steps())
+        return sorted(s)
+
+    def max_n1(self) -> int:
+        return max(l.n1 for l in self.layers)
+
+    def max_n2(self) -> int:
+        return max(l.n2 for l in self.layers)
+
+    def op_counts(self) -> dict:
+        ks = sum((l.n1 - 1) + (l.n2 - 1) + l.rs_count() for l in self.layers) + (len(self.layers) - 1)
+        return {"key_switches": ks, "multplain": sum(l.m for l in self.layers),
+                "rescales": 2 * len(self.layers) - 1, "squares": len(self.layers) - 1,
+                "hoisted_modups": sum(1 for l in self.layers if l.n1 > 1)}
+
+
+def plan_network(log_n: int, q, p, alpha: int, scale_bits: int, shapes) -> NetPlan:
+    """shapes: [(m, n, n1), ...] from the first layer to the last."""
+    pl = NetPlan(log_n, list(q), list(p), alpha, float(2 ** scale_bits))
+    level, s = pl.L, pl.scale
+    for li, (m, n, n1) in enumerate(shapes):
+        lay = LayerPlan(m, n, n1, level, s, pl.scale)
+        pl.layers.append(lay)
+        s = s * lay.pt_scale
+        s = s / pl.q[level]
+        level -= 1
+        if li + 1 < len(shapes):
+            s = s * s
+            s = s / pl.q[level]
+            level -= 1
+        if level < 0:
+            raise ValueError("modulus chain too short for this network")
+    pl.out_level, pl.out_scale = level, s
+    return pl
+
+
+# Workload presets (ring, primes by bit size, digit size, scale, layer shapes).
+PRESETS = {
+    "cfg1": dict(log_n=13, q_bits=[45] + [35] * 3, p_bits=[45], alpha=1, scale_bits=35,
+                 shapes=[(64, 256, 8), (2, 64, 2)], sigma=0.05),
+    "cfg3": dict(log_n=15, q_bits=[60] + [40] * 6, p_bits=[60] * 2, alpha=2, scale_bits=40,
+                 shapes=[(128, 1024, 32), (2, 128, 2)], sigma=0.03),
+    "cfg4": dict(log_n=16, q_bits=[60] + [45] * 10, p_bits=[60] * 3, alpha=3, scale_bits=45,
+                 shapes=[(256, 4096, 16), (64, 256, 8), (2, 64, 2)], sigma=0.02),
+}
+
+
+def preset_plan(name: str, shapes=None) -> NetPlan:
+    from . import he
+    c = PRESETS[name]
+    q, p = he.prime_chain(c["log_n"], c["q_bits"], c["p_bits"])
+    return plan_network(c["log_n"], q, p, c["alpha"], c["scale_bits"], shapes or c["shapes"])
