@@ -1,0 +1,58 @@
+"""Serving on the GPU: each result is the same alone and in the mix (bit for bit),
+and equals the oracle's evaluation of that request."""
+import numpy as np
+import pytest
+
+from oracle import ckks, params, plan
+from paper_2104_09164_amd import netplan, serve, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def build(pr, shapes, scale_bits, max_batch, slots):
+    from paper_2104_09164_amd import he
+    o = ckks.Oracle(pr)
+    keys = o.keygen(1, ckks.network_steps(shapes))
+    Ws, bs = synth.network_weights(shapes, 0.05)
+    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes])
+    npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, scale_bits, shapes)
+    for a, b in zip(lays, npl.layers):
+        assert (a.level, a.pt_scale, a.bias_scale) == (b.level, b.pt_scale, b.bias_scale)
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    ctx.bind(max_batch, npl.max_n1(), npl.max_n2())
+    ctx.load_keys(keys.rlk, keys.rot)
+    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale) for l in lays]
+    be = serve.NetBackend("small", ctx, npl, dls, max_batch=max_batch, slots=slots)
+    return o, keys, lays, be
+
+
+def test_serving_mix_equals_alone_and_oracle():
+    pr = params.make(12, [50, 40, 40, 40, 40], [50, 50], 2, 30)
+    shapes = [(8, 64, 4), (2, 8, 2)]
+    o, keys, lays, be = build(pr, shapes, 30, max_batch=4, slots=6)
+    count = 12
+    cts = []
+    for r in range(count):
+        x = synth.request_input(shapes[0][1], r)
+        cts.append(o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r)))
+    times = serve.poisson_arrivals(rate=3000.0, count=count, seed=3)
+    sched = serve.Scheduler({"small": be}, budget_bytes=4 * be.slot_bytes, window=3)
+    reqs = [serve.Request(r, "small", (cts[r].data, cts[r].level, cts[r].scale), float(times[r]))
+            for r in range(count)]
+    serve.run_arrivals(sched, reqs, timeout_s=120)
+    assert len(sched.done) == count and all(r.error is None for r in sched.done)
+    assert max(s for _, _, s in sched.batches) > 1          # requests shared launches
+    mixed = {r.rid: r.result for r in sched.done}
+    for r in range(count):
+        want = o.eval_network(cts[r], lays, keys)
+        data, level, scale = mixed[r]
+        assert level == want.level and scale == want.scale
+        assert np.array_equal(data, want.data), f"request {r} differs from the oracle"
+    # alone: one request at a time through a fresh scheduler on the same backend
+    for r in (0, 5, 11):
+        s1 = serve.Scheduler({"small": be}, budget_bytes=10 ** 12)
+        req = serve.Request(100 + r, "small", (cts[r].data, cts[r].level, cts[r].scale), 0.0)
+        serve.run_arrivals(s1, [req], timeout_s=60)
+        assert np.array_equal(s1.done[0].result[0], mixed[r][0])
+    m = sched.metrics()
+    assert m["completed"] == count and m["p99_ms"] >= m["p50_ms"] > 0
