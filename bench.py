@@ -1,13 +1,18 @@
 """Benchmark: encrypted inferences/s of the small dense net, batched vs plain.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg3|cfg4] [--batch B]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--large-batch B]
+                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-cpu]
 
 One step = one batched encrypted inference of B requests through the whole
-network (dense -> rescale -> square -> rescale -> dense -> rescale; every
-dense layer = hoisted baby-step rotations, MultPlain inner sums, giant-step
-and rotate-and-sum key switches, bias), replayed from a captured HIP graph,
-inputs resident in HBM.  Reported beside it, in the same JSON line:
+small network (N=2^15; dense 1024->128 -> rescale -> square -> rescale ->
+dense 128->2 -> rescale; every dense layer = hoisted baby-step rotations,
+MultPlain inner sums, giant-step and rotate-and-sum key switches, bias),
+replayed from a captured HIP graph, inputs resident in HBM.  `value` is that
+leg's inferences/s.  Reported beside it, in the same JSON line:
   * plain one-request-at-a-time inferences/s and p50/p99 latency;
+  * the same two legs for the large network (N=2^16, 4096->256->64->2);
+  * serving: Poisson arrivals at several rates, 70% small / 30% large
+    requests, continuous batching, p50/p99 from arrival to exported result;
   * the NTT micro-benchmark (64 ciphertexts x 2 x 24 limbs at N=2^16,
     forward + inverse) in algorithmic HBM GB/s;
   * the roofline of the dominant kernel (HIP events on the library stream);
@@ -161,74 +166,139 @@ def cpu_baseline(plan, budget_s=20.0):
                        f"per inference (est. {per_inf:.1f} s/inference)")}
 
 
+def network_legs(name, batch, steps, warmup, plain_n, graph=True):
+    """Batched (graph replay) and plain (one request at a time) legs of one preset."""
+    import torch
+    from paper_2104_09164_amd import netplan
+    plan = netplan.preset_plan(name)
+    log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}")
+    ctx, runner = setup(plan, batch)
+    torch.cuda.synchronize()
+    step = runner.capture(batch).replay if graph else (lambda: runner.run(batch))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"{name}: batched leg")
+    per_step = time_events(step, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"{name}: plain leg")
+    for _ in range(2):
+        runner.run(1)
+    torch.cuda.synchronize()
+    lat = time_events(lambda: runner.run(1), plain_n)
+    c = netplan.PRESETS[name]
+    res = {"batch": batch, "inferences_per_s": batch * steps / wall, "ms_per_step": wall * 1e3 / steps,
+           "batched_p50_ms": float(np.percentile(per_step, 50)), "batched_p99_ms": float(np.percentile(per_step, 99)),
+           "plain_inferences_per_s": 1000.0 / float(np.mean(lat)),
+           "plain_p50_ms": float(np.percentile(lat, 50)), "plain_p99_ms": float(np.percentile(lat, 99)),
+           "workload": (f"{name}: N=2^{plan.log_n}, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
+                        f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
+                        + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers) + ", x^2 between"),
+           "ops_per_inference": plan.op_counts()}
+    res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
+    return plan, ctx, runner, res
+
+
+def serving_leg(nets, rates, seconds, seed=21):
+    """Poisson arrivals (total rate lambda, the superposition of 256 camera
+    streams), 70% small-net / 30% large-net requests, keys and plaintexts
+    resident, admission by device-memory footprint, continuous batching."""
+    import torch
+    from paper_2104_09164_amd import serve
+    backends = {}
+    payloads = {}
+    for name, (plan, ctx, max_batch) in nets.items():
+        backends[name] = serve.NetBackend(name, ctx, plan, runner_layers[name], max_batch=max_batch,
+                                          slots=2 * max_batch + 8, own_stream=True)
+        N = 1 << plan.log_n
+        payloads[name] = [(residues(plan.q, N, (2,), seed + 50 + k), plan.L, plan.scale) for k in range(4)]
+    budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
+    out = {}
+    for rate in rates:
+        count = max(60, int(rate * seconds))
+        rng = np.random.default_rng(seed + int(rate))
+        times = serve.poisson_arrivals(rate, count, seed + int(rate))
+        kinds = np.where(rng.random(count) < 0.7, "small", "large")
+        reqs = [serve.Request(i, str(kinds[i]), payloads[str(kinds[i])][i % 4], float(times[i])) for i in range(count)]
+        sched = serve.Scheduler(backends, budget_bytes=budget, window=4)
+        log(f"serving: {count} requests at {rate} req/s")
+        serve.run_arrivals(sched, reqs, timeout_s=120)
+        torch.cuda.synchronize()
+        m = sched.metrics()
+        for name in nets:
+            lat = [1e3 * (r.finish - r.arrival) for r in sched.done if r.net == name and r.error is None]
+            if lat:
+                m[f"{name}_p50_ms"] = float(np.percentile(lat, 50))
+                m[f"{name}_p99_ms"] = float(np.percentile(lat, 99))
+        out[str(rate)] = m
+    return out
+
+
+runner_layers = {}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg3", choices=["cfg3", "cfg4"])
-    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=16, help="requests per launch, small net")
+    ap.add_argument("--large-batch", type=int, default=32, help="requests per launch, large net")
     ap.add_argument("--plain", type=int, default=8, help="one-request inferences timed for the plain leg")
+    ap.add_argument("--serve-rates", default="50,200,400")
+    ap.add_argument("--serve-seconds", type=float, default=2.5)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ntt", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--ntt-only", action="store_true",
+                    help="only the NTT leg (profiling runs), preceded by a 1 GiB device copy whose "
+                         "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (requests shard across GPUs "
               "with no exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
         return 2
     import torch
-    from paper_2104_09164_amd import netplan
-    batch = args.batch or (16 if args.config == "cfg3" else 32)
-    plan = netplan.preset_plan(args.config)
-    c = netplan.PRESETS[args.config]
-    log(f"config {args.config}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}")
-    ctx, runner = setup(plan, batch)
+    if args.ntt_only:
+        src = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)                                   # 1 GiB read + 1 GiB written: counter calibration
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps({"ntt": ntt_leg()}), flush=True)
+        return 0
+    plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
+                                            graph=not args.no_graph)
+    runner_layers["small"] = run3.layers
+    out = {"metric": METRIC, "value": small["inferences_per_s"], "unit": "inferences/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": small["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": ("small-net batched encrypted inference, " + small["workload"]
+                                   + f", {args.batch} requests per launch, HIP graph replay"),
+                      "batch": args.batch, "ops_per_inference": small["ops_per_inference"]},
+           "latency_ms": {"batched_p50": small["batched_p50_ms"], "batched_p99": small["batched_p99_ms"],
+                          "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
+           "plain_inferences_per_s": small["plain_inferences_per_s"],
+           "batched_over_plain": small["batched_over_plain"]}
+    nets = {"small": (plan3, ctx3, args.batch)}
+    if not args.no_large:
+        plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, max(3, args.steps // 2), 1,
+                                                max(3, args.plain // 2), graph=not args.no_graph)
+        runner_layers["large"] = run4.layers
+        out["large_net"] = large
+        nets["large"] = (plan4, ctx4, args.large_batch)
+    if not args.no_serve and not args.no_large:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        out["serving"] = serving_leg(nets, rates, args.serve_seconds)
+    del nets
     torch.cuda.synchronize()
-
-    # ---- batched leg (graph replay)
-    if args.no_graph:
-        step = lambda: runner.run(batch)
-    else:
-        g = runner.capture(batch)
-        step = g.replay
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("batched leg")
-    per_step = time_events(step, args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    value = batch * args.steps / wall
-
-    # ---- plain leg: one request at a time, eager launches
-    log("plain leg")
-    for _ in range(2):
-        runner.run(1)
-    torch.cuda.synchronize()
-    lat = time_events(lambda: runner.run(1), args.plain)
-    plain_rate = 1000.0 / float(np.mean(lat))
-
-    out = {"metric": METRIC, "value": value, "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-           "config": {"workload": (f"{args.config} batched encrypted inference: N=2^{plan.log_n}, "
-                                   f"q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
-                                   f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
-                                   + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers)
-                                   + f", x^2 between, {batch} requests per launch, HIP graph replay"),
-                      "batch": batch, "ops_per_inference": plan.op_counts()},
-           "latency_ms": {"batched_p50": float(np.percentile(per_step, 50)),
-                          "batched_p99": float(np.percentile(per_step, 99)),
-                          "plain_p50": float(np.percentile(lat, 50)), "plain_p99": float(np.percentile(lat, 99))},
-           "plain_inferences_per_s": plain_rate, "batched_over_plain": value / plain_rate}
-    del runner, ctx
-    torch.cuda.empty_cache()
     if not args.no_ntt:
         log("ntt leg")
         nt = ntt_leg()
@@ -238,7 +308,7 @@ def main():
                            "frac": nt["fwd_gbs"] / HBM_PEAK_GBS, "traffic": None}
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(plan)
+        out["cpu_baseline"] = cpu_baseline(plan3)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -200,6 +200,15 @@ int he_rotate_hoisted_batch(he_ctx* ctx, uint32_t n, const he_ct* in, uint32_t n
 int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first_prime, uint32_t limbs,
            int inverse);
 
+/* Execution knobs: launch shapes and scheduling choices that never change a
+ * result bit (the arithmetic and its reduction points are fixed).  Set by the
+ * autotuner.  Keys:
+ *   "ntt_chunk_mb"  two-phase NTT: run both phases per chunk of this many MiB
+ *                   of polynomials (0 = each phase over the whole batch)
+ * Returns HE_EINVAL for an unknown key or a negative value. */
+int he_ctx_set_knob(he_ctx* ctx, const char* key, int64_t value);
+int he_ctx_get_knob(const he_ctx* ctx, const char* key, int64_t* value);
+
 /* Waits for all work enqueued on the context's stream. */
 int he_sync(he_ctx* ctx);
 

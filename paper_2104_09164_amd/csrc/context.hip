@@ -75,6 +75,9 @@ PrimeConst make_pc(u64 q, u32 N) {
   p.r2 = mul_mod(p.rmod, p.rmod, q);
   p.ninv = inv_mod(N, q);
   p.ninv_sh = shoup_of(p.ninv, q);
+  p.nq = (u64)0 - q;
+  p.nq2 = (u64)0 - 2 * q;
+  p.nq4 = (u64)0 - 4 * q;
   return p;
 }
 // x 2^64 mod m (Montgomery form of a host constant)
@@ -428,6 +431,18 @@ int he_ntt(he_ctx* c, uint32_t n_items, uint64_t* const* items, uint32_t first_p
   }
   for (u32 r = 0; r < limbs; ++r) pb.prime[r] = (uint8_t)(first_prime + r);
   return launch_ntt(c, pb, inverse != 0);
+}
+
+int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
+  if (!c || !key || value < 0) return HE_EINVAL;
+  if (!std::strcmp(key, "ntt_chunk_mb")) { c->ntt_chunk_mb = value; return HE_OK; }
+  return HE_EINVAL;
+}
+
+int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
+  if (!c || !key || !value) return HE_EINVAL;
+  if (!std::strcmp(key, "ntt_chunk_mb")) { *value = c->ntt_chunk_mb; return HE_OK; }
+  return HE_EINVAL;
 }
 
 int he_sync(he_ctx* c) {

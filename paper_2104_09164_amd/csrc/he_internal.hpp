@@ -22,6 +22,7 @@ struct PrimeConst {
   u64 r2;          // 2^128 mod q: REDC(x * r2) = x 2^64 mod q
   u64 ninv, ninv_sh;   // N^{-1} mod q and its Shoup companion
   u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
+  u64 nq, nq2, nq4;    // 2^64 - q, 2^64 - 2q, 2^64 - 4q
 };
 
 // Twiddle tables of prime i at tw + i * 4N, as (w, Shoup companion) pairs:
@@ -66,6 +67,9 @@ struct he_ctx {
   // Rescale: qlinv[l][i] (+shoup) = q_l^{-1} mod q_i, i < l
   u64* d_rescale = nullptr;        // [nq][nq][2]
   std::vector<PrimeConst> h_pc;
+
+  // execution knobs (bit-preserving)
+  int64_t ntt_chunk_mb = 0;
 
   // workspace
   uint8_t* ws = nullptr;

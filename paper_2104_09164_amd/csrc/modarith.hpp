@@ -47,6 +47,28 @@ __device__ __forceinline__ u64 shoup_lazy4(u64 x, u64 w, u64 wsh, u64 q) {
   const u64 qh = (u64)x1 * s1 + mid;
   return x * w - qh * q;
 }
+// X + (x w mod q) for X < 2^64 - 4q: the Shoup product of shoup_lazy4 with
+// the subtraction of qh q folded into the low-64-bit accumulation chain as
+// + qh (2^64 - q):  t = x0 w0 + X + qh0 nq0 (two v_mad_u64_u32), high word
+// + lo32 of the four cross products.  nq = 2^64 - q.  Result X + T with T in
+// [0, 4q) (exact as an integer while X + 4q < 2^64).
+__device__ __forceinline__ u64 add_shoup4(u64 X, u64 x, u64 w, u64 wsh, u64 nq) {
+  const u32 x0 = (u32)x, x1 = (u32)(x >> 32), s0 = (u32)wsh, s1 = (u32)(wsh >> 32);
+  const u32 w0 = (u32)w, w1 = (u32)(w >> 32), n0 = (u32)nq, n1 = (u32)(nq >> 32);
+  const u64 qh = (u64)x1 * s1 + ((u64)__umulhi(x1, s0) + (u64)__umulhi(x0, s1));
+  const u32 h0 = (u32)qh, h1 = (u32)(qh >> 32);
+  u64 t = (u64)x0 * w0 + X;
+  t = (u64)h0 * n0 + t;
+  const u32 hi = (u32)(t >> 32) + x1 * w0 + x0 * w1 + h1 * n0 + h0 * n1;
+  return ((u64)hi << 32) | (u32)t;
+}
+// x < 2m (m <= 2^63): x - m if x >= m; negm = 2^64 - m supplied from memory so
+// that the difference is one 64-bit add (v_lshl_add_u64) instead of a
+// subtract-with-borrow pair.
+__device__ __forceinline__ u64 csub_neg(u64 x, u64 negm) {
+  const u64 d = x + negm;
+  return (int64_t)d < 0 ? x : d;
+}
 // x < 2m (m <= 2^62): x - m if x >= m, by the sign of the 64-bit difference.
 __device__ __forceinline__ u64 csub_signed(u64 x, u64 m) {
   const u64 d = x - m;

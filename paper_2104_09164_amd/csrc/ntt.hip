@@ -20,6 +20,7 @@
 // cover the phase.  HBM is touched once per phase (coalesced tile copies).
 // The hot path is HBM/VALU balanced on MI355X: a 64x64-bit modular multiply
 // is ~9 VALU ops (v_mad_u64_u32 is full rate on gfx950).
+#include <algorithm>
 #include "he_internal.hpp"
 #include "modarith.hpp"
 
@@ -54,15 +55,21 @@ struct Phase {
   }
 
   template <int U, int RB>
-  __device__ static __forceinline__ void pass(u64* lds, const ulonglong2* __restrict__ tw, u64 q, u32 sub0) {
+  __device__ static __forceinline__ void pass(u64* lds, const ulonglong2* __restrict__ tw, const PrimeConst& k,
+                                              u32 sub0) {
+    const u64 q = k.q;
     constexpr int R = 1 << RB;
     constexpr int KL = 1 << (LP - U - RB);
     constexpr int KT = 1 << U;
     constexpr int GROUPS = COLS * KL * KT;
     for (int g = threadIdx.x; g < GROUPS; g += NT) {
       u32 kl, col, kt;
+      // Lane order.  Columns layout: column fastest (stride 1 word).  Rows
+      // layout: k bits fastest (kl, then kt: stride 1 or 2^r words, 17 after
+      // padding), rows last; a row-fastest order would put 256-word strides
+      // between lanes and serialise on two bank groups.
       if (!ROWS) { col = g % COLS; u32 t = g / COLS; kl = t % KL; kt = t / KL; }
-      else { kl = g % KL; u32 t = g / KL; col = t % COLS; kt = t / COLS; }
+      else { kl = g % KL; u32 t = g / KL; kt = t % KT; col = t / KT; }
       const u32 hi = ROWS ? sub0 + col : 0;
       u64 x[R];
 #pragma unroll
@@ -80,10 +87,10 @@ struct Phase {
 #pragma unroll
             for (int e = 0; e < half; ++e) {
               const int m0 = blk * 2 * half + e, m1 = m0 + half;
-              const u64 X = csub_signed(x[m0], q4);                 // < 4q
-              const u64 T = shoup_lazy4(x[m1], wp.x, wp.y, q);      // < 4q
-              x[m0] = X + T;                                        // < 8q
-              x[m1] = X + q4 - T;                                   // (0, 8q)
+              const u64 X = csub_neg(x[m0], k.nq4);                      // < 4q
+              const u64 S = add_shoup4(X, x[m1], wp.x, wp.y, k.nq);      // X + T < 8q
+              x[m0] = S;
+              x[m1] = 2 * X + q4 - S;                                   // X + 4q - T in (0, 8q)
             }
           }
         }
@@ -99,9 +106,9 @@ struct Phase {
 #pragma unroll
             for (int e = 0; e < half; ++e) {
               const int m0 = blk * 2 * half + e, m1 = m0 + half;
-              const u64 A = x[m0], B = x[m1];                       // < 4q
-              x[m0] = csub_signed(A + B, q4);                       // < 4q
-              x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);       // < 4q
+              const u64 A = x[m0], B = x[m1];                            // < 4q
+              x[m0] = csub_neg(A + B, k.nq4);                            // < 4q
+              x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);            // < 4q
             }
           }
         }
@@ -112,19 +119,19 @@ struct Phase {
   }
 
   template <int P>
-  __device__ static __forceinline__ void passes_fwd(u64* lds, const ulonglong2* tw, u64 q, u32 sub0) {
+  __device__ static __forceinline__ void passes_fwd(u64* lds, const ulonglong2* tw, const PrimeConst& k, u32 sub0) {
     if constexpr (P < npasses(LP)) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, q, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, k, sub0);
       __syncthreads();
-      passes_fwd<P + 1>(lds, tw, q, sub0);
+      passes_fwd<P + 1>(lds, tw, k, sub0);
     }
   }
   template <int P>
-  __device__ static __forceinline__ void passes_inv(u64* lds, const ulonglong2* tw, u64 q, u32 sub0) {
+  __device__ static __forceinline__ void passes_inv(u64* lds, const ulonglong2* tw, const PrimeConst& k, u32 sub0) {
     if constexpr (P >= 0) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, q, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, k, sub0);
       __syncthreads();
-      passes_inv<P - 1>(lds, tw, q, sub0);
+      passes_inv<P - 1>(lds, tw, k, sub0);
     }
   }
 };
@@ -138,11 +145,15 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   using Ph = Phase<LOGN, S0, LP, COLS, NT, INV>;
   constexpr int TILE = Ph::TILE;
   __shared__ u64 lds[TILE + TILE / 16];
-  const u32 tile = blockIdx.x, r = blockIdx.y, b = blockIdx.z;
+  // grid (tile, item, poly): all items of one limb are adjacent, so the twiddle
+  // table of that prime is reused from L2 across the batch; 2^k tiles per
+  // polynomial keep tile t on XCD t mod 8, which then needs 1/8 of the table.
+  const u32 tile = blockIdx.x, b = blockIdx.y, r = blockIdx.z;
   const u32 pr = pb.prime[r];
   if (pr == 0xFF) return;
   const u32 N = 1u << LOGN;
-  const u64 q = pc[pr].q;
+  const PrimeConst k = pc[pr];
+  const u64 q = k.q;
   const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
   const u64* src = read_src ? pb.src[b] + (size_t)(pb.src_off + r) * N : pb.dst[b] + (size_t)(pb.dst_off + r) * N;
   u64* dst = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
@@ -154,22 +165,20 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
     lds[pidx(i + 1)] = v.y;
   }
   __syncthreads();
-  if (!INV) Ph::template passes_fwd<0>(lds, tw, q, sub0);
-  else Ph::template passes_inv<npasses(LP) - 1>(lds, tw, q, sub0);
+  if (!INV) Ph::template passes_fwd<0>(lds, tw, k, sub0);
+  else Ph::template passes_inv<npasses(LP) - 1>(lds, tw, k, sub0);
   ulonglong2 v;
   if (final_) {
     if (!INV) {
-      const u64 q4 = 4 * q, q2 = 2 * q;
       for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-        v.x = csub_signed(csub_signed(csub_signed(lds[pidx(i)], q4), q2), q);
-        v.y = csub_signed(csub_signed(csub_signed(lds[pidx(i + 1)], q4), q2), q);
+        v.x = csub_neg(csub_neg(csub_neg(lds[pidx(i)], k.nq4), k.nq2), k.nq);
+        v.y = csub_neg(csub_neg(csub_neg(lds[pidx(i + 1)], k.nq4), k.nq2), k.nq);
         *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
       }
     } else {
-      const u64 ni = pc[pr].ninv, nish = pc[pr].ninv_sh, q2 = 2 * q;
       for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-        v.x = csub_signed(csub_signed(shoup_lazy4(lds[pidx(i)], ni, nish, q), q2), q);
-        v.y = csub_signed(csub_signed(shoup_lazy4(lds[pidx(i + 1)], ni, nish, q), q2), q);
+        v.x = csub_neg(csub_neg(shoup_lazy4(lds[pidx(i)], k.ninv, k.ninv_sh, q), k.nq2), k.nq);
+        v.y = csub_neg(csub_neg(shoup_lazy4(lds[pidx(i + 1)], k.ninv, k.ninv_sh, q), k.nq2), k.nq);
         *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
       }
     }
@@ -184,12 +193,16 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
 
 template <int LOGN, int S0, int LP, int COLS, int NT, bool INV>
 void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
-  dim3 grid((1u << (LOGN - LP)) / COLS, pb.npoly, pb.nitems);
+  dim3 grid((1u << (LOGN - LP)) / COLS, pb.nitems, pb.npoly);
   hipLaunchKernelGGL((k_ntt_phase<LOGN, S0, LP, COLS, NT, INV>), grid, dim3(NT), 0, c->stream, pb, c->d_tw, c->d_pc,
                      read_src, final_);
 }
 
-// Single phase for logN <= 13, two phases (LA = ceil(logN/2)) above.
+// Single phase for logN <= 13, two phases (LA = ceil(logN/2)) above.  With
+// the knob ntt_chunk_mb > 0 the two-phase transform runs phase A then phase B
+// on chunks of that many MiB of polynomials, so that the intermediate written
+// by phase A can still be in the Infinity Cache when phase B reads it back.
+
 template <int LOGN>
 void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
   if constexpr (LOGN <= 13) {
@@ -201,12 +214,25 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
     constexpr int COLS = 16;
     constexpr int NTA = ((COLS << LA) / 16) > 512 ? 512 : ((COLS << LA) / 16);
     constexpr int NTB = ((COLS << LB) / 16) > 512 ? 512 : ((COLS << LB) / 16);
-    if (!inv) {
-      launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, pb, 1, 0);
-      launch_phase<LOGN, LA, LB, COLS, NTB, false>(c, pb, 0, 1);
-    } else {
-      launch_phase<LOGN, LA, LB, COLS, NTB, true>(c, pb, 1, 0);
-      launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, pb, 0, 1);
+    const size_t poly_bytes = (size_t)8 << LOGN;
+    u32 per = pb.npoly;
+    if (c->ntt_chunk_mb > 0) {
+      per = (u32)(((size_t)c->ntt_chunk_mb << 20) / (poly_bytes * pb.nitems));
+      if (per < 1) per = 1;
+    }
+    for (u32 r0 = 0; r0 < pb.npoly; r0 += per) {
+      PolyBatch ch = pb;
+      ch.npoly = std::min(per, pb.npoly - r0);
+      ch.src_off = pb.src_off + r0;
+      ch.dst_off = pb.dst_off + r0;
+      for (u32 r = 0; r < ch.npoly; ++r) ch.prime[r] = pb.prime[r0 + r];
+      if (!inv) {
+        launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, ch, 1, 0);
+        launch_phase<LOGN, LA, LB, COLS, NTB, false>(c, ch, 0, 1);
+      } else {
+        launch_phase<LOGN, LA, LB, COLS, NTB, true>(c, ch, 1, 0);
+        launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, ch, 0, 1);
+      }
     }
   }
 }

@@ -24,7 +24,7 @@ __device__ __forceinline__ u32 galois_perm(u32 k, u32 g, u32 logn) {
 }
 
 __global__ void __launch_bounds__(BS) k_copy_polys(PolyBatch pb, u32 N) {
-  const u32 r = blockIdx.y, b = blockIdx.z;
+  const u32 b = blockIdx.y, r = blockIdx.z;
   if (pb.prime[r] == 0xFF) return;
   const u64* src = pb.src[b] + (size_t)(pb.src_off + r) * N;
   u64* dst = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
@@ -244,10 +244,10 @@ __global__ void __launch_bounds__(BS) k_add_plain(Items ct, const u64* __restric
   ct.p[b][o] = add_mod(ct.p[b][o], poly[o], pc[i].q);
 }
 
-// grid: (N/BS, npoly, nitems)
+// grid: (N/BS, nitems, npoly)
 __global__ void __launch_bounds__(BS) k_to_mont(PolyBatch pb, const PrimeConst* __restrict__ pc, u32 N) {
   const u32 k = blockIdx.x * BS + threadIdx.x;
-  const u32 r = blockIdx.y, b = blockIdx.z;
+  const u32 b = blockIdx.y, r = blockIdx.z;
   const u32 pr = pb.prime[r];
   if (pr == 0xFF) return;
   u64* x = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
@@ -260,7 +260,7 @@ inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
 
 int launch_copy_polys(he_ctx* c, const PolyBatch& pb) {
   if (!pb.nitems || !pb.npoly) return HE_OK;
-  hipLaunchKernelGGL(k_copy_polys, dim3(c->N / BS / 4, pb.npoly, pb.nitems), dim3(BS), 0, c->stream, pb, c->N);
+  hipLaunchKernelGGL(k_copy_polys, dim3(c->N / BS / 4, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->N);
   return ok();
 }
 
@@ -332,6 +332,6 @@ int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
 }
 
 int launch_to_mont(he_ctx* c, const PolyBatch& pb) {
-  hipLaunchKernelGGL(k_to_mont, dim3(c->N / BS, pb.npoly, pb.nitems), dim3(BS), 0, c->stream, pb, c->d_pc, c->N);
+  hipLaunchKernelGGL(k_to_mont, dim3(c->N / BS, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->d_pc, c->N);
   return ok();
 }

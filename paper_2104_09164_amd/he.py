@@ -77,6 +77,8 @@ def lib() -> C.CDLL:
             "he_rotate_hoisted_batch": (C.c_int, [vp, u32, ctp, u32, C.POINTER(i32), ctp]),
             "he_ntt": (C.c_int, [vp, u32, C.POINTER(vp), u32, u32, C.c_int]),
             "he_sync": (C.c_int, [vp]),
+            "he_ctx_set_knob": (C.c_int, [vp, C.c_char_p, C.c_int64]),
+            "he_ctx_get_knob": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -91,7 +93,7 @@ EXPORTED = ("he_strerror", "he_gen_primes", "he_ctx_create", "he_ctx_destroy", "
             "he_dense_free", "he_ct_import", "he_ct_export", "he_ct_from_coeff_dev", "he_ct_to_coeff_dev",
             "he_eval_dense", "he_square", "he_rotate", "he_rotate_hoisted", "he_rescale", "he_add",
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
-            "he_sync")
+            "he_sync", "he_ctx_set_knob", "he_ctx_get_knob")
 
 
 def _check(rc: int, where: str) -> None:
@@ -304,6 +306,14 @@ class Context:
     def ntt(self, bufs, first_prime: int, limbs: int, inverse: bool) -> None:
         ptrs = (C.c_void_p * len(bufs))(*[b.data_ptr() for b in bufs])
         _check(lib().he_ntt(self.h, len(bufs), ptrs, first_prime, limbs, int(inverse)), "he_ntt")
+
+    def set_knob(self, key: str, value: int) -> None:
+        _check(lib().he_ctx_set_knob(self.h, key.encode(), int(value)), f"he_ctx_set_knob({key})")
+
+    def get_knob(self, key: str) -> int:
+        v = C.c_int64()
+        _check(lib().he_ctx_get_knob(self.h, key.encode(), C.byref(v)), f"he_ctx_get_knob({key})")
+        return int(v.value)
 
     def sync(self) -> None:
         _check(lib().he_sync(self.h), "he_sync")

@@ -269,11 +269,16 @@ class NetBackend(Backend):
     """One encrypted network on the HIP library: slot pool of device
     ciphertext buffers for every stage, batched launches, async import/export."""
 
-    def __init__(self, name: str, ctx, plan, layers: list, max_batch: int, slots: int):
+    def __init__(self, name: str, ctx, plan, layers: list, max_batch: int, slots: int, own_stream: bool = False):
         import torch
         from . import he
         self.torch, self.he = torch, he
         self.name, self.ctx, self.plan, self.layers = name, ctx, plan, layers
+        # Each network may get its own stream (default priority) so that two
+        # networks' batches overlap on the device.
+        self.stream = torch.cuda.Stream(device=ctx.device) if own_stream else torch.cuda.current_stream(ctx.device)
+        with torch.cuda.stream(self.stream):
+            ctx.use_current_stream()
         self.max_batch = max_batch
         self.stages = []
         for li in range(len(plan.layers)):
@@ -302,7 +307,7 @@ class NetBackend(Backend):
 
     def _event(self):
         e = self.torch.cuda.Event()
-        e.record()
+        e.record(self.stream)
         return e
 
     def acquire_slot(self):
@@ -312,6 +317,18 @@ class NetBackend(Backend):
         self.free.append(slot)
 
     def load(self, slot, payload):
+        with self.torch.cuda.stream(self.stream):
+            return self._load(slot, payload)
+
+    def run(self, stage, slots):
+        with self.torch.cuda.stream(self.stream):
+            return self._run(stage, slots)
+
+    def export(self, slot):
+        with self.torch.cuda.stream(self.stream):
+            return self._export(slot)
+
+    def _load(self, slot, payload):
         coeff, level, scale = payload
         b = self.bufs[slot]
         host = self.torch.from_numpy(np.ascontiguousarray(coeff).view(np.int64).reshape(-1))
@@ -328,7 +345,7 @@ class NetBackend(Backend):
     def _src(self, slot, stage):
         return self.bufs[slot]["in"] if stage == 0 else self.bufs[slot]["stage"][stage - 1]
 
-    def run(self, stage, slots):
+    def _run(self, stage, slots):
         kind, li = self.stages[stage]
         ins = [self._src(s, stage) for s in slots]
         outs = [self.bufs[s]["stage"][stage] for s in slots]
@@ -340,7 +357,7 @@ class NetBackend(Backend):
             self.ctx.square_batch(ins, outs)
         return self._event()
 
-    def export(self, slot):
+    def _export(self, slot):
         b = self.bufs[slot]
         ct = b["stage"][-1]
         c = ct._c()
