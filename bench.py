@@ -124,6 +124,30 @@ def ntt_leg(reps=10):
             "fwd_inv_gbs": 2 * alg_bytes / (f + i) / 1e6, "alg_bytes_per_transform": alg_bytes}
 
 
+def ntt_roofline(nt):
+    """Dominant kernel: the forward NTT, one he_ntt call = one phase-A and one
+    phase-B launch over 1536 limb-polys of 2^16 words.  Algorithmic bytes =
+    one read + one write of every word (16 B per coefficient); `traffic` is
+    the rocprofv3 FETCH_SIZE + WRITE_SIZE of those two launches (calibrated by
+    a 1 GiB copy), taken from profiles/ and dropped if the NTT source changed."""
+    import hashlib
+    polys = nt["alg_bytes_per_transform"] // (2 * 8 * 65536) // 2          # per call
+    alg = polys * 65536 * 8 * 2
+    t_call = nt["fwd_ms"] / 2 * 1e-3
+    achieved = alg / t_call / 1e9
+    traffic = None
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "ntt_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2104_09164_amd", "csrc", "ntt.hip"), "rb").read()
+        if prof["kernel_source_sha256"] == hashlib.sha256(src).hexdigest() and prof["polys_per_call"] == polys:
+            traffic = prof["fetch_bytes_per_call"] + prof["write_bytes_per_call"]
+    except (OSError, KeyError, ValueError):
+        traffic = None
+    return {"bound": "hbm", "kernel": f"forward NTT N=2^16, one call = phase-A + phase-B launch over {polys} limb-polys",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "alg_bytes": alg, "ms_per_call": t_call * 1e3}
+
+
 def cpu_baseline(plan, budget_s=20.0):
     """The oracle, untuned, on a bounded sample at the same ring and primes:
     timed key switch (rotation), MultPlain, square and rescale on one request,
@@ -166,13 +190,21 @@ def cpu_baseline(plan, budget_s=20.0):
                        f"per inference (est. {per_inf:.1f} s/inference)")}
 
 
-def network_legs(name, batch, steps, warmup, plain_n, graph=True):
-    """Batched (graph replay) and plain (one request at a time) legs of one preset."""
+def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=True):
+    """Batched (graph replay) and plain (one request at a time) legs of one preset.
+    A committed tuning file (paper_2104_09164_amd/tuning/<gfx>_<name>.json)
+    supplies the execution knobs and the per-layer baby-step counts."""
     import torch
-    from paper_2104_09164_amd import netplan
-    plan = netplan.preset_plan(name)
-    log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}")
+    from paper_2104_09164_amd import netplan, tune
+    tuned = tune.load(name) if use_tuning else None
+    shapes = None
+    if tuned and tuned.get("n1"):
+        shapes = [(m, n, n1) for (m, n, _), n1 in zip(netplan.PRESETS[name]["shapes"], tuned["n1"])]
+    plan = netplan.preset_plan(name, shapes)
+    log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}, "
+        f"n1={[l.n1 for l in plan.layers]}, knobs={tuned.get('knobs') if tuned else None}")
     ctx, runner = setup(plan, batch)
+    tune.apply_knobs(ctx, tuned)
     torch.cuda.synchronize()
     step = runner.capture(batch).replay if graph else (lambda: runner.run(batch))
     for _ in range(warmup):
@@ -199,7 +231,8 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True):
            "workload": (f"{name}: N=2^{plan.log_n}, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
                         f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
                         + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers) + ", x^2 between"),
-           "ops_per_inference": plan.op_counts()}
+           "ops_per_inference": plan.op_counts(),
+           "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1")} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
     return plan, ctx, runner, res
 
@@ -253,6 +286,7 @@ def main():
     ap.add_argument("--serve-rates", default="50,200,400")
     ap.add_argument("--serve-seconds", type=float, default=2.5)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore committed tuning files")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ntt", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -275,14 +309,15 @@ def main():
         print(json.dumps({"ntt": ntt_leg()}), flush=True)
         return 0
     plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
-                                            graph=not args.no_graph)
+                                            graph=not args.no_graph, use_tuning=not args.no_tuning)
     runner_layers["small"] = run3.layers
     out = {"metric": METRIC, "value": small["inferences_per_s"], "unit": "inferences/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": small["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
            "config": {"workload": ("small-net batched encrypted inference, " + small["workload"]
                                    + f", {args.batch} requests per launch, HIP graph replay"),
-                      "batch": args.batch, "ops_per_inference": small["ops_per_inference"]},
+                      "batch": args.batch, "ops_per_inference": small["ops_per_inference"],
+                      "tuning": small["tuning"]},
            "latency_ms": {"batched_p50": small["batched_p50_ms"], "batched_p99": small["batched_p99_ms"],
                           "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
            "plain_inferences_per_s": small["plain_inferences_per_s"],
@@ -290,7 +325,8 @@ def main():
     nets = {"small": (plan3, ctx3, args.batch)}
     if not args.no_large:
         plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, max(3, args.steps // 2), 1,
-                                                max(3, args.plain // 2), graph=not args.no_graph)
+                                                max(3, args.plain // 2), graph=not args.no_graph,
+                                                use_tuning=not args.no_tuning)
         runner_layers["large"] = run4.layers
         out["large_net"] = large
         nets["large"] = (plan4, ctx4, args.large_batch)
@@ -303,9 +339,7 @@ def main():
         log("ntt leg")
         nt = ntt_leg()
         out["ntt"] = nt
-        out["roofline"] = {"bound": "hbm", "kernel": "negacyclic NTT (forward, two phase launches)",
-                           "achieved": nt["fwd_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": nt["fwd_gbs"] / HBM_PEAK_GBS, "traffic": None}
+        out["roofline"] = ntt_roofline(nt)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(plan3)

@@ -91,6 +91,10 @@ typedef struct {
 } he_params;
 
 const char* he_strerror(int code);
+/* Text of the last HIP runtime failure seen by this thread (the failing call
+ * and hipGetErrorString), or "" if none; valid until the next library call
+ * on the same thread. */
+const char* he_last_error(void);
 
 /* Prime selection helper (parameter set-up, host only): the `count` largest
  * primes 2^bits + 1 - k*2N (k >= 1) that are not listed in taken[0..n_taken),
@@ -205,6 +209,8 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  * autotuner.  Keys:
  *   "ntt_chunk_mb"  two-phase NTT: run both phases per chunk of this many MiB
  *                   of polynomials (0 = each phase over the whole batch)
+ *   "ntt_cols"      two-phase NTT: sub-transforms per workgroup tile, 8, 16
+ *                   (default) or 32
  * Returns HE_EINVAL for an unknown key or a negative value. */
 int he_ctx_set_knob(he_ctx* ctx, const char* key, int64_t value);
 int he_ctx_get_knob(const he_ctx* ctx, const char* key, int64_t* value);

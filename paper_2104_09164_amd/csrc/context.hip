@@ -1,5 +1,6 @@
 // Context set-up, table generation, device uploads and the non-evaluation
 // entry points of include/he.h.
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <algorithm>
@@ -85,8 +86,9 @@ u64 to_mont_host(u64 x, u64 m) { return (u64)(((u128)(x % m) << 64) % m); }
 
 template <class T>
 int upload(he_ctx* c, T** dptr, const std::vector<T>& h) {
-  if (hipMalloc((void**)dptr, h.size() * sizeof(T)) != hipSuccess) return HE_EDEVICE;
-  if (hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return HE_EDEVICE;
+  (void)c;
+  HE_HIP(hipMalloc((void**)dptr, h.size() * sizeof(T)));
+  HE_HIP(hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return HE_OK;
 }
 
@@ -199,8 +201,16 @@ PolyBatch one_item(u64* p, u32 npoly, u32 period, u32 first_prime) {
 
 }  // namespace
 
+thread_local char g_last_error[256] = "";
+
+void note_hip_error(const char* where, hipError_t e) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
+
+const char* he_last_error(void) { return g_last_error; }
 
 const char* he_strerror(int code) {
   switch (code) {
@@ -259,8 +269,13 @@ int he_ctx_create(const he_params* pr, void* stream, he_ctx** out) {
   c->dnum = dnum;
   c->primes = primes;
   c->stream = (hipStream_t)stream;
-  hipGetDevice(&c->device);
-  int rc = build_tables(c);
+  g_last_error[0] = 0;
+  int rc = HE_OK;
+  {
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { note_hip_error("hipGetDevice", e); rc = HE_EDEVICE; }
+  }
+  if (!rc) rc = build_tables(c);
   if (rc) {
     free_tables(c);
     delete c;
@@ -436,12 +451,18 @@ int he_ntt(he_ctx* c, uint32_t n_items, uint64_t* const* items, uint32_t first_p
 int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
   if (!c || !key || value < 0) return HE_EINVAL;
   if (!std::strcmp(key, "ntt_chunk_mb")) { c->ntt_chunk_mb = value; return HE_OK; }
+  if (!std::strcmp(key, "ntt_cols")) {
+    if (value != 8 && value != 16 && value != 32) return HE_EINVAL;
+    c->ntt_cols = value;
+    return HE_OK;
+  }
   return HE_EINVAL;
 }
 
 int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!c || !key || !value) return HE_EINVAL;
   if (!std::strcmp(key, "ntt_chunk_mb")) { *value = c->ntt_chunk_mb; return HE_OK; }
+  if (!std::strcmp(key, "ntt_cols")) { *value = c->ntt_cols; return HE_OK; }
   return HE_EINVAL;
 }
 

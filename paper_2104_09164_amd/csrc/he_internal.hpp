@@ -70,6 +70,7 @@ struct he_ctx {
 
   // execution knobs (bit-preserving)
   int64_t ntt_chunk_mb = 0;
+  int64_t ntt_cols = 16;      // sub-transforms per NTT workgroup tile: 8, 16 or 32
 
   // workspace
   uint8_t* ws = nullptr;
@@ -96,6 +97,17 @@ static inline size_t limb_bytes(const he_ctx* c) { return (size_t)c->N * sizeof(
 // prime index of extended limb t in basis q_0..q_l, p_0..p_{K-1}
 static inline u32 ext_prime(const he_ctx* c, u32 l, u32 t) { return t <= l ? t : c->nq + (t - l - 1); }
 static inline u32 digits_at(const he_ctx* c, u32 l) { return (l + 1 + c->alpha - 1) / c->alpha; }
+
+// Records a HIP failure (call site + error string) for he_last_error().
+void note_hip_error(const char* where, hipError_t e);
+#define HE_HIP(call)                                    \
+  do {                                                  \
+    hipError_t he_e_ = (call);                          \
+    if (he_e_ != hipSuccess) {                          \
+      note_hip_error(#call, he_e_);                     \
+      return HE_EDEVICE;                                \
+    }                                                   \
+  } while (0)
 
 // kernel launchers (ntt.hip)
 int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse);

@@ -203,6 +203,20 @@ void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
 // on chunks of that many MiB of polynomials, so that the intermediate written
 // by phase A can still be in the Infinity Cache when phase B reads it back.
 
+template <int LOGN, int COLS>
+void ntt_two_phase(he_ctx* c, const PolyBatch& ch, bool inv) {
+  constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+  constexpr int NTA = ((COLS << LA) / 16) > 512 ? 512 : ((COLS << LA) / 16);
+  constexpr int NTB = ((COLS << LB) / 16) > 512 ? 512 : ((COLS << LB) / 16);
+  if (!inv) {
+    launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, ch, 1, 0);
+    launch_phase<LOGN, LA, LB, COLS, NTB, false>(c, ch, 0, 1);
+  } else {
+    launch_phase<LOGN, LA, LB, COLS, NTB, true>(c, ch, 1, 0);
+    launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, ch, 0, 1);
+  }
+}
+
 template <int LOGN>
 void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
   if constexpr (LOGN <= 13) {
@@ -210,10 +224,6 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
     if (!inv) launch_phase<LOGN, 0, LOGN, 1, NT, false>(c, pb, 1, 1);
     else launch_phase<LOGN, 0, LOGN, 1, NT, true>(c, pb, 1, 1);
   } else {
-    constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
-    constexpr int COLS = 16;
-    constexpr int NTA = ((COLS << LA) / 16) > 512 ? 512 : ((COLS << LA) / 16);
-    constexpr int NTB = ((COLS << LB) / 16) > 512 ? 512 : ((COLS << LB) / 16);
     const size_t poly_bytes = (size_t)8 << LOGN;
     u32 per = pb.npoly;
     if (c->ntt_chunk_mb > 0) {
@@ -226,13 +236,10 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
       ch.src_off = pb.src_off + r0;
       ch.dst_off = pb.dst_off + r0;
       for (u32 r = 0; r < ch.npoly; ++r) ch.prime[r] = pb.prime[r0 + r];
-      if (!inv) {
-        launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, ch, 1, 0);
-        launch_phase<LOGN, LA, LB, COLS, NTB, false>(c, ch, 0, 1);
-      } else {
-        launch_phase<LOGN, LA, LB, COLS, NTB, true>(c, ch, 1, 0);
-        launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, ch, 0, 1);
-      }
+      // tile width: sub-transforms per workgroup (knob ntt_cols)
+      if (c->ntt_cols == 8) ntt_two_phase<LOGN, 8>(c, ch, inv);
+      else if (c->ntt_cols == 32) ntt_two_phase<LOGN, 32>(c, ch, inv);
+      else ntt_two_phase<LOGN, 16>(c, ch, inv);
     }
   }
 }

@@ -22,7 +22,8 @@ HE_MAX_BATCH = 64
 
 class HeError(RuntimeError):
     def __init__(self, code: int, where: str):
-        super().__init__(f"{where}: {lib().he_strerror(code).decode()} ({code})")
+        detail = lib().he_last_error().decode() if code == -7 else ""
+        super().__init__(f"{where}: {lib().he_strerror(code).decode()} ({code})" + (f" [{detail}]" if detail else ""))
         self.code = code
 
 
@@ -44,11 +45,17 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                               "python paper_2104_09164_amd/build.py")
+        # torch ships its own HIP runtime with the same soname; it must be
+        # loaded first so that libhe.so binds to it.  Otherwise the process
+        # would hold two HIP/HSA runtimes and the device memory and streams
+        # torch hands over would belong to the other one.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, u32, u64, i32, sz, dbl = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_size_t, C.c_double
         ctp = C.POINTER(_Ct)
         sig = {
             "he_strerror": (C.c_char_p, [C.c_int]),
+            "he_last_error": (C.c_char_p, []),
             "he_gen_primes": (C.c_int, [u32, u32, u32, C.POINTER(u64), u32, C.POINTER(u64)]),
             "he_ctx_create": (C.c_int, [C.POINTER(_Params), vp, C.POINTER(vp)]),
             "he_ctx_destroy": (C.c_int, [vp]),
@@ -88,7 +95,7 @@ def lib() -> C.CDLL:
     return _lib
 
 
-EXPORTED = ("he_strerror", "he_gen_primes", "he_ctx_create", "he_ctx_destroy", "he_ctx_set_stream", "he_ct_bytes",
+EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "he_ctx_destroy", "he_ctx_set_stream", "he_ct_bytes",
             "he_key_bytes", "he_workspace_bytes", "he_dense_bytes", "he_ctx_bind", "he_load_keys", "he_dense_load",
             "he_dense_free", "he_ct_import", "he_ct_export", "he_ct_from_coeff_dev", "he_ct_to_coeff_dev",
             "he_eval_dense", "he_square", "he_rotate", "he_rotate_hoisted", "he_rescale", "he_add",

@@ -57,3 +57,13 @@ def test_product_path_has_no_oracle_import():
         for f in files:
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 assert not pat.search(open(os.path.join(dirpath, f)).read()), f
+
+
+def test_single_hip_runtime_whatever_the_import_order():
+    import subprocess
+    import sys
+    code = ("import os; from paper_2104_09164_amd import he; he.lib(); import torch; "
+            "m = open(f'/proc/{os.getpid()}/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "1"

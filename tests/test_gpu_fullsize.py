@@ -1,0 +1,73 @@
+"""Full-size parity in the benchmark's launch configuration (graph replay of the
+batched network with the committed tuned plan).
+
+cfg3 (N = 2^15, the benchmark's `value` workload): one request's whole
+network, bit for bit against the oracle, plus FP64 tolerance.
+cfg4 (N = 2^16): the oracle's full network is minutes of CPU work, so the
+property checked at full size is the plaintext one: decrypted logits within
+2^-12 of the FP64 network and the same predicted class, for two requests
+evaluated in one batched graph replay.
+"""
+import numpy as np
+import pytest
+
+from oracle import ckks, params, plainnet, plan
+from paper_2104_09164_amd import netplan, synth, tune
+
+pytestmark = pytest.mark.gpu
+
+
+def run_network(name, requests, check_bits):
+    import torch
+    from paper_2104_09164_amd import he
+    from paper_2104_09164_amd.batch import NetworkRunner
+    c = netplan.PRESETS[name]
+    tuned = tune.load(name, "gfx950")
+    n1s = tuned["n1"] if tuned else [s[2] for s in c["shapes"]]
+    shapes = [(m, n, n1) for (m, n, _), n1 in zip(c["shapes"], n1s)]
+    pr = params.preset(name)
+    o = ckks.Oracle(pr)
+    print(f"[fullsize] {name}: keygen for {len(ckks.network_steps(shapes))} rotation keys", flush=True)
+    keys = o.keygen(synth.SEED_KEYS, ckks.network_steps(shapes))
+    Ws, bs = synth.network_weights(shapes, c["sigma"])
+    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes])
+    npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, c["scale_bits"], shapes)
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    tune.apply_knobs(ctx, tuned)
+    B = len(requests)
+    ctx.bind(B, npl.max_n1(), npl.max_n2())
+    ctx.load_keys(keys.rlk, keys.rot)
+    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale) for l in lays]
+    runner = NetworkRunner(ctx, npl, dls, B)
+    cts, xs = [], []
+    for i, r in enumerate(requests):
+        x = synth.request_input(shapes[0][1], r)
+        ct = o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r))
+        runner.inputs[i].buf.copy_(ctx.import_ct(ct.data, ct.level, ct.scale).buf)
+        cts.append(ct)
+        xs.append(x)
+    g = runner.capture(B)
+    g.replay()
+    torch.cuda.synchronize()
+    outs = runner.outputs(B)
+    for i in range(B):
+        got = ctx.export_ct(outs[i])
+        assert outs[i].level == npl.out_level and outs[i].scale == npl.out_scale
+        if check_bits:
+            print(f"[fullsize] {name}: oracle network for request {requests[i]}", flush=True)
+            want = o.eval_network(cts[i], lays, keys)
+            assert want.scale == outs[i].scale
+            assert np.array_equal(got, want.data), f"{name} request {requests[i]} differs from the oracle"
+        y = o.decrypt_decode(ckks.Ciphertext(got, outs[i].level, outs[i].scale), keys.sk).real[:2]
+        yr = plainnet.forward(xs[i], Ws, bs)
+        assert np.max(np.abs(y - yr)) <= 2.0 ** -12
+        if abs(yr[0] - yr[1]) >= 2.0 ** -11:
+            assert plainnet.predict(y) == plainnet.predict(yr)
+
+
+def test_cfg3_network_full_size_bit_exact():
+    run_network("cfg3", [0, 1], check_bits=True)
+
+
+def test_cfg4_network_full_size_fp64():
+    run_network("cfg4", [0, 1], check_bits=False)

@@ -1,0 +1,56 @@
+"""Autotuner selection logic (CPU); the GPU test checks that knobs never change a bit."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2104_09164_amd import tune
+
+
+def test_n1_candidates():
+    assert tune.n1_candidates(128) == [1, 2, 4, 8, 16, 32, 64]
+    assert tune.n1_candidates(2) == [1, 2]
+    assert tune.n1_candidates(256, 32) == [1, 2, 4, 8, 16, 32]
+    for m in (2, 64, 256):
+        for n1 in tune.n1_candidates(m):
+            assert m % n1 == 0
+
+
+def test_pick_min_and_batch():
+    assert tune.pick_min({"a": 3.0, "b": 1.0, "c": 1.0}) == "b"
+    rates = {1: 100.0, 8: 700.0, 16: 1100.0, 32: 1150.0}
+    lat = {1: 10.0, 8: 11.4, 16: 14.5, 32: 27.8}
+    assert tune.pick_batch(rates, lat, None) == 32
+    assert tune.pick_batch(rates, lat, 20.0) == 16
+    assert tune.pick_batch(rates, lat, 5.0) == 1
+
+
+def test_knob_grid_covers_space():
+    grid = tune.knob_grid({"a": [1, 2], "b": [3, 4, 5]})
+    assert len(grid) == 6 and {json.dumps(g, sort_keys=True) for g in grid} == \
+        {json.dumps({"a": a, "b": b}, sort_keys=True) for a in (1, 2) for b in (3, 4, 5)}
+
+
+@pytest.mark.gpu
+def test_knobs_preserve_bits():
+    from oracle import ckks, params, plan
+    from paper_2104_09164_amd import he, synth
+    pr = params.make(14, [50, 40, 40, 40], [50, 50], 2, 30)
+    o = ckks.Oracle(pr)
+    m, n, n1 = 8, 64, 4
+    keys = o.keygen(1, plan.rotation_steps(m, n, n1))
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    ctx.bind(3, n1, m // n1)
+    ctx.load_keys(keys.rlk, keys.rot)
+    W, b = synth.network_weights([(m, n, n1)], 0.05)
+    cts = [o.encrypt(plan.input_slots(synth.request_input(n, r), pr.slots), keys.pk, r) for r in range(3)]
+    lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale)
+    want = [o.rescale(o.square(o.dense(c, lay, keys), keys)).data for c in cts]
+    for knobs in tune.knob_grid():
+        for k, v in knobs.items():
+            ctx.set_knob(k, v)
+        gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+        out = ctx.rescale_batch(ctx.square_batch(ctx.eval_dense_batch(gs, d)))
+        for g, w in zip(out, want):
+            assert np.array_equal(ctx.export_ct(g), w), knobs
