@@ -219,10 +219,13 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"{name}: plain leg")
-    for _ in range(2):
-        runner.run(1)
-    torch.cuda.synchronize()
-    lat = time_events(lambda: runner.run(1), plain_n)
+    if plain_n > 0:
+        for _ in range(2):
+            runner.run(1)
+        torch.cuda.synchronize()
+        lat = time_events(lambda: runner.run(1), plain_n)
+    else:
+        lat = [float("nan")]
     c = netplan.PRESETS[name]
     res = {"batch": batch, "inferences_per_s": batch * steps / wall, "ms_per_step": wall * 1e3 / steps,
            "batched_p50_ms": float(np.percentile(per_step, 50)), "batched_p99_ms": float(np.percentile(per_step, 99)),

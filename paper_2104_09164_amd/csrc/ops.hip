@@ -71,7 +71,8 @@ PolyBatch batch_of(u32 nitems) {
 
 // ModUp of the c1 polynomials (NTT form) of B items at level l into w.ext
 // (all digits, NTT form): INTT to coefficients, fast base conversion of each
-// digit, the digit's own limbs copied unchanged, NTT of the converted limbs.
+// digit, NTT of the converted limbs.  A digit's own limbs are the source's
+// limbs unchanged; the inner product reads them from the source.
 int modup(he_ctx* c, u32 l, u32 B, u64* const* c1, const WS& w) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np, beta = digits_at(c, l);
@@ -84,18 +85,6 @@ int modup(he_ctx* c, u32 l, u32 B, u64* const* c1, const WS& w) {
   for (u32 r = 0; r <= l; ++r) pb.prime[r] = (uint8_t)r;
   int rc = launch_ntt(c, pb, true);
   if (!rc) rc = launch_modup_conv(c, l, B, w.coef, w.ext);
-  for (u32 j = 0; !rc && j < beta; ++j) {
-    const u32 lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
-    PolyBatch cp = batch_of(B);
-    cp.npoly = hi - lo;
-    cp.src_off = cp.dst_off = lo;
-    for (u32 b = 0; b < B; ++b) {
-      cp.src[b] = c1[b];
-      cp.dst[b] = w.ext + ((size_t)b * c->dnum + j) * ne * N;
-    }
-    for (u32 r = 0; r < cp.npoly; ++r) cp.prime[r] = (uint8_t)(lo + r);
-    rc = launch_copy_polys(c, cp);
-  }
   if (rc) return rc;
   PolyBatch nt = batch_of(B);
   nt.npoly = beta * ne;
@@ -108,12 +97,16 @@ int modup(he_ctx* c, u32 l, u32 B, u64* const* c1, const WS& w) {
   return launch_ntt(c, nt, false);
 }
 
-// Key switch of the digits in w.ext with `key` (automorphism `galois` on the
-// digits), ModDown, combined into fa.out.
-int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, const u64* key, u32 galois, const FinalArgs& fa, const u64* bias) {
+// Key switch of the digits in w.ext (own limbs from c1) with `key`
+// (automorphism `galois` on the digits), ModDown, combined into fa.out.
+int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key, u32 galois, const FinalArgs& fa,
+            const u64* bias) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np;
-  int rc = launch_ks_inner(c, l, B, w.ext, key, galois, w.u);
+  Items own;
+  own.n = B;
+  for (u32 b = 0; b < B; ++b) own.p[b] = c1[b];
+  int rc = launch_ks_inner(c, l, B, w.ext, own, key, galois, w.u);
   if (rc) return rc;
   PolyBatch pi = batch_of(B);
   pi.npoly = 2 * ne;
@@ -195,11 +188,9 @@ int he_rotate_hoisted_batch(he_ctx* c, uint32_t n, const he_ct* in, uint32_t n_s
   const size_t N = c->N;
   bool need_modup = false;
   for (u32 s = 0; s < n_steps; ++s) need_modup |= keys[s] != nullptr;
-  if (need_modup) {
-    u64* c1[HE_MAXB];
-    for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
-    if ((rc = modup(c, l, n, c1, w))) return rc;
-  }
+  u64* c1[HE_MAXB];
+  for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
+  if (need_modup && (rc = modup(c, l, n, c1, w))) return rc;
   for (u32 s = 0; s < n_steps; ++s) {
     for (u32 b = 0; b < n; ++b) {
       out[b * n_steps + s].level = l;
@@ -215,7 +206,7 @@ int he_rotate_hoisted_batch(he_ctx* c, uint32_t n, const he_ct* in, uint32_t n_s
       fa.out[b] = out[b * n_steps + s].dev;
       fa.add0[b] = in[b].dev;
     }
-    if ((rc = ks_core(c, l, n, w, keys[s]->dev, keys[s]->galois, fa, nullptr))) return rc;
+    if ((rc = ks_core(c, l, n, w, c1, keys[s]->dev, keys[s]->galois, fa, nullptr))) return rc;
   }
   return HE_OK;
 }
@@ -248,7 +239,7 @@ int he_square_batch(he_ctx* c, uint32_t n, const he_ct* in, he_ct* out) {
     fa.add0[b] = w.d01 + (size_t)b * 2 * (l + 1) * N;
     fa.add1[b] = w.d01 + (size_t)b * 2 * (l + 1) * N + (size_t)(l + 1) * N;
   }
-  if ((rc = ks_core(c, l, n, w, c->relin_dev, 1, fa, nullptr))) return rc;
+  if ((rc = ks_core(c, l, n, w, c1, c->relin_dev, 1, fa, nullptr))) return rc;
   for (u32 b = 0; b < n; ++b) {
     out[b].level = l;
     out[b].scale = in[b].scale * in[b].scale;
@@ -350,10 +341,10 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   for (u32 b = 0; b < n; ++b) inI.p[b] = in[b].dev;
 
   // Baby steps: one hoisted ModUp, n1 - 1 key switches.
+  u64* c1in[HE_MAXB];
+  for (u32 b = 0; b < n; ++b) c1in[b] = in[b].dev + (size_t)(l + 1) * N;
   if (n1 > 1) {
-    u64* c1[HE_MAXB];
-    for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
-    if ((rc = modup(c, l, n, c1, w))) return rc;
+    if ((rc = modup(c, l, n, c1in, w))) return rc;
     for (u32 i = 1; i < n1; ++i) {
       FinalArgs fa = no_final();
       for (u32 b = 0; b < n; ++b) {
@@ -365,7 +356,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
           if ((rc = copy_ct(c, l, in[b].dev, fa.out[b]))) return rc;
         continue;
       }
-      if ((rc = ks_core(c, l, n, w, baby[i]->dev, baby[i]->galois, fa, nullptr))) return rc;
+      if ((rc = ks_core(c, l, n, w, c1in, baby[i]->dev, baby[i]->galois, fa, nullptr))) return rc;
     }
   }
   // Inner sums s_j (giant region [B][n2][csz]).
@@ -398,7 +389,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       u64* c1[HE_MAXB];
       for (u32 b = 0; b < n; ++b) c1[b] = src[b] + (size_t)(l + 1) * N;
       if ((r = modup(c, l, n, c1, w))) return r;
-      if ((r = ks_core(c, l, n, w, key->dev, key->galois, fa, bias))) return r;
+      if ((r = ks_core(c, l, n, w, c1, key->dev, key->galois, fa, bias))) return r;
     } else {
       // rotation by a multiple of N/2 is the identity: dst = cur + src
       Items a, s, o;

@@ -60,11 +60,13 @@ __global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef,
 }
 
 // grid: (N/BS, ne, 1); loops over items so key words are loaded once per batch.
+// A digit's own limbs are not copied into ext: they are read from the source
+// polynomial (NTT form) given per item in `own`.
 template <bool PERM>
-__global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, const u64* __restrict__ key,
+__global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, Items own, const u64* __restrict__ key,
                                                  u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
                                                  u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
-                                                 u32 nitems, u32 galois) {
+                                                 u32 nitems, u32 galois, u32 alpha) {
   const u32 k = blockIdx.x * BS + threadIdx.x;
   const u32 t = blockIdx.y;
   const u32 ne = l + 1 + np, nt = nq + np;
@@ -76,11 +78,12 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, co
     kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + k];
     ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
   }
+  const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
   for (u32 b = 0; b < nitems; ++b) {
     u128v sb = {0, 0}, sa = {0, 0};
     const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
     for (u32 j = 0; j < beta; ++j) {
-      const u64 x = e[(size_t)j * ne * N];
+      const u64 x = j == own_digit ? own.p[b][(size_t)t * N + ks] : e[(size_t)j * ne * N];
       acc_wide(sb, x, kb[j]);
       acc_wide(sa, x, ka[j]);
     }
@@ -270,14 +273,15 @@ int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
   return ok();
 }
 
-int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const u64* key, u32 galois, u64* u) {
+int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& own, const u64* key, u32 galois,
+                    u64* u) {
   dim3 grid(c->N / BS, l + 1 + c->np, 1);
   if (galois != 1)
-    hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(BS), 0, c->stream, ext, key, u, c->d_pc, c->N, c->log_n, l, c->nq,
-                       c->np, digits_at(c, l), c->dnum, nitems, galois);
+    hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
+                       c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
   else
-    hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(BS), 0, c->stream, ext, key, u, c->d_pc, c->N, c->log_n, l, c->nq,
-                       c->np, digits_at(c, l), c->dnum, nitems, galois);
+    hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
+                       c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
   return ok();
 }
 
@@ -295,9 +299,12 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
 }
 
 int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s) {
-  const u32 jc = n2 >= 4 ? 4 : n2;
+  // all giant-step sums of a thread in registers (up to 8) so every baby-step
+  // ciphertext is read once per batch
+  const u32 jc = n2 >= 8 ? 8 : n2;
   dim3 grid(c->N / BS, l + 1, in.n * (n2 / jc));
   switch (jc) {
+    case 8: hipLaunchKernelGGL(k_multplain_acc<8>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
     case 4: hipLaunchKernelGGL(k_multplain_acc<4>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
     case 2: hipLaunchKernelGGL(k_multplain_acc<2>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
     default: hipLaunchKernelGGL(k_multplain_acc<1>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;

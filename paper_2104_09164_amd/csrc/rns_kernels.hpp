@@ -14,13 +14,16 @@ int launch_copy_polys(he_ctx* c, const PolyBatch& pb);
 
 // ModUp conversion at level l: coef = [B][l+1][N] coefficient form (item
 // stride (l+1) N); ext = [B][beta][l+1+K][N]; writes every limb of every digit
-// except the digit's own limbs (coefficient form).
+// except the digit's own limbs (coefficient form; those stay in the source).
 int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext);
 
 // Key inner product at level l: for item b and key part p in {b, a}:
 //   u[b][p][t][k] = sum_j ext[b][j][t][perm_g(k)] * key[j][p][prime(t)][k]   (Montgomery)
 // galois == 1: no permutation.  ext = [B][beta][l+1+K][N], u = [B][2][l+1+K][N].
-int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const u64* key, u32 galois, u64* u);
+// The limbs of digit j that belong to j itself are read from own.p[b] (the
+// NTT-form source polynomial, [l+1][N]) instead of ext.
+int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& own, const u64* key, u32 galois,
+                    u64* u);
 
 // ModDown conversion: u = [B][2][l+1+K][N] with the P-limbs already in
 // coefficient form; conv = [B][2][l+1][N] coefficient form.
