@@ -15,7 +15,9 @@ leg's inferences/s.  Reported beside it, in the same JSON line:
     requests, continuous batching, p50/p99 from arrival to exported result;
   * the NTT micro-benchmark (64 ciphertexts x 2 x 24 limbs at N=2^16,
     forward + inverse) in algorithmic HBM GB/s;
-  * the roofline of the dominant kernel (HIP events on the library stream);
+  * the roofline of the step's dominant kernel class: the same step run
+    eagerly with the library tracer on (HIP events around every launch on the
+    library stream, algorithmic bytes per launch), plus the NTT leg's;
   * the CPU oracle on a bounded sample, scaled to inferences/s.
 Inputs are seeded uniform residues (keys, plaintext diagonals, ciphertexts):
 every kernel's work and memory traffic is independent of the residue values,
@@ -190,6 +192,69 @@ def cpu_baseline(plan, budget_s=20.0):
                        f"per inference (est. {per_inf:.1f} s/inference)")}
 
 
+KERNEL_LABEL = {
+    "ntt_fwd_a": "forward NTT, phase A (column transforms)",
+    "ntt_fwd_b": "forward NTT, phase B (row transforms)",
+    "ntt_inv_b": "inverse NTT, phase B (row transforms)",
+    "ntt_inv_a": "inverse NTT, phase A (column transforms, N^-1)",
+    "ks_inner": "key-switch inner product (eval-key x extended digits, automorphism gather)",
+    "ks_final": "key-switch epilogue ((u - conv) P^-1 + sigma(c0) + accumulators)",
+    "multplain": "MultPlain inner sums over baby-step ciphertexts",
+}
+
+
+def trace_steps(ctx, runner, batch, steps):
+    """Run `steps` batched inferences eagerly with the library tracer on: every
+    launch bracketed by HIP events on the library stream, carrying its
+    algorithmic byte count.  Same launches as the graph the timed leg replays."""
+    import torch
+    runner.run(batch)
+    torch.cuda.synchronize()
+    ctx.trace_read()
+    ctx.set_knob("trace", 1)
+    for _ in range(steps):
+        runner.run(batch)
+    tab = ctx.trace_read()
+    ctx.set_knob("trace", 0)
+    return tab
+
+
+def traffic_record(kernel, launches_per_step):
+    """rocprofv3 FETCH_SIZE/WRITE_SIZE of one kernel class, per launch, from
+    profiles/; dropped unless taken on the current kernel sources."""
+    import hashlib
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "roofline_traffic.json")))
+        h = hashlib.sha256()
+        for f in sorted(os.listdir(os.path.join(ROOT, "paper_2104_09164_amd", "csrc"))):
+            h.update(open(os.path.join(ROOT, "paper_2104_09164_amd", "csrc", f), "rb").read())
+        rec = prof.get("kernels", {}).get(kernel)
+        if (rec and prof["csrc_sha256"] == h.hexdigest()
+                and rec["launches_per_step"] == launches_per_step):
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
+def step_roofline(tab, steps):
+    """Roofline of the dominant kernel class of one step (largest summed time):
+    achieved = its algorithmic bytes per launch / its mean launch duration."""
+    kern = max(tab, key=lambda k: tab[k][1])
+    n, ms, by = tab[kern]
+    achieved = by / (ms * 1e-3) / 1e9
+    per_step = n // steps
+    total_ms = sum(v[1] for v in tab.values())
+    return {"bound": "hbm", "kernel": KERNEL_LABEL.get(kern, kern), "kernel_class": kern,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_record(kern, per_step), "alg_bytes_per_launch": by / n,
+            "us_per_launch": ms * 1e3 / n, "launches_per_step": per_step,
+            "share_of_kernel_time": ms / total_ms,
+            "classes": {k: {"launches_per_step": v[0] // steps, "ms_per_step": v[1] / steps,
+                            "gbs": v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None}
+                        for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])}}
+
+
 def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=True):
     """Batched (graph replay) and plain (one request at a time) legs of one preset.
     A committed tuning file (paper_2104_09164_amd/tuning/<gfx>_<name>.json)
@@ -237,6 +302,8 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
            "ops_per_inference": plan.op_counts(),
            "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1")} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
+    log(f"{name}: traced eager pass")
+    res["trace"] = trace_steps(ctx, runner, batch, steps)
     return plan, ctx, runner, res
 
 
@@ -278,6 +345,16 @@ def serving_leg(nets, rates, seconds, seed=21):
 runner_layers = {}
 
 
+def calibration_copy():
+    """1 GiB read + 1 GiB written by one device copy: scales the HBM counters."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +371,9 @@ def main():
     ap.add_argument("--no-ntt", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the small-net traced pass (profiling runs): 1 GiB calibration copy, "
+                         "setup, one untimed step, --steps traced steps")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the NTT leg (profiling runs), preceded by a 1 GiB device copy whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -304,12 +384,19 @@ def main():
         return 2
     import torch
     if args.ntt_only:
-        src = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
-        dst = torch.empty_like(src)
-        dst.copy_(src)                                   # 1 GiB read + 1 GiB written: counter calibration
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy()
         print(json.dumps({"ntt": ntt_leg()}), flush=True)
+        return 0
+    if args.roofline_only:
+        from paper_2104_09164_amd import netplan, tune
+        calibration_copy()
+        tuned = tune.load("cfg3")
+        shapes = [(m, n, n1) for (m, n, _), n1 in zip(netplan.PRESETS["cfg3"]["shapes"], tuned["n1"])]
+        plan = netplan.preset_plan("cfg3", shapes)
+        ctx, runner = setup(plan, args.batch)
+        tune.apply_knobs(ctx, tuned)
+        tab = trace_steps(ctx, runner, args.batch, args.steps)
+        print(json.dumps({"roofline": step_roofline(tab, args.steps)}), flush=True)
         return 0
     plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
                                             graph=not args.no_graph, use_tuning=not args.no_tuning)
@@ -323,14 +410,17 @@ def main():
                       "tuning": small["tuning"]},
            "latency_ms": {"batched_p50": small["batched_p50_ms"], "batched_p99": small["batched_p99_ms"],
                           "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
+           "roofline": step_roofline(small.pop("trace"), args.steps),
            "plain_inferences_per_s": small["plain_inferences_per_s"],
            "batched_over_plain": small["batched_over_plain"]}
     nets = {"small": (plan3, ctx3, args.batch)}
     if not args.no_large:
-        plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, max(3, args.steps // 2), 1,
+        large_steps = max(3, args.steps // 2)
+        plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, large_steps, 1,
                                                 max(3, args.plain // 2), graph=not args.no_graph,
                                                 use_tuning=not args.no_tuning)
         runner_layers["large"] = run4.layers
+        large["roofline"] = step_roofline(large.pop("trace"), large_steps)
         out["large_net"] = large
         nets["large"] = (plan4, ctx4, args.large_batch)
     if not args.no_serve and not args.no_large:
@@ -342,7 +432,7 @@ def main():
         log("ntt leg")
         nt = ntt_leg()
         out["ntt"] = nt
-        out["roofline"] = ntt_roofline(nt)
+        out["ntt_roofline"] = ntt_roofline(nt)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(plan3)

@@ -211,9 +211,29 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   of polynomials (0 = each phase over the whole batch)
  *   "ntt_cols"      two-phase NTT: sub-transforms per workgroup tile, 8, 16
  *                   (default) or 32
+ *   "ntt_single_pass"  N = 2^15: 1 = one register-resident launch per
+ *                   transform (one HBM pass), 0 (default) = two phases
+ *   "trace"         1 = bracket every kernel launch with HIP events on the
+ *                   context stream (not while the stream is being captured
+ *                   into a graph); read with he_trace_read.  0 = off.
  * Returns HE_EINVAL for an unknown key or a negative value. */
 int he_ctx_set_knob(he_ctx* ctx, const char* key, int64_t value);
 int he_ctx_get_knob(const he_ctx* ctx, const char* key, int64_t* value);
+
+/* Per-kernel-class totals of the launches traced since the last read
+ * (knob "trace"): launches, summed event time in ms, and algorithmic bytes
+ * (every word a launch must read or write, counted once).  Synchronises the
+ * stream, then resets the trace.  Writes up to `capacity` entries, sets
+ * *count to the number of classes seen; HE_ENOMEM if launches were dropped
+ * because more than 8192 were traced between reads.  `kernel` points to a
+ * static string. */
+typedef struct {
+  const char* kernel;
+  uint64_t launches;
+  double ms;
+  double bytes;
+} he_trace_entry;
+int he_trace_read(he_ctx* ctx, he_trace_entry* out, uint32_t capacity, uint32_t* count);
 
 /* Waits for all work enqueued on the context's stream. */
 int he_sync(he_ctx* ctx);

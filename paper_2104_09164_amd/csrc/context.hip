@@ -181,6 +181,8 @@ int build_tables(he_ctx* c) {
 }
 
 void free_tables(he_ctx* c) {
+  for (auto& e : c->tr.pool) hipEventDestroy(e);
+  c->tr.pool.clear();
   hipFree(c->d_pc);
   hipFree(c->d_tw);
   hipFree(c->d_modup_hatinv);
@@ -202,6 +204,44 @@ PolyBatch one_item(u64* p, u32 npoly, u32 period, u32 first_prime) {
 }  // namespace
 
 thread_local char g_last_error[256] = "";
+
+static const char* kTraceNames[TK_COUNT] = {
+    "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
+    "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner", "moddown_conv", "ks_final", "multplain_acc", "tensor",
+    "rescale_reduce", "rescale_final", "add", "add_plain", "copy_polys", "to_mont"};
+
+const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
+
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+TraceScope::TraceScope(he_ctx* ctx, int k, double b) : c(ctx), kind(k), bytes(b) {
+  if (!c->tr.on || capturing(c->stream)) return;
+  if (c->tr.next + 2 > c->tr.pool.size()) { ++c->tr.dropped; return; }
+  a = c->tr.pool[c->tr.next++];
+  hipEventRecord(a, c->stream);
+}
+
+TraceScope::~TraceScope() {
+  if (!a) return;
+  hipEvent_t b = c->tr.pool[c->tr.next++];
+  hipEventRecord(b, c->stream);
+  c->tr.recs.push_back({kind, a, b, bytes});
+}
+
+static int trace_enable(he_ctx* c, bool on) {
+  if (on && c->tr.pool.empty()) {
+    c->tr.pool.resize(16384);
+    for (auto& e : c->tr.pool) HE_HIP(hipEventCreate(&e));
+  }
+  c->tr.on = on;
+  c->tr.next = 0;
+  c->tr.recs.clear();
+  c->tr.dropped = 0;
+  return HE_OK;
+}
 
 void note_hip_error(const char* where, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
@@ -456,13 +496,48 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ntt_cols = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ntt_single_pass")) {
+    if (value > 1) return HE_EINVAL;
+    c->ntt_single_pass = value;
+    return HE_OK;
+  }
+  if (!std::strcmp(key, "trace")) {
+    if (value > 1) return HE_EINVAL;
+    return trace_enable(c, value == 1);
+  }
   return HE_EINVAL;
+}
+
+int he_trace_read(he_ctx* c, he_trace_entry* out, uint32_t capacity, uint32_t* count) {
+  if (!c || !count || (capacity && !out)) return HE_EINVAL;
+  HE_HIP(hipStreamSynchronize(c->stream));
+  uint64_t n[TK_COUNT] = {0};
+  double ms[TK_COUNT] = {0}, by[TK_COUNT] = {0};
+  for (const TraceRec& r : c->tr.recs) {
+    float t = 0;
+    HE_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ++n[r.kind];
+    ms[r.kind] += t;
+    by[r.kind] += r.bytes;
+  }
+  uint32_t k = 0;
+  for (int i = 0; i < TK_COUNT; ++i) {
+    if (!n[i]) continue;
+    if (k < capacity) out[k] = he_trace_entry{trace_name(i), n[i], ms[i], by[i]};
+    ++k;
+  }
+  *count = k;
+  c->tr.next = 0;
+  c->tr.recs.clear();
+  return c->tr.dropped ? HE_ENOMEM : HE_OK;
 }
 
 int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!c || !key || !value) return HE_EINVAL;
   if (!std::strcmp(key, "ntt_chunk_mb")) { *value = c->ntt_chunk_mb; return HE_OK; }
   if (!std::strcmp(key, "ntt_cols")) { *value = c->ntt_cols; return HE_OK; }
+  if (!std::strcmp(key, "ntt_single_pass")) { *value = c->ntt_single_pass; return HE_OK; }
+  if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }
 

@@ -40,6 +40,28 @@ struct PolyBatch {
   uint8_t prime[HE_MAX_POLYS];
 };
 
+// Kernel classes of the tracer (he_trace_read aggregates per class).
+enum TraceKind {
+  TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
+  TK_MODUP_CONV, TK_KS_INNER, TK_MODDOWN_CONV, TK_KS_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE,
+  TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_TO_MONT, TK_COUNT
+};
+const char* trace_name(int kind);
+
+struct TraceRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Tracer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // created when tracing is switched on
+  size_t next = 0;
+  std::vector<TraceRec> recs;
+  uint64_t dropped = 0;           // launches not recorded (pool exhausted)
+};
+
 struct KeySlot {
   int32_t step;
   u32 galois;
@@ -71,6 +93,9 @@ struct he_ctx {
   // execution knobs (bit-preserving)
   int64_t ntt_chunk_mb = 0;
   int64_t ntt_cols = 16;      // sub-transforms per NTT workgroup tile: 8, 16 or 32
+  int64_t ntt_single_pass = 0;  // N = 2^15: register-resident single-pass transform (off: VALU-bound either way)
+
+  Tracer tr;
 
   // workspace
   uint8_t* ws = nullptr;
@@ -108,6 +133,18 @@ void note_hip_error(const char* where, hipError_t e);
       return HE_EDEVICE;                                \
     }                                                   \
   } while (0)
+
+// Brackets one kernel launch with HIP events on the context stream while
+// tracing is on (and the stream is not being captured into a graph);
+// `bytes` = algorithmic bytes of the launch (each word read or written once).
+struct TraceScope {
+  he_ctx* c;
+  int kind;
+  double bytes;
+  hipEvent_t a = nullptr;
+  TraceScope(he_ctx* ctx, int k, double b);
+  ~TraceScope();
+};
 
 // kernel launchers (ntt.hip)
 int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse);

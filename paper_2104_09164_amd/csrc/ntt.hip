@@ -136,6 +136,166 @@ struct Phase {
   }
 };
 
+// Radix-2^RB butterflies on a register array x[m], m = the RB index bits of
+// the stages s0 .. s0+RB-1 (most significant first); `prefix` = the index bits
+// above them, so the twiddle of sub-stage uu, block blk is
+// psi^brev(2^(s0+uu) + prefix 2^uu + blk).
+template <int RB, bool INV>
+__device__ __forceinline__ void reg_pass(u64 (&x)[1 << RB], const ulonglong2* __restrict__ tw, const PrimeConst& k,
+                                         u32 s0, u32 prefix) {
+  constexpr int R = 1 << RB;
+  const u64 q = k.q, q4 = 4 * q;
+  if (!INV) {
+#pragma unroll
+    for (int uu = 0; uu < RB; ++uu) {
+      const int half = R >> (uu + 1);
+#pragma unroll
+      for (int blk = 0; blk < (1 << uu); ++blk) {
+        const ulonglong2 wp = tw[(1u << (s0 + uu)) + (prefix << uu) + blk];
+#pragma unroll
+        for (int e = 0; e < half; ++e) {
+          const int m0 = blk * 2 * half + e, m1 = m0 + half;
+          const u64 X = csub_neg(x[m0], k.nq4);
+          const u64 S = add_shoup4(X, x[m1], wp.x, wp.y, k.nq);
+          x[m0] = S;
+          x[m1] = 2 * X + q4 - S;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int uu = RB - 1; uu >= 0; --uu) {
+      const int half = R >> (uu + 1);
+#pragma unroll
+      for (int blk = 0; blk < (1 << uu); ++blk) {
+        const ulonglong2 wp = tw[(1u << (s0 + uu)) + (prefix << uu) + blk];
+#pragma unroll
+        for (int e = 0; e < half; ++e) {
+          const int m0 = blk * 2 * half + e, m1 = m0 + half;
+          const u64 A = x[m0], B = x[m1];
+          x[m0] = csub_neg(A + B, k.nq4);
+          x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);
+        }
+      }
+    }
+  }
+}
+
+// Single-pass transform for N = 2^15: one 1024-thread workgroup per
+// limb-poly holds the whole polynomial in registers (32 words per thread);
+// index j = a 2^10 + b 2^5 + c.  Pass 1 (stages 0-4, bits of a) runs in
+// thread (b, c), pass 2 (stages 5-9, bits of b) in thread (a, c), pass 3
+// (stages 10-14, bits of c) in thread (a, b).  The two transposes go through
+// LDS in two rounds, each round moving the words of the threads that keep
+// the preserved index's top bit (c for the first, a for the second): those
+// threads write all 32 words and read back 32, reusing one register array,
+// so no thread ever holds more than 32 words.  HBM sees one read and one
+// write of every word.  Grid: (item, poly), polynomials of one prime adjacent.
+constexpr int T1_A = 32 * 16 + 16;       // transpose 1 slab: [a][b][c mod 16]
+constexpr int T2_ROW = 33, T2_SLAB = 32 * T2_ROW;   // transpose 2: [a mod 16][b][c], rows padded
+
+template <bool INV>
+__global__ void __launch_bounds__(1024) k_ntt15(PolyBatch pb, const u64* __restrict__ tw_all,
+                                                const PrimeConst* __restrict__ pc) {
+  constexpr u32 N = 1u << 15;
+  __shared__ u64 lds[32 * T1_A > 16 * T2_SLAB ? 32 * T1_A : 16 * T2_SLAB];
+  const u32 b_item = blockIdx.x, r = blockIdx.y;
+  const u32 pr = pb.prime[r];
+  if (pr == 0xFF) return;
+  const PrimeConst k = pc[pr];
+  const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
+  const u64* src = pb.src[b_item] + (size_t)(pb.src_off + r) * N;
+  u64* dst = pb.dst[b_item] + (size_t)(pb.dst_off + r) * N;
+  const u32 t = threadIdx.x, hi5 = t >> 5, lo5 = t & 31;
+  const u32 c_half = lo5 >> 4, cl = lo5 & 15, a_half = t >> 9, al = hi5 & 15;
+  u64 x[32];
+  if (!INV) {
+    // thread (b, c) = (hi5, lo5): x[a] = word a 2^10 + t (coalesced)
+#pragma unroll
+    for (int a = 0; a < 32; ++a) x[a] = src[a * 1024 + t];
+    reg_pass<5, false>(x, tw, k, 0, 0);
+    // transpose 1 (c preserved): (b, c) holds a  ->  (a, c) holds b
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) __syncthreads();
+      if (c_half == (u32)h) {
+#pragma unroll
+        for (int a = 0; a < 32; ++a) lds[a * T1_A + hi5 * 16 + cl] = x[a];
+      }
+      __syncthreads();
+      if (c_half == (u32)h) {
+#pragma unroll
+        for (int bb = 0; bb < 32; ++bb) x[bb] = lds[hi5 * T1_A + bb * 16 + cl];
+      }
+    }
+    reg_pass<5, false>(x, tw, k, 5, hi5);                   // thread (a, c): prefix a
+    // transpose 2 (a preserved): (a, c) holds b  ->  (a, b) holds c
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();
+      if (a_half == (u32)h) {
+#pragma unroll
+        for (int bb = 0; bb < 32; ++bb) lds[al * T2_SLAB + bb * T2_ROW + lo5] = x[bb];
+      }
+      __syncthreads();
+      if (a_half == (u32)h) {
+#pragma unroll
+        for (int cc = 0; cc < 32; ++cc) x[cc] = lds[al * T2_SLAB + lo5 * T2_ROW + cc];
+      }
+    }
+    reg_pass<5, false>(x, tw, k, 10, t);                    // thread (a, b): prefix a 2^5 + b = t
+#pragma unroll
+    for (int cc = 0; cc < 32; cc += 2) {
+      ulonglong2 v;
+      v.x = csub_neg(csub_neg(csub_neg(x[cc], k.nq4), k.nq2), k.nq);
+      v.y = csub_neg(csub_neg(csub_neg(x[cc + 1], k.nq4), k.nq2), k.nq);
+      *(ulonglong2*)(dst + t * 32 + cc) = v;
+    }
+  } else {
+    // thread (a, b) = (hi5, lo5): x[c] = word t 2^5 + c
+#pragma unroll
+    for (int cc = 0; cc < 32; cc += 2) {
+      const ulonglong2 v = *(const ulonglong2*)(src + t * 32 + cc);
+      x[cc] = v.x;
+      x[cc + 1] = v.y;
+    }
+    reg_pass<5, true>(x, tw, k, 10, t);
+    // transpose 2 back (a preserved): (a, b) holds c  ->  (a, c) holds b
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();
+      if (a_half == (u32)h) {
+#pragma unroll
+        for (int cc = 0; cc < 32; ++cc) lds[al * T2_SLAB + lo5 * T2_ROW + cc] = x[cc];
+      }
+      __syncthreads();
+      if (a_half == (u32)h) {
+#pragma unroll
+        for (int bb = 0; bb < 32; ++bb) x[bb] = lds[al * T2_SLAB + bb * T2_ROW + lo5];
+      }
+    }
+    reg_pass<5, true>(x, tw, k, 5, hi5);                    // thread (a, c)
+    // transpose 1 back (c preserved): (a, c) holds b  ->  (b, c) holds a
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();
+      if (c_half == (u32)h) {
+#pragma unroll
+        for (int bb = 0; bb < 32; ++bb) lds[hi5 * T1_A + bb * 16 + cl] = x[bb];
+      }
+      __syncthreads();
+      if (c_half == (u32)h) {
+#pragma unroll
+        for (int a = 0; a < 32; ++a) x[a] = lds[a * T1_A + hi5 * 16 + cl];
+      }
+    }
+    reg_pass<5, true>(x, tw, k, 0, 0);                      // thread (b, c)
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      dst[a * 1024 + t] = csub_neg(csub_neg(shoup_lazy4(x[a], k.ninv, k.ninv_sh, k.q), k.nq2), k.nq);
+  }
+}
+
 // One launch = one phase over every (tile, poly, item).  read_src: load from
 // pb.src (first phase) else from pb.dst.  final_: reduce to [0, q) (and scale
 // by N^{-1} for the inverse) on the way out.
@@ -191,8 +351,17 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   }
 }
 
+u32 valid_polys(const PolyBatch& pb) {
+  u32 n = 0;
+  for (u32 r = 0; r < pb.npoly; ++r) n += pb.prime[r] != 0xFF;
+  return n * pb.nitems;
+}
+
 template <int LOGN, int S0, int LP, int COLS, int NT, bool INV>
 void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
+  const int kind = LP == LOGN ? (INV ? TK_NTT_ONE_INV : TK_NTT_ONE_FWD)
+                              : (S0 == 0 ? (INV ? TK_NTT_INV_A : TK_NTT_FWD_A) : (INV ? TK_NTT_INV_B : TK_NTT_FWD_B));
+  TraceScope ts(c, kind, 16.0 * (double)valid_polys(pb) * (double)(1u << LOGN));
   dim3 grid((1u << (LOGN - LP)) / COLS, pb.nitems, pb.npoly);
   hipLaunchKernelGGL((k_ntt_phase<LOGN, S0, LP, COLS, NT, INV>), grid, dim3(NT), 0, c->stream, pb, c->d_tw, c->d_pc,
                      read_src, final_);
@@ -219,6 +388,15 @@ void ntt_two_phase(he_ctx* c, const PolyBatch& ch, bool inv) {
 
 template <int LOGN>
 void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
+  if constexpr (LOGN == 15) {
+    if (c->ntt_single_pass) {
+      TraceScope ts(c, inv ? TK_NTT15_INV : TK_NTT15_FWD, 16.0 * (double)valid_polys(pb) * (double)(1u << LOGN));
+      dim3 grid(pb.nitems, pb.npoly);
+      if (!inv) hipLaunchKernelGGL(k_ntt15<false>, grid, dim3(1024), 0, c->stream, pb, c->d_tw, c->d_pc);
+      else hipLaunchKernelGGL(k_ntt15<true>, grid, dim3(1024), 0, c->stream, pb, c->d_tw, c->d_pc);
+      return;
+    }
+  }
   if constexpr (LOGN <= 13) {
     constexpr int NT = LOGN >= 12 ? 256 : 128;
     if (!inv) launch_phase<LOGN, 0, LOGN, 1, NT, false>(c, pb, 1, 1);

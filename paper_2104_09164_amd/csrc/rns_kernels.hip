@@ -263,11 +263,16 @@ inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
 
 int launch_copy_polys(he_ctx* c, const PolyBatch& pb) {
   if (!pb.nitems || !pb.npoly) return HE_OK;
+  u32 nv = 0;
+  for (u32 r = 0; r < pb.npoly; ++r) nv += pb.prime[r] != 0xFF;
+  TraceScope ts(c, TK_COPY, 2.0 * nv * pb.nitems * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_copy_polys, dim3(c->N / BS / 4, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->N);
   return ok();
 }
 
 int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
+  const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
+  TraceScope ts(c, TK_MODUP_CONV, (double)nitems * ((l + 1) + (beta * ne - (l + 1))) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_modup_conv, dim3(c->N / BS, digits_at(c, l), nitems), dim3(BS), 0, c->stream, coef, ext, c->d_pc,
                      c->d_modup_hatinv, c->d_modup_hatmod, c->N, l, c->nq, c->np, c->alpha, c->dnum);
   return ok();
@@ -275,6 +280,8 @@ int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
 
 int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& own, const u64* key, u32 galois,
                     u64* u) {
+  const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
+  TraceScope ts(c, TK_KS_INNER, ((double)nitems * beta * ne + 2.0 * beta * ne + 2.0 * nitems * ne) * (8.0 * (double)c->N));
   dim3 grid(c->N / BS, l + 1 + c->np, 1);
   if (galois != 1)
     hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
@@ -286,6 +293,7 @@ int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& o
 }
 
 int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv) {
+  TraceScope ts(c, TK_MODDOWN_CONV, (double)nitems * (2.0 * c->np + 2.0 * (l + 1)) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_moddown_conv, dim3(c->N / BS, 2, nitems), dim3(BS), 0, c->stream, u, conv, c->d_pc, c->d_moddown,
                      c->N, l, c->nq, c->np);
   return ok();
@@ -293,12 +301,19 @@ int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv) {
 
 int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv, u32 galois, const FinalArgs& fa,
                     const u64* bias) {
+  double per = 6.0 * (l + 1);                      // u and conv (2 polys each) read, 2 polys written
+  if (fa.add0[0]) per += l + 1;
+  if (fa.add1[0]) per += l + 1;
+  if (fa.acc[0]) per += 2.0 * (l + 1);
+  TraceScope ts(c, TK_KS_FINAL, ((double)nitems * per + (bias ? l + 1 : 0)) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_ks_final, dim3(c->N / BS, l + 1, nitems), dim3(BS), 0, c->stream, u, conv, fa, bias, c->d_pc,
                      c->d_moddown, c->N, c->log_n, l, c->nq, c->np, galois);
   return ok();
 }
 
 int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s) {
+  TraceScope ts(c, TK_MULTPLAIN,
+                ((double)in.n * (n1 + n2) * 2.0 * (l + 1) + (double)n1 * n2 * (l + 1)) * (8.0 * (double)c->N));
   // all giant-step sums of a thread in registers (up to 8) so every baby-step
   // ciphertext is read once per batch
   const u32 jc = n2 >= 8 ? 8 : n2;
@@ -313,32 +328,40 @@ int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, cons
 }
 
 int launch_tensor(he_ctx* c, u32 l, const Items& in, u64* d01, u64* d2) {
+  TraceScope ts(c, TK_TENSOR, (double)in.n * 5.0 * (l + 1) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_tensor, dim3(c->N / BS, l + 1, in.n), dim3(BS), 0, c->stream, in, d01, d2, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_rescale_reduce(he_ctx* c, u32 l, u32 nitems, const u64* last, u64* red) {
+  TraceScope ts(c, TK_RESCALE_REDUCE, (double)nitems * (2.0 + 2.0 * l) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_rescale_reduce, dim3(c->N / BS, l, 2 * nitems), dim3(BS), 0, c->stream, last, red, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_rescale_final(he_ctx* c, u32 l, const Items& in, const u64* red, const Items& out) {
+  TraceScope ts(c, TK_RESCALE_FINAL, (double)in.n * 6.0 * l * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_rescale_final, dim3(c->N / BS, l, 2 * in.n), dim3(BS), 0, c->stream, in, red, out, c->d_pc,
                      c->d_rescale, c->N, l, c->nq);
   return ok();
 }
 
 int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& out) {
+  TraceScope ts(c, TK_ADD, (double)a.n * 6.0 * (l + 1) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_add, dim3(c->N / BS, 2 * (l + 1), a.n), dim3(BS), 0, c->stream, a, b, out, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
+  TraceScope ts(c, TK_ADD_PLAIN, ((double)ct.n * 2.0 + 1.0) * (l + 1) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_add_plain, dim3(c->N / BS, l + 1, ct.n), dim3(BS), 0, c->stream, ct, poly, c->d_pc, c->N);
   return ok();
 }
 
 int launch_to_mont(he_ctx* c, const PolyBatch& pb) {
+  u32 nv = 0;
+  for (u32 r = 0; r < pb.npoly; ++r) nv += pb.prime[r] != 0xFF;
+  TraceScope ts(c, TK_TO_MONT, 2.0 * nv * pb.nitems * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_to_mont, dim3(c->N / BS, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->d_pc, c->N);
   return ok();
 }

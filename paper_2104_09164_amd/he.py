@@ -31,6 +31,10 @@ class _Ct(C.Structure):
     _fields_ = [("dev", C.c_void_p), ("level", C.c_uint32), ("scale", C.c_double)]
 
 
+class _TraceEntry(C.Structure):
+    _fields_ = [("kernel", C.c_char_p), ("launches", C.c_uint64), ("ms", C.c_double), ("bytes", C.c_double)]
+
+
 class _Params(C.Structure):
     _fields_ = [("log_n", C.c_uint32), ("n_q", C.c_uint32), ("q", C.POINTER(C.c_uint64)),
                 ("n_p", C.c_uint32), ("p", C.POINTER(C.c_uint64)), ("alpha", C.c_uint32)]
@@ -86,6 +90,7 @@ def lib() -> C.CDLL:
             "he_sync": (C.c_int, [vp]),
             "he_ctx_set_knob": (C.c_int, [vp, C.c_char_p, C.c_int64]),
             "he_ctx_get_knob": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int64)]),
+            "he_trace_read": (C.c_int, [vp, C.POINTER(_TraceEntry), u32, C.POINTER(u32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -100,7 +105,7 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_dense_free", "he_ct_import", "he_ct_export", "he_ct_from_coeff_dev", "he_ct_to_coeff_dev",
             "he_eval_dense", "he_square", "he_rotate", "he_rotate_hoisted", "he_rescale", "he_add",
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
-            "he_sync", "he_ctx_set_knob", "he_ctx_get_knob")
+            "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read")
 
 
 def _check(rc: int, where: str) -> None:
@@ -321,6 +326,15 @@ class Context:
         v = C.c_int64()
         _check(lib().he_ctx_get_knob(self.h, key.encode(), C.byref(v)), f"he_ctx_get_knob({key})")
         return int(v.value)
+
+    def trace_read(self) -> dict:
+        """{kernel class: (launches, ms, algorithmic bytes)} since the last read."""
+        cap = 64
+        arr = (_TraceEntry * cap)()
+        n = C.c_uint32()
+        _check(lib().he_trace_read(self.h, arr, cap, C.byref(n)), "he_trace_read")
+        return {arr[i].kernel.decode(): (int(arr[i].launches), float(arr[i].ms), float(arr[i].bytes))
+                for i in range(min(n.value, cap))}
 
     def sync(self) -> None:
         _check(lib().he_sync(self.h), "he_sync")

@@ -75,7 +75,45 @@ def test_ntt_roundtrip_and_convolution(log_n):
     ctx.ntt(bufs[:1], 0, len(primes), inverse=True)
     ctx.sync()
     assert np.array_equal(bufs[0].cpu().numpy().view(np.uint64).reshape(len(primes), pr.n), a)
+    if log_n == 15:
+        # the register-resident single-pass transform gives the same words as the two-phase one
+        ctx.set_knob("ntt_single_pass", 1)
+        x = torch.from_numpy(a.view(np.int64).copy()).to("cuda")
+        ctx.ntt([x], 0, len(primes), inverse=False)
+        ctx.sync()
+        assert np.array_equal(x.cpu().numpy().view(np.uint64).reshape(len(primes), pr.n), A)
+        ctx.ntt([x], 0, len(primes), inverse=True)
+        ctx.sync()
+        assert np.array_equal(x.cpu().numpy().view(np.uint64).reshape(len(primes), pr.n), a)
     del rng
+
+
+def test_tracer_counts_launches_and_bytes(setup10):
+    """The tracer only observes: same bits with it on, and per-class counts
+    that match the launch structure of a hoisted rotation."""
+    pr, o, keys, ctx = setup10
+    _, ct = encrypt(o, keys, pr, 31)
+    g = ctx.import_ct(ct.data, ct.level, ct.scale)
+    ctx.sync()
+    ctx.trace_read()
+    assert ctx.trace_read() == {}                                  # tracer off: nothing recorded
+    ctx.set_knob("trace", 1)
+    try:
+        out = ctx.rotate_hoisted_batch([g], [1, 7])
+        tab = ctx.trace_read()
+    finally:
+        ctx.set_knob("trace", 0)
+    for u, s in enumerate([1, 7]):
+        assert np.array_equal(ctx.export_ct(out[u]), o.rotate(ct, s, keys).data)
+    # one ModUp shared by both steps, one key switch (inner product + epilogue) per step
+    assert tab["modup_conv"][0] == 1 and tab["ks_inner"][0] == 2 and tab["ks_final"][0] == 2
+    N, l, K = pr.n, ct.level, len(pr.p)
+    beta = -(-(l + 1) // pr.alpha)
+    ne = l + 1 + K
+    # per step: the extended digits and the step's key (2 polys per digit) read, u (2 polys) written
+    assert tab["ks_inner"][2] == 2 * (beta * ne + 2 * beta * ne + 2 * ne) * N * 8
+    for name, (n, ms, by) in tab.items():
+        assert n > 0 and ms > 0 and by > 0, name
 
 
 def test_import_export_roundtrip(setup10):
