@@ -318,17 +318,19 @@ void orc_modup(void* h, const u64* x, int level, int digit, u64* out) {
   for (int t = 0; t < ne; ++t) {
     int pt = ext_prime(c, level, t); u64 qt = c.primes[pt];
     if (t >= lo && t < hi) { std::memcpy(out + t * N, x + t * N, N * sizeof(u64)); continue; }
+    std::vector<u64> hat_inv(hi - lo, 1), hat_t(hi - lo, 1);   // (Q_D/q_i)^{-1} mod q_i, (Q_D/q_i) mod t
+    for (int i = lo; i < hi; ++i) {
+      u64 qi = c.primes[i];
+      for (int i2 = lo; i2 < hi; ++i2) if (i2 != i) {
+        hat_inv[i - lo] = mulmod(hat_inv[i - lo], invmod(c.primes[i2] % qi, qi), qi);
+        hat_t[i - lo] = mulmod(hat_t[i - lo], c.primes[i2] % qt, qt);
+      }
+    }
     for (size_t k = 0; k < N; ++k) {
       u64 acc = 0;
       for (int i = lo; i < hi; ++i) {
-        u64 qi = c.primes[i];
-        u64 hat_inv = 1, hat_t = 1;                  // (Q_D/q_i)^{-1} mod q_i, (Q_D/q_i) mod t
-        for (int i2 = lo; i2 < hi; ++i2) if (i2 != i) {
-          hat_inv = mulmod(hat_inv, invmod(c.primes[i2] % qi, qi), qi);
-          hat_t = mulmod(hat_t, c.primes[i2] % qt, qt);
-        }
-        u64 v = mulmod(x[i * N + k], hat_inv, qi);
-        acc = addmod(acc, mulmod(v % qt, hat_t, qt), qt);
+        u64 v = mulmod(x[i * N + k], hat_inv[i - lo], c.primes[i]);
+        acc = addmod(acc, mulmod(v % qt, hat_t[i - lo], qt), qt);
       }
       out[t * N + k] = acc;
     }
@@ -342,18 +344,20 @@ void orc_moddown(void* h, const u64* y, int level, u64* out) {
   for (int i = 0; i <= level; ++i) {
     u64 qi = c.primes[i];
     u64 Pinv = 1; for (int k = 0; k < K; ++k) Pinv = mulmod(Pinv, invmod(c.primes[c.nq + k] % qi, qi), qi);
+    std::vector<u64> hat_inv(K, 1), hat_q(K, 1);   // (P/p_k)^{-1} mod p_k, (P/p_k) mod q_i
+    for (int k = 0; k < K; ++k) {
+      u64 pk = c.primes[c.nq + k];
+      for (int k2 = 0; k2 < K; ++k2) if (k2 != k) {
+        u64 p2 = c.primes[c.nq + k2];
+        hat_inv[k] = mulmod(hat_inv[k], invmod(p2 % pk, pk), pk);
+        hat_q[k] = mulmod(hat_q[k], p2 % qi, qi);
+      }
+    }
     for (size_t n = 0; n < N; ++n) {
       u64 conv = 0;
       for (int k = 0; k < K; ++k) {
-        u64 pk = c.primes[c.nq + k];
-        u64 hat_inv = 1, hat_q = 1;
-        for (int k2 = 0; k2 < K; ++k2) if (k2 != k) {
-          u64 p2 = c.primes[c.nq + k2];
-          hat_inv = mulmod(hat_inv, invmod(p2 % pk, pk), pk);
-          hat_q = mulmod(hat_q, p2 % qi, qi);
-        }
-        u64 v = mulmod(y[(size_t)(level + 1 + k) * N + n], hat_inv, pk);
-        conv = addmod(conv, mulmod(v % qi, hat_q, qi), qi);
+        u64 v = mulmod(y[(size_t)(level + 1 + k) * N + n], hat_inv[k], c.primes[c.nq + k]);
+        conv = addmod(conv, mulmod(v % qi, hat_q[k], qi), qi);
       }
       out[i * N + n] = mulmod(submod(y[i * N + n], conv, qi), Pinv, qi);
     }
