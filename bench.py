@@ -1,20 +1,24 @@
 """Benchmark: encrypted inferences/s of the small dense net, batched vs plain.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--large-batch B]
-                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-cpu]
+                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-cpu]
 
 One step = one batched encrypted inference of B requests through the whole
-small network (N=2^15; dense 1024->128 -> rescale -> square -> rescale ->
-dense 128->2 -> rescale; every dense layer = hoisted baby-step rotations,
+small network (N=2^15; dense 1024->128 with 32 baby steps -> rescale ->
+square -> rescale -> dense 128->2 -> rescale; every dense layer = hoisted
+baby-step rotations,
 MultPlain inner sums, giant-step and rotate-and-sum key switches, bias),
 replayed from a captured HIP graph, inputs resident in HBM.  `value` is that
 leg's inferences/s.  Reported beside it, in the same JSON line:
   * plain one-request-at-a-time inferences/s and p50/p99 latency;
+  * the small net again with the autotuner's baby-step counts;
   * the same two legs for the large network (N=2^16, 4096->256->64->2);
   * serving: Poisson arrivals at several rates, 70% small / 30% large
     requests, continuous batching, p50/p99 from arrival to exported result;
   * the NTT micro-benchmark (64 ciphertexts x 2 x 24 limbs at N=2^16,
     forward + inverse) in algorithmic HBM GB/s;
+  * the key-switch micro-benchmark (the same 64 ciphertexts' shape, dnum = 3,
+    32 random rotation steps) in key switches/s, with its kernel classes;
   * the roofline of the step's dominant kernel class: the same step run
     eagerly with the library tracer on (HIP events around every launch on the
     library stream, algorithmic bytes per launch), plus the NTT leg's;
@@ -126,6 +130,56 @@ def ntt_leg(reps=10):
             "fwd_inv_gbs": 2 * alg_bytes / (f + i) / 1e6, "alg_bytes_per_transform": alg_bytes}
 
 
+def ks_leg(reps=3, items=64, n_steps=32):
+    """Kernel micro-benchmark, key switching: 64 ciphertexts at N=2^16 with 24
+    limbs of 50-bit primes, hybrid key switching with dnum = 3 (8 special
+    primes), rotated by each of 32 random steps (every rotation a full key
+    switch: ModUp, inner product, ModDown).  Rotation keys are resident
+    (32 keys x 3 digits x 2 x 32 limbs x 2^16 words = 3.2 GB)."""
+    import torch
+    from paper_2104_09164_amd import he, synth
+    log_n, limbs, K = 16, 24, 8
+    q, p = he.prime_chain(log_n, [50] * limbs, [50] * K)
+    ctx = he.Context(log_n, q, p, K)
+    N = 1 << log_n
+    dnum = -(-limbs // K)
+    ctx.bind(items, 1, 1)
+    steps = synth.rotation_steps_random(n_steps, N // 2)
+    log(f"ks leg: {len(steps)} rotation keys, dnum={dnum}, {items} ciphertexts")
+    rot = {s: residues(q + p, N, (dnum, 2), 500 + i) for i, s in enumerate(steps)}
+    ctx.load_keys(None, rot)
+    del rot
+    qt = torch.tensor(q, dtype=torch.int64, device="cuda").view(1, limbs, 1)
+    g = torch.Generator(device="cuda").manual_seed(13)
+    cts = []
+    for _ in range(items):
+        ct = ctx.new_ct(limbs - 1, 2.0 ** 50)
+        ct.buf.view(2, limbs, N).copy_(torch.randint(0, 2 ** 62, (2, limbs, N), device="cuda", generator=g,
+                                                     dtype=torch.int64) % qt)
+        cts.append(ct)
+    outs = [ctx.new_ct(limbs - 1) for _ in range(items)]
+
+    def run():
+        for st in steps:
+            ctx.rotate_hoisted_batch(cts, [st], outs)
+    run()
+    torch.cuda.synchronize()
+    t = time_events(run, reps)
+    ms = float(np.median(t))
+    ctx.trace_read()
+    ctx.set_knob("trace", 1)
+    run()
+    tab = ctx.trace_read()
+    ctx.set_knob("trace", 0)
+    res = {"workload": (f"{items} ct x N=2^16, 24 x 50-bit limbs, dnum={dnum} (8 x 50-bit special primes), "
+                        f"{n_steps} random rotation steps, one full key switch per (ct, step)"),
+           "key_switches_per_s": items * n_steps / (ms * 1e-3), "ms_per_pass": ms,
+           "roofline": step_roofline(tab, 1)}
+    del ctx, cts, outs
+    torch.cuda.synchronize()
+    return res
+
+
 def ntt_roofline(nt):
     """Dominant kernel: the forward NTT, one he_ntt call = one phase-A and one
     phase-B launch over 1536 limb-polys of 2^16 words.  Algorithmic bytes =
@@ -193,13 +247,13 @@ def cpu_baseline(plan, budget_s=20.0):
 
 
 KERNEL_LABEL = {
-    "ntt_fwd_a": "forward NTT, phase A (column transforms)",
-    "ntt_fwd_b": "forward NTT, phase B (row transforms)",
-    "ntt_inv_b": "inverse NTT, phase B (row transforms)",
-    "ntt_inv_a": "inverse NTT, phase A (column transforms, N^-1)",
+    "ntt_fwd_phaseA": "forward NTT, phase A (column transforms)",
+    "ntt_fwd_phaseB": "forward NTT, phase B (row transforms)",
+    "ntt_inv_phaseB": "inverse NTT, phase B (row transforms)",
+    "ntt_inv_phaseA": "inverse NTT, phase A (column transforms, N^-1)",
     "ks_inner": "key-switch inner product (eval-key x extended digits, automorphism gather)",
     "ks_final": "key-switch epilogue ((u - conv) P^-1 + sigma(c0) + accumulators)",
-    "multplain": "MultPlain inner sums over baby-step ciphertexts",
+    "multplain_acc": "MultPlain inner sums over baby-step ciphertexts",
 }
 
 
@@ -255,15 +309,16 @@ def step_roofline(tab, steps):
                         for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])}}
 
 
-def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=True):
+def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=True, tuned_n1=True, trace=True):
     """Batched (graph replay) and plain (one request at a time) legs of one preset.
     A committed tuning file (paper_2104_09164_amd/tuning/<gfx>_<name>.json)
-    supplies the execution knobs and the per-layer baby-step counts."""
+    supplies the execution knobs and, with tuned_n1, the per-layer baby-step
+    counts (else the preset's)."""
     import torch
     from paper_2104_09164_amd import netplan, tune
     tuned = tune.load(name) if use_tuning else None
     shapes = None
-    if tuned and tuned.get("n1"):
+    if tuned and tuned.get("n1") and tuned_n1:
         shapes = [(m, n, n1) for (m, n, _), n1 in zip(netplan.PRESETS[name]["shapes"], tuned["n1"])]
     plan = netplan.preset_plan(name, shapes)
     log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}, "
@@ -300,10 +355,11 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
                         f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
                         + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers) + ", x^2 between"),
            "ops_per_inference": plan.op_counts(),
-           "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1")} if tuned else None}
+           "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1") if tuned_n1 else None} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
-    log(f"{name}: traced eager pass")
-    res["trace"] = trace_steps(ctx, runner, batch, steps)
+    if trace:
+        log(f"{name}: traced eager pass")
+        res["trace"] = trace_steps(ctx, runner, batch, steps)
     return plan, ctx, runner, res
 
 
@@ -369,6 +425,8 @@ def main():
     ap.add_argument("--no-tuning", action="store_true", help="ignore committed tuning files")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ntt", action="store_true")
+    ap.add_argument("--no-ks", action="store_true")
+    ap.add_argument("--no-tuned-split", action="store_true", help="skip the small-net leg with tuned baby steps")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--roofline-only", action="store_true",
@@ -391,15 +449,16 @@ def main():
         from paper_2104_09164_amd import netplan, tune
         calibration_copy()
         tuned = tune.load("cfg3")
-        shapes = [(m, n, n1) for (m, n, _), n1 in zip(netplan.PRESETS["cfg3"]["shapes"], tuned["n1"])]
-        plan = netplan.preset_plan("cfg3", shapes)
+        plan = netplan.preset_plan("cfg3")
         ctx, runner = setup(plan, args.batch)
         tune.apply_knobs(ctx, tuned)
         tab = trace_steps(ctx, runner, args.batch, args.steps)
         print(json.dumps({"roofline": step_roofline(tab, args.steps)}), flush=True)
         return 0
+    # headline: the preset's BSGS split (32 baby steps in the first layer), tuned execution knobs
     plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
-                                            graph=not args.no_graph, use_tuning=not args.no_tuning)
+                                            graph=not args.no_graph, use_tuning=not args.no_tuning,
+                                            tuned_n1=False)
     runner_layers["small"] = run3.layers
     out = {"metric": METRIC, "value": small["inferences_per_s"], "unit": "inferences/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": small["ms_per_step"],
@@ -414,6 +473,13 @@ def main():
            "plain_inferences_per_s": small["plain_inferences_per_s"],
            "batched_over_plain": small["batched_over_plain"]}
     nets = {"small": (plan3, ctx3, args.batch)}
+    if not args.no_tuning and not args.no_tuned_split:
+        # same workload with the autotuner's baby-step counts
+        _, ctx3t, _, small_t = network_legs("cfg3", args.batch, args.steps, 1, 0, graph=not args.no_graph,
+                                            tuned_n1=True, trace=False)
+        out["small_net_tuned_split"] = {k: small_t[k] for k in ("inferences_per_s", "ms_per_step", "batched_p50_ms",
+                                                                "batched_p99_ms", "workload", "tuning")}
+        del ctx3t, small_t
     if not args.no_large:
         large_steps = max(3, args.steps // 2)
         plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, large_steps, 1,
@@ -433,6 +499,9 @@ def main():
         nt = ntt_leg()
         out["ntt"] = nt
         out["ntt_roofline"] = ntt_roofline(nt)
+    if not args.no_ks:
+        log("key-switch leg")
+        out["key_switch"] = ks_leg()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(plan3)

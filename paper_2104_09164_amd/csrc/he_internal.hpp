@@ -37,7 +37,8 @@ struct PolyBatch {
   u64* src[HE_MAXB];
   u64* dst[HE_MAXB];
   u32 src_off, dst_off, npoly, nitems;
-  uint8_t prime[HE_MAX_POLYS];
+  uint8_t prime[HE_MAX_POLYS];   // prime index of poly row r; 0xFF = skip the row
+  uint8_t row[HE_MAX_POLYS];     // NTT launches only: grid row -> poly row (rows compacted)
 };
 
 // Kernel classes of the tracer (he_trace_read aggregates per class).

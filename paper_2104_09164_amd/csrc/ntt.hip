@@ -201,11 +201,11 @@ __global__ void __launch_bounds__(1024) k_ntt15(PolyBatch pb, const u64* __restr
   __shared__ u64 lds[32 * T1_A > 16 * T2_SLAB ? 32 * T1_A : 16 * T2_SLAB];
   const u32 b_item = blockIdx.x, r = blockIdx.y;
   const u32 pr = pb.prime[r];
-  if (pr == 0xFF) return;
   const PrimeConst k = pc[pr];
   const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
-  const u64* src = pb.src[b_item] + (size_t)(pb.src_off + r) * N;
-  u64* dst = pb.dst[b_item] + (size_t)(pb.dst_off + r) * N;
+  const u32 row = pb.row[r];
+  const u64* src = pb.src[b_item] + (size_t)(pb.src_off + row) * N;
+  u64* dst = pb.dst[b_item] + (size_t)(pb.dst_off + row) * N;
   const u32 t = threadIdx.x, hi5 = t >> 5, lo5 = t & 31;
   const u32 c_half = lo5 >> 4, cl = lo5 & 15, a_half = t >> 9, al = hi5 & 15;
   u64 x[32];
@@ -310,13 +310,13 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   // polynomial keep tile t on XCD t mod 8, which then needs 1/8 of the table.
   const u32 tile = blockIdx.x, b = blockIdx.y, r = blockIdx.z;
   const u32 pr = pb.prime[r];
-  if (pr == 0xFF) return;
   const u32 N = 1u << LOGN;
   const PrimeConst k = pc[pr];
   const u64 q = k.q;
   const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
-  const u64* src = read_src ? pb.src[b] + (size_t)(pb.src_off + r) * N : pb.dst[b] + (size_t)(pb.dst_off + r) * N;
-  u64* dst = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
+  const u32 row = pb.row[r];
+  const u64* src = read_src ? pb.src[b] + (size_t)(pb.src_off + row) * N : pb.dst[b] + (size_t)(pb.dst_off + row) * N;
+  u64* dst = pb.dst[b] + (size_t)(pb.dst_off + row) * N;
   const u32 sub0 = tile * COLS;
   // Tile copy in 16-byte pairs (COLS and 2^LP are even, so pairs never straddle a row).
   for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
@@ -351,11 +351,7 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   }
 }
 
-u32 valid_polys(const PolyBatch& pb) {
-  u32 n = 0;
-  for (u32 r = 0; r < pb.npoly; ++r) n += pb.prime[r] != 0xFF;
-  return n * pb.nitems;
-}
+u32 valid_polys(const PolyBatch& pb) { return pb.npoly * pb.nitems; }   // rows are compacted
 
 template <int LOGN, int S0, int LP, int COLS, int NT, bool INV>
 void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
@@ -411,9 +407,10 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
     for (u32 r0 = 0; r0 < pb.npoly; r0 += per) {
       PolyBatch ch = pb;
       ch.npoly = std::min(per, pb.npoly - r0);
-      ch.src_off = pb.src_off + r0;
-      ch.dst_off = pb.dst_off + r0;
-      for (u32 r = 0; r < ch.npoly; ++r) ch.prime[r] = pb.prime[r0 + r];
+      for (u32 r = 0; r < ch.npoly; ++r) {
+        ch.prime[r] = pb.prime[r0 + r];
+        ch.row[r] = pb.row[r0 + r];
+      }
       // tile width: sub-transforms per workgroup (knob ntt_cols)
       if (c->ntt_cols == 8) ntt_two_phase<LOGN, 8>(c, ch, inv);
       else if (c->ntt_cols == 32) ntt_two_phase<LOGN, 32>(c, ch, inv);
@@ -424,7 +421,17 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
 
 }  // namespace
 
-int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse) {
+int launch_ntt(he_ctx* c, const PolyBatch& in, bool inverse) {
+  // Compact the grid to the rows that are transformed: skipped rows would
+  // otherwise occupy workgroup slots that exit at once.
+  PolyBatch pb = in;
+  u32 n = 0;
+  for (u32 r = 0; r < in.npoly; ++r)
+    if (in.prime[r] != 0xFF) {
+      pb.prime[n] = in.prime[r];
+      pb.row[n++] = (uint8_t)r;
+    }
+  pb.npoly = n;
   if (pb.nitems == 0 || pb.npoly == 0) return HE_OK;
   switch (c->log_n) {
     case 10: ntt_dispatch<10>(c, pb, inverse); break;

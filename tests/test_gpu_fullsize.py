@@ -1,8 +1,12 @@
-"""Full-size parity in the benchmark's launch configuration (graph replay of the
-batched network with the committed tuned plan).
+"""Full-size parity in the benchmark's launch configurations.
 
-cfg3 (N = 2^15, the benchmark's `value` workload): one request's whole
-network, bit for bit against the oracle, plus FP64 tolerance.
+cfg3 (N = 2^15, the benchmark's `value` workload): whole network by graph
+replay, bit for bit against the oracle plus FP64 tolerance, with the preset
+BSGS split (the headline leg) and with the autotuner's split.
+cfg2 (N = 2^16, 24 x 50-bit limbs, dnum = 3: the key-switch micro-benchmark):
+batches of 64 ciphertexts rotated one random step per call, as timed; the
+oracle's rotation of the one encrypted ciphertext in the batch is compared bit
+for bit (sampled outputs), and its decryption against the rotated message.
 cfg4 (N = 2^16): the oracle's full network is minutes of CPU work, so the
 property checked at full size is the plaintext one: decrypted logits within
 2^-12 of the FP64 network and the same predicted class, for two requests
@@ -17,13 +21,13 @@ from paper_2104_09164_amd import netplan, synth, tune
 pytestmark = pytest.mark.gpu
 
 
-def run_network(name, requests, check_bits):
+def run_network(name, requests, check_bits, tuned_split=True):
     import torch
     from paper_2104_09164_amd import he
     from paper_2104_09164_amd.batch import NetworkRunner
     c = netplan.PRESETS[name]
     tuned = tune.load(name, "gfx950")
-    n1s = tuned["n1"] if tuned else [s[2] for s in c["shapes"]]
+    n1s = tuned["n1"] if tuned and tuned_split else [s[2] for s in c["shapes"]]
     shapes = [(m, n, n1) for (m, n, _), n1 in zip(c["shapes"], n1s)]
     pr = params.preset(name)
     o = ckks.Oracle(pr)
@@ -66,8 +70,49 @@ def run_network(name, requests, check_bits):
 
 
 def test_cfg3_network_full_size_bit_exact():
-    run_network("cfg3", [0, 1], check_bits=True)
+    run_network("cfg3", [0, 1], check_bits=True, tuned_split=False)
+
+
+def test_cfg3_network_tuned_split_bit_exact():
+    run_network("cfg3", [2], check_bits=True, tuned_split=True)
 
 
 def test_cfg4_network_full_size_fp64():
     run_network("cfg4", [0, 1], check_bits=False)
+
+
+def test_cfg2_key_switch_batch_full_size():
+    import torch
+    from paper_2104_09164_amd import he
+    pr = params.preset("cfg2")
+    o = ckks.Oracle(pr)
+    steps = synth.rotation_steps_random(32, pr.slots)[:2]
+    print(f"[fullsize] cfg2: keygen for steps {steps}", flush=True)
+    keys = o.keygen(synth.SEED_KEYS, steps, relin=False)
+    x = synth.request_input(pr.slots, 0)
+    ct = o.encrypt(x, keys.pk, synth.request_seed(0))
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    B = 64
+    ctx.bind(B, 1, 1)
+    ctx.load_keys(None, keys.rot)
+    L1, N = len(pr.q), pr.n
+    qt = torch.tensor(pr.q, dtype=torch.int64, device="cuda").view(1, L1, 1)
+    g = torch.Generator(device="cuda").manual_seed(13)
+    cts = [ctx.import_ct(ct.data, ct.level, ct.scale)]
+    for _ in range(B - 1):
+        c = ctx.new_ct(pr.L, ct.scale)
+        c.buf.view(2, L1, N).copy_(torch.randint(0, 2 ** 62, (2, L1, N), device="cuda", generator=g,
+                                                 dtype=torch.int64) % qt)
+        cts.append(c)
+    outs = [ctx.new_ct(pr.L) for _ in range(B)]
+    for s in steps:
+        ctx.rotate_hoisted_batch(cts, [s], outs)
+        got = ctx.export_ct(outs[0])
+        print(f"[fullsize] cfg2: oracle rotation by {s}", flush=True)
+        want = o.rotate(ct, s, keys)
+        assert np.array_equal(got, want.data), f"rotation by {s} differs from the oracle"
+        y = o.decrypt_decode(want, keys.sk)
+        assert np.max(np.abs(y - np.roll(x, -s))) < 2.0 ** -20
+        # a random ciphertext of the batch equals its own single-ciphertext rotation
+        single = ctx.rotate(cts[37], s)
+        assert np.array_equal(ctx.export_ct(single), ctx.export_ct(outs[37]))
