@@ -253,6 +253,8 @@ KERNEL_LABEL = {
     "ntt_inv_phaseA": "inverse NTT, phase A (column transforms, N^-1)",
     "ks_inner": "key-switch inner product (eval-key x extended digits, automorphism gather)",
     "ks_final": "key-switch epilogue ((u - conv) P^-1 + sigma(c0) + accumulators)",
+    "ks_inner_steps": "key-switch inner product, all hoisted steps of a batch in one launch",
+    "ks_final_steps": "key-switch epilogue, all hoisted steps of a batch in one launch",
     "multplain_acc": "MultPlain inner sums over baby-step ciphertexts",
 }
 

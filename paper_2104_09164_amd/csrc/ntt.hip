@@ -36,6 +36,17 @@ __host__ __device__ constexpr int pass_start(int lp, int p) {
   return s;
 }
 
+__device__ __forceinline__ const u64* item_src(const PolyBatch& pb, u32 b) {
+  return pb.stride ? pb.src[0] + (size_t)b * pb.stride : pb.src[b];
+}
+__device__ __forceinline__ u64* item_dst(const PolyBatch& pb, u32 b) {
+  return pb.stride ? pb.dst[0] + (size_t)b * pb.stride : pb.dst[b];
+}
+
+// Primes below 2^57 take the forward butterflies without the per-stage
+// conditional subtraction (room for the lazy bound growth up to N = 2^17).
+constexpr u64 kLazyQ = 1ull << 57;
+
 // LDS padding: one spare word every 16 to spread strided accesses over banks.
 __device__ __forceinline__ u32 pidx(u32 i) { return i + (i >> 4); }
 
@@ -54,7 +65,37 @@ struct Phase {
     return (i / COLS) * (1u << (LOGN - LP)) + sub0 + (i % COLS);
   }
 
-  template <int U, int RB>
+  // Forward stages S0+U .. S0+U+RB-1 on one radix-2^RB group.  CSUB-free
+  // form (NOCSUB, primes below kLazyQ): X is not brought below 4q, so the
+  // bound grows by 4q per stage, from below 8q at the input to below
+  // (8 + 4 logN) q <= 76 q < 2^64 after the last stage; the final pass
+  // reduces it.  Otherwise values stay below 8q between stages.
+  template <int U, int RB, bool NOCSUB>
+  __device__ static __forceinline__ void fwd_stages(u64 (&x)[1 << RB], const ulonglong2* __restrict__ tw,
+                                                    const PrimeConst& k, u32 hi, u32 kt) {
+    constexpr int R = 1 << RB;
+    const u64 q4 = 4 * k.q;
+#pragma unroll
+    for (int uu = 0; uu < RB; ++uu) {
+      const int s = S0 + U + uu;
+      const int half = R >> (uu + 1);
+#pragma unroll
+      for (int blk = 0; blk < (1 << uu); ++blk) {
+        const u32 ti = (1u << s) + (hi << (U + uu)) + (kt << uu) + blk;
+        const ulonglong2 wp = tw[ti];
+#pragma unroll
+        for (int e = 0; e < half; ++e) {
+          const int m0 = blk * 2 * half + e, m1 = m0 + half;
+          const u64 X = NOCSUB ? x[m0] : csub_neg(x[m0], k.nq4);     // < 4q (CSUB form)
+          const u64 S = add_shoup4(X, x[m1], wp.x, wp.y, k.nq);      // X + T, T < 4q
+          x[m0] = S;
+          x[m1] = 2 * X + q4 - S;                                   // X + 4q - T > 0 (mod 2^64 wrap exact)
+        }
+      }
+    }
+  }
+
+  template <int U, int RB, bool NOCSUB>
   __device__ static __forceinline__ void pass(u64* lds, const ulonglong2* __restrict__ tw, const PrimeConst& k,
                                               u32 sub0) {
     const u64 q = k.q;
@@ -76,24 +117,7 @@ struct Phase {
       for (int m = 0; m < R; ++m) x[m] = lds[pidx(local(col, kt * (R * KL) + m * KL + kl))];
       const u64 q4 = 4 * q;
       if (!INV) {
-#pragma unroll
-        for (int uu = 0; uu < RB; ++uu) {
-          const int s = S0 + U + uu;
-          const int half = R >> (uu + 1);
-#pragma unroll
-          for (int blk = 0; blk < (1 << uu); ++blk) {
-            const u32 ti = (1u << s) + (hi << (U + uu)) + (kt << uu) + blk;
-            const ulonglong2 wp = tw[ti];
-#pragma unroll
-            for (int e = 0; e < half; ++e) {
-              const int m0 = blk * 2 * half + e, m1 = m0 + half;
-              const u64 X = csub_neg(x[m0], k.nq4);                      // < 4q
-              const u64 S = add_shoup4(X, x[m1], wp.x, wp.y, k.nq);      // X + T < 8q
-              x[m0] = S;
-              x[m1] = 2 * X + q4 - S;                                   // X + 4q - T in (0, 8q)
-            }
-          }
-        }
+        fwd_stages<U, RB, NOCSUB>(x, tw, k, hi, kt);
       } else {
 #pragma unroll
         for (int uu = RB - 1; uu >= 0; --uu) {
@@ -118,20 +142,62 @@ struct Phase {
     }
   }
 
-  template <int P>
+  template <int P, bool NOCSUB>
   __device__ static __forceinline__ void passes_fwd(u64* lds, const ulonglong2* tw, const PrimeConst& k, u32 sub0) {
     if constexpr (P < npasses(LP)) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, k, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P), NOCSUB>(lds, tw, k, sub0);
       __syncthreads();
-      passes_fwd<P + 1>(lds, tw, k, sub0);
+      passes_fwd<P + 1, NOCSUB>(lds, tw, k, sub0);
     }
   }
   template <int P>
   __device__ static __forceinline__ void passes_inv(u64* lds, const ulonglong2* tw, const PrimeConst& k, u32 sub0) {
     if constexpr (P >= 0) {
-      pass<pass_start(LP, P), pass_bits(LP, P)>(lds, tw, k, sub0);
+      pass<pass_start(LP, P), pass_bits(LP, P), false>(lds, tw, k, sub0);
       __syncthreads();
       passes_inv<P - 1>(lds, tw, k, sub0);
+    }
+  }
+
+  // Tile in (16-byte pairs; COLS and 2^LP are even, so pairs never straddle
+  // a row), the phase's stages, tile out.  final_: reduce to [0, q) (and
+  // scale by N^{-1} for the inverse) on the way out.
+  template <bool NOCSUB>
+  __device__ static __forceinline__ void body(u64* lds, const u64* __restrict__ src, u64* __restrict__ dst,
+                                              const ulonglong2* __restrict__ tw, const PrimeConst& k, u32 sub0,
+                                              int final_) {
+    const u64 q = k.q;
+    for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+      const ulonglong2 v = *(const ulonglong2*)(src + gaddr(sub0, i));
+      lds[pidx(i)] = v.x;
+      lds[pidx(i + 1)] = v.y;
+    }
+    __syncthreads();
+    if (!INV) passes_fwd<0, NOCSUB>(lds, tw, k, sub0);
+    else passes_inv<npasses(LP) - 1>(lds, tw, k, sub0);
+    ulonglong2 v;
+    if (final_) {
+      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+        const u64 a = lds[pidx(i)], b = lds[pidx(i + 1)];
+        if (INV) {
+          v.x = csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
+          v.y = csub_neg(csub_neg(shoup_lazy4(b, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
+        } else if (NOCSUB) {
+          // below 76q: Shoup product by 1 (companion floor(2^64/q)) -> [0, 4q), then two steps
+          v.x = csub_neg(csub_neg(shoup_lazy4(a, 1, k.mu, q), k.nq2), k.nq);
+          v.y = csub_neg(csub_neg(shoup_lazy4(b, 1, k.mu, q), k.nq2), k.nq);
+        } else {
+          v.x = csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
+          v.y = csub_neg(csub_neg(csub_neg(b, k.nq4), k.nq2), k.nq);
+        }
+        *(ulonglong2*)(dst + gaddr(sub0, i)) = v;
+      }
+    } else {
+      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+        v.x = lds[pidx(i)];
+        v.y = lds[pidx(i + 1)];
+        *(ulonglong2*)(dst + gaddr(sub0, i)) = v;
+      }
     }
   }
 };
@@ -204,8 +270,8 @@ __global__ void __launch_bounds__(1024) k_ntt15(PolyBatch pb, const u64* __restr
   const PrimeConst k = pc[pr];
   const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
   const u32 row = pb.row[r];
-  const u64* src = pb.src[b_item] + (size_t)(pb.src_off + row) * N;
-  u64* dst = pb.dst[b_item] + (size_t)(pb.dst_off + row) * N;
+  const u64* src = item_src(pb, b_item) + (size_t)(pb.src_off + row) * N;
+  u64* dst = item_dst(pb, b_item) + (size_t)(pb.dst_off + row) * N;
   const u32 t = threadIdx.x, hi5 = t >> 5, lo5 = t & 31;
   const u32 c_half = lo5 >> 4, cl = lo5 & 15, a_half = t >> 9, al = hi5 & 15;
   u64 x[32];
@@ -315,40 +381,13 @@ __global__ void __launch_bounds__(NT) k_ntt_phase(PolyBatch pb, const u64* __res
   const u64 q = k.q;
   const ulonglong2* tw = (const ulonglong2*)(tw_all + (size_t)pr * 4 * N + (INV ? 2 * N : 0));
   const u32 row = pb.row[r];
-  const u64* src = read_src ? pb.src[b] + (size_t)(pb.src_off + row) * N : pb.dst[b] + (size_t)(pb.dst_off + row) * N;
-  u64* dst = pb.dst[b] + (size_t)(pb.dst_off + row) * N;
+  u64* dst = item_dst(pb, b) + (size_t)(pb.dst_off + row) * N;
+  const u64* src = read_src ? item_src(pb, b) + (size_t)(pb.src_off + row) * N : dst;
   const u32 sub0 = tile * COLS;
-  // Tile copy in 16-byte pairs (COLS and 2^LP are even, so pairs never straddle a row).
-  for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-    const ulonglong2 v = *(const ulonglong2*)(src + Ph::gaddr(sub0, i));
-    lds[pidx(i)] = v.x;
-    lds[pidx(i + 1)] = v.y;
-  }
-  __syncthreads();
-  if (!INV) Ph::template passes_fwd<0>(lds, tw, k, sub0);
-  else Ph::template passes_inv<npasses(LP) - 1>(lds, tw, k, sub0);
-  ulonglong2 v;
-  if (final_) {
-    if (!INV) {
-      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-        v.x = csub_neg(csub_neg(csub_neg(lds[pidx(i)], k.nq4), k.nq2), k.nq);
-        v.y = csub_neg(csub_neg(csub_neg(lds[pidx(i + 1)], k.nq4), k.nq2), k.nq);
-        *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
-      }
-    } else {
-      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-        v.x = csub_neg(csub_neg(shoup_lazy4(lds[pidx(i)], k.ninv, k.ninv_sh, q), k.nq2), k.nq);
-        v.y = csub_neg(csub_neg(shoup_lazy4(lds[pidx(i + 1)], k.ninv, k.ninv_sh, q), k.nq2), k.nq);
-        *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
-      }
-    }
-  } else {
-    for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-      v.x = lds[pidx(i)];
-      v.y = lds[pidx(i + 1)];
-      *(ulonglong2*)(dst + Ph::gaddr(sub0, i)) = v;
-    }
-  }
+  // the whole body is specialised on the butterfly form, so no load is
+  // shared (and hoisted) across the two
+  if (!INV && q < kLazyQ) Ph::template body<true>(lds, src, dst, tw, k, sub0, final_);
+  else Ph::template body<false>(lds, src, dst, tw, k, sub0, final_);
 }
 
 u32 valid_polys(const PolyBatch& pb) { return pb.npoly * pb.nitems; }   // rows are compacted

@@ -14,6 +14,9 @@ struct WS {
   u64 *rtmp, *coef, *ext, *u, *conv, *d01, *d2, *red, *baby, *giant, *z0, *z1;
 };
 
+// Rotation steps per step-batched key switch: the baby steps of the widest layer.
+u32 ks_group(u32 n1) { return n1 > 2 ? std::min<u32>(n1 - 1, HE_MAX_STEPS) : 1; }
+
 size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   const size_t N = c->N, L1 = c->nq, E = c->nq + c->np;
   const size_t csz = 2 * L1 * N;
@@ -27,8 +30,10 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   take(&x.rtmp, B * csz);
   take(&x.coef, B * L1 * N);
   take(&x.ext, B * c->dnum * E * N);
-  take(&x.u, B * 2 * E * N);
-  take(&x.conv, B * csz);
+  // u and conv hold every step of one step-batched key switch (G steps of B items)
+  const size_t G = ks_group(n1);
+  take(&x.u, G * B * 2 * E * N);
+  take(&x.conv, G * B * csz);
   take(&x.d01, B * csz);
   take(&x.d2, B * L1 * N);
   take(&x.red, B * csz);
@@ -122,6 +127,33 @@ int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key
   return launch_ks_final(c, l, B, w.u, w.conv, galois, fa, bias);
 }
 
+// S rotation steps of the same B items (digits of their c1 already in w.ext
+// from one ModUp): one launch per stage for all S B key switches.
+int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
+             const OutMap& om) {
+  const size_t N = c->N;
+  const u32 ne = l + 1 + c->np;
+  Items own;
+  own.n = B;
+  for (u32 b = 0; b < B; ++b) own.p[b] = c1[b];
+  int rc = launch_ks_inner_steps(c, l, B, S, w.ext, own, keys, w.u);
+  if (rc) return rc;
+  PolyBatch pi = batch_of(S * B);
+  pi.npoly = 2 * ne;
+  pi.src[0] = pi.dst[0] = w.u;
+  pi.stride = (size_t)2 * ne * N;
+  for (u32 r = 0; r < 2 * ne; ++r) pi.prime[r] = (r % ne) > l ? (uint8_t)ext_prime(c, l, r % ne) : 0xFF;
+  if ((rc = launch_ntt(c, pi, true))) return rc;
+  if ((rc = launch_moddown_conv(c, l, S * B, w.u, w.conv))) return rc;
+  PolyBatch pf = batch_of(S * B);
+  pf.npoly = 2 * (l + 1);
+  pf.src[0] = pf.dst[0] = w.conv;
+  pf.stride = (size_t)2 * (l + 1) * N;
+  for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
+  if ((rc = launch_ntt(c, pf, false))) return rc;
+  return launch_ks_final_steps(c, l, B, S, w.u, w.conv, keys, add0, om);
+}
+
 FinalArgs no_final() {
   FinalArgs fa;
   std::memset(&fa, 0, sizeof(fa));
@@ -191,22 +223,36 @@ int he_rotate_hoisted_batch(he_ctx* c, uint32_t n, const he_ct* in, uint32_t n_s
   u64* c1[HE_MAXB];
   for (u32 b = 0; b < n; ++b) c1[b] = in[b].dev + (size_t)(l + 1) * N;
   if (need_modup && (rc = modup(c, l, n, c1, w))) return rc;
+  Items add0;
+  add0.n = n;
+  for (u32 b = 0; b < n; ++b) add0.p[b] = in[b].dev;
+  // keyed steps in groups that fit the workspace and the output pointer table
+  const u32 group = std::max<u32>(1, std::min<u32>(ks_group(c->ws_n1), HE_MAXB / n));
+  std::vector<u32> keyed;
   for (u32 s = 0; s < n_steps; ++s) {
     for (u32 b = 0; b < n; ++b) {
       out[b * n_steps + s].level = l;
       out[b * n_steps + s].scale = in[b].scale;
     }
-    if (!keys[s]) {
-      for (u32 b = 0; b < n; ++b)
-        if ((rc = copy_ct(c, l, in[b].dev, out[b * n_steps + s].dev))) return rc;
+    if (keys[s]) {
+      keyed.push_back(s);
       continue;
     }
-    FinalArgs fa = no_final();
-    for (u32 b = 0; b < n; ++b) {
-      fa.out[b] = out[b * n_steps + s].dev;
-      fa.add0[b] = in[b].dev;
+    for (u32 b = 0; b < n; ++b)
+      if ((rc = copy_ct(c, l, in[b].dev, out[b * n_steps + s].dev))) return rc;
+  }
+  for (size_t g0 = 0; g0 < keyed.size(); g0 += group) {
+    const u32 S = (u32)std::min<size_t>(group, keyed.size() - g0);
+    StepKeys sk;
+    OutMap om;
+    std::memset(&om, 0, sizeof(om));
+    for (u32 i = 0; i < S; ++i) {
+      const u32 s = keyed[g0 + i];
+      sk.key[i] = keys[s]->dev;
+      sk.galois[i] = keys[s]->galois;
+      for (u32 b = 0; b < n; ++b) om.ptr[i * n + b] = out[b * n_steps + s].dev;
     }
-    if ((rc = ks_core(c, l, n, w, c1, keys[s]->dev, keys[s]->galois, fa, nullptr))) return rc;
+    if ((rc = ks_steps(c, l, n, S, w, c1, sk, add0, om))) return rc;
   }
   return HE_OK;
 }
@@ -344,19 +390,24 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   u64* c1in[HE_MAXB];
   for (u32 b = 0; b < n; ++b) c1in[b] = in[b].dev + (size_t)(l + 1) * N;
   if (n1 > 1) {
+    // Baby step i (1 <= i < n1) of item b goes to baby + (b (n1-1) + i - 1) csz;
+    // steps 1 .. n1-1 are below N/2, so each has a key.  All of them (in
+    // groups of the workspace's step count) are one step-batched key switch.
     if ((rc = modup(c, l, n, c1in, w))) return rc;
-    for (u32 i = 1; i < n1; ++i) {
-      FinalArgs fa = no_final();
-      for (u32 b = 0; b < n; ++b) {
-        fa.out[b] = w.baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
-        fa.add0[b] = in[b].dev;
+    const u32 group = ks_group(c->ws_n1);
+    for (u32 i0 = 1; i0 < n1; i0 += group) {
+      const u32 S = std::min(group, n1 - i0);
+      StepKeys sk;
+      for (u32 i = 0; i < S; ++i) {
+        sk.key[i] = baby[i0 + i]->dev;
+        sk.galois[i] = baby[i0 + i]->galois;
       }
-      if (!baby[i]) {
-        for (u32 b = 0; b < n; ++b)
-          if ((rc = copy_ct(c, l, in[b].dev, fa.out[b]))) return rc;
-        continue;
-      }
-      if ((rc = ks_core(c, l, n, w, c1in, baby[i]->dev, baby[i]->galois, fa, nullptr))) return rc;
+      OutMap om;
+      std::memset(&om, 0, sizeof(om));
+      om.base = w.baby + (size_t)(i0 - 1) * csz;
+      om.os = csz;
+      om.ob = (size_t)(n1 - 1) * csz;
+      if ((rc = ks_steps(c, l, n, S, w, c1in, sk, inI, om))) return rc;
     }
   }
   // Inner sums s_j (giant region [B][n2][csz]).

@@ -79,7 +79,29 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
     ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
   }
   const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
-  for (u32 b = 0; b < nitems; ++b) {
+  // Items two at a time: both items' digit words are in flight together.
+  u32 b = 0;
+  for (; b + 2 <= nitems; b += 2) {
+    u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
+    const u64* e0 = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e1 = e0 + (size_t)dstride * ne * N;
+    for (u32 j = 0; j < beta; ++j) {
+      const bool own_j = j == own_digit;
+      const u64 x0 = own_j ? own.p[b][(size_t)t * N + ks] : e0[(size_t)j * ne * N];
+      const u64 x1 = own_j ? own.p[b + 1][(size_t)t * N + ks] : e1[(size_t)j * ne * N];
+      acc_wide(sb0, x0, kb[j]);
+      acc_wide(sa0, x0, ka[j]);
+      acc_wide(sb1, x1, kb[j]);
+      acc_wide(sa1, x1, ka[j]);
+    }
+    u64* o = u + ((size_t)b * 2 * ne + t) * N + k;
+    o[0] = redc(sb0, q, qneg);
+    o[(size_t)ne * N] = redc(sa0, q, qneg);
+    o += (size_t)2 * ne * N;
+    o[0] = redc(sb1, q, qneg);
+    o[(size_t)ne * N] = redc(sa1, q, qneg);
+  }
+  if (b < nitems) {
     u128v sb = {0, 0}, sa = {0, 0};
     const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
     for (u32 j = 0; j < beta; ++j) {
@@ -91,6 +113,81 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
     o[0] = redc(sb, q, qneg);
     o[(size_t)ne * N] = redc(sa, q, qneg);
   }
+}
+
+// grid: (S, N/BS, ne): the steps of one (k-range, limb) are adjacent, so the
+// extended digits they share come from L2 after the first.
+__global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, Items own, StepKeys keys,
+                                                       u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
+                                                       u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
+                                                       u32 nitems, u32 alpha) {
+  const u32 s = blockIdx.x, k = blockIdx.y * BS + threadIdx.x, t = blockIdx.z;
+  const u32 ne = l + 1 + np, nt = nq + np;
+  const u32 pr = t <= l ? t : nq + (t - l - 1);
+  const u64 q = pc[pr].q, qneg = pc[pr].qneg;
+  const u32 ks = galois_perm(k, keys.galois[s], logn);
+  const u64* key = keys.key[s];
+  u64 kb[8], ka[8];
+  for (u32 j = 0; j < beta; ++j) {
+    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + k];
+    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
+  }
+  const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
+  u64* ub = u + (size_t)s * nitems * 2 * ne * N;
+  u32 b = 0;
+  for (; b + 2 <= nitems; b += 2) {
+    u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
+    const u64* e0 = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e1 = e0 + (size_t)dstride * ne * N;
+    for (u32 j = 0; j < beta; ++j) {
+      const bool own_j = j == own_digit;
+      const u64 x0 = own_j ? own.p[b][(size_t)t * N + ks] : e0[(size_t)j * ne * N];
+      const u64 x1 = own_j ? own.p[b + 1][(size_t)t * N + ks] : e1[(size_t)j * ne * N];
+      acc_wide(sb0, x0, kb[j]);
+      acc_wide(sa0, x0, ka[j]);
+      acc_wide(sb1, x1, kb[j]);
+      acc_wide(sa1, x1, ka[j]);
+    }
+    u64* o = ub + ((size_t)b * 2 * ne + t) * N + k;
+    o[0] = redc(sb0, q, qneg);
+    o[(size_t)ne * N] = redc(sa0, q, qneg);
+    o += (size_t)2 * ne * N;
+    o[0] = redc(sb1, q, qneg);
+    o[(size_t)ne * N] = redc(sa1, q, qneg);
+  }
+  if (b < nitems) {
+    u128v sb = {0, 0}, sa = {0, 0};
+    const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    for (u32 j = 0; j < beta; ++j) {
+      const u64 x = j == own_digit ? own.p[b][(size_t)t * N + ks] : e[(size_t)j * ne * N];
+      acc_wide(sb, x, kb[j]);
+      acc_wide(sa, x, ka[j]);
+    }
+    u64* o = ub + ((size_t)b * 2 * ne + t) * N + k;
+    o[0] = redc(sb, q, qneg);
+    o[(size_t)ne * N] = redc(sa, q, qneg);
+  }
+}
+
+// grid: (N/BS, l+1, S B), item z = s B + b
+__global__ void __launch_bounds__(BS) k_ks_final_steps(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                       StepKeys keys, Items add0, OutMap om,
+                                                       const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                       u32 N, u32 logn, u32 l, u32 np, u32 nq, u32 B) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, z = blockIdx.z, s = z / B, b = z % B;
+  const u32 ne = l + 1 + np;
+  const u64 q = pc[i].q;
+  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
+  const size_t ui = ((size_t)z * 2 * ne + i) * N + k;
+  const size_t ci = ((size_t)z * 2 * (l + 1) + i) * N + k;
+  u64 r0 = shoup(u[ui] + q - conv[ci], w, wsh, q);
+  const u64 r1 = shoup(u[ui + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q);
+  r0 = add_mod(r0, add0.p[b][(size_t)i * N + galois_perm(k, keys.galois[s], logn)], q);
+  u64* out = om.base ? om.base + s * om.os + b * om.ob : om.ptr[z];
+  out[(size_t)i * N + k] = r0;
+  out[(size_t)(l + 1 + i) * N + k] = r1;
 }
 
 // grid: (N/BS, 2, B)
@@ -289,6 +386,26 @@ int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& o
   else
     hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
                        c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
+  return ok();
+}
+
+int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, const Items& own, const StepKeys& keys,
+                          u64* u) {
+  const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
+  TraceScope ts(c, TK_KS_INNER_STEPS,
+                (double)S * ((double)B * beta * ne + 2.0 * beta * ne + 2.0 * B * ne) * (8.0 * (double)c->N));
+  dim3 grid(S, c->N / BS, ne);
+  hipLaunchKernelGGL(k_ks_inner_steps, grid, dim3(BS), 0, c->stream, ext, own, keys, u, c->d_pc, c->N, c->log_n, l,
+                     c->nq, c->np, beta, c->dnum, B, c->alpha);
+  return ok();
+}
+
+int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
+                          const Items& add0, const OutMap& om) {
+  // per item: u and conv (2 polys each) and add0.c0 read, 2 polys written
+  TraceScope ts(c, TK_KS_FINAL_STEPS, (double)S * B * 7.0 * (l + 1) * (8.0 * (double)c->N));
+  hipLaunchKernelGGL(k_ks_final_steps, dim3(c->N / BS, l + 1, S * B), dim3(BS), 0, c->stream, u, conv, keys, add0, om,
+                     c->d_pc, c->d_moddown, c->N, c->log_n, l, c->np, c->nq, B);
   return ok();
 }
 

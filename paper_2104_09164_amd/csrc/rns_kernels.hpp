@@ -44,6 +44,28 @@ struct FinalArgs {
 int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv, u32 galois, const FinalArgs& fa,
                     const u64* bias);
 
+// Several rotation steps of the same B items in one set of launches (the
+// hoisted form: the digits in ext are shared by every step).  Item (s, b) of
+// the u / conv workspaces is s B + b.
+#define HE_MAX_STEPS 64
+struct StepKeys {
+  const u64* key[HE_MAX_STEPS];   // rotation key of step s ([dnum][2][L+1+K][N], Montgomery form)
+  u32 galois[HE_MAX_STEPS];       // its Galois element
+};
+// u[s B + b] = key-switch inner product of item b with key s (as launch_ks_inner).
+int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, const Items& own, const StepKeys& keys,
+                          u64* u);
+// Output ciphertext of item (s, b): base + s os + b ob when base is set, else ptr[s B + b] (S B <= HE_MAXB).
+struct OutMap {
+  u64* ptr[HE_MAXB];
+  u64* base;
+  size_t os, ob;
+};
+// Rotation outputs: out(s, b).c0 = add0.p[b].c0[perm_{g_s}(.)] + (u_b - conv_b) P^{-1},
+//                   out(s, b).c1 =                               (u_a - conv_a) P^{-1}.
+int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
+                          const Items& add0, const OutMap& om);
+
 // Inner sums of the baby-step/giant-step product, item b, j < n2:
 //   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
 // r_0(b) = in.p[b]; r_i(b) = baby + ((b (n1-1) + i - 1) * 2 (l+1)) N for i >= 1.

@@ -105,13 +105,14 @@ def test_tracer_counts_launches_and_bytes(setup10):
         ctx.set_knob("trace", 0)
     for u, s in enumerate([1, 7]):
         assert np.array_equal(ctx.export_ct(out[u]), o.rotate(ct, s, keys).data)
-    # one ModUp shared by both steps, one key switch (inner product + epilogue) per step
-    assert tab["modup_conv"][0] == 1 and tab["ks_inner"][0] == 2 and tab["ks_final"][0] == 2
+    # one ModUp shared by both steps; both key switches in one step-batched launch per stage
+    assert tab["modup_conv"][0] == 1 and tab["ks_inner_steps"][0] == 1 and tab["ks_final_steps"][0] == 1
+    assert tab["moddown_conv"][0] == 1 and "ks_inner" not in tab
     N, l, K = pr.n, ct.level, len(pr.p)
     beta = -(-(l + 1) // pr.alpha)
     ne = l + 1 + K
     # per step: the extended digits and the step's key (2 polys per digit) read, u (2 polys) written
-    assert tab["ks_inner"][2] == 2 * (beta * ne + 2 * beta * ne + 2 * ne) * N * 8
+    assert tab["ks_inner_steps"][2] == 2 * (beta * ne + 2 * beta * ne + 2 * ne) * N * 8
     for name, (n, ms, by) in tab.items():
         assert n > 0 and ms > 0 and by > 0, name
 
