@@ -114,7 +114,10 @@ size_t he_ct_bytes(const he_ctx* ctx, uint32_t level);
 /* Key storage for the relinearisation key plus n_rot rotation keys. */
 size_t he_key_bytes(const he_ctx* ctx, uint32_t n_rot);
 /* Workspace for batched calls of up to max_batch ciphertexts and dense
- * layers with baby-step count <= max_n1 and giant-step count <= max_n2. */
+ * layers with baby-step count <= max_n1 (at most 65) and giant-step count
+ * <= max_n2.  The key-switch buffers hold min(max_n1 - 1, 64) rotation steps
+ * of max_batch ciphertexts at once (one launch per stage for all of them);
+ * hoisted rotations beyond that run in groups. */
 size_t he_workspace_bytes(const he_ctx* ctx, uint32_t max_batch, uint32_t max_n1, uint32_t max_n2);
 /* Plaintext storage of one dense layer (m diagonals at `level`, + bias). */
 size_t he_dense_bytes(const he_ctx* ctx, uint32_t level, uint32_t m, int has_bias);

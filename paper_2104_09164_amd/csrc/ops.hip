@@ -37,7 +37,7 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   take(&x.d01, B * csz);
   take(&x.d2, B * L1 * N);
   take(&x.red, B * csz);
-  take(&x.baby, B * (n1 > 1 ? n1 - 1 : 0) * csz);
+  take(&x.baby, 0);   // baby-step rotations are folded into the inner sums, never stored
   take(&x.giant, B * (n2 ? n2 : 1) * csz);
   take(&x.z0, B * csz);
   take(&x.z1, B * csz);
@@ -129,8 +129,9 @@ int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key
 
 // S rotation steps of the same B items (digits of their c1 already in w.ext
 // from one ModUp): one launch per stage for all S B key switches.
-int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
-             const OutMap& om) {
+// Everything of a step-batched key switch but the epilogue: u (NTT form,
+// P-limbs included) and conv (NTT form) of every (step, item) in w.u / w.conv.
+int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np;
   Items own;
@@ -150,8 +151,13 @@ int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const 
   pf.src[0] = pf.dst[0] = w.conv;
   pf.stride = (size_t)2 * (l + 1) * N;
   for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
-  if ((rc = launch_ntt(c, pf, false))) return rc;
-  return launch_ks_final_steps(c, l, B, S, w.u, w.conv, keys, add0, om);
+  return launch_ntt(c, pf, false);
+}
+
+int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
+             const OutMap& om) {
+  int rc = ks_steps_inner(c, l, B, S, w, c1, keys);
+  return rc ? rc : launch_ks_final_steps(c, l, B, S, w.u, w.conv, keys, add0, om);
 }
 
 FinalArgs no_final() {
@@ -365,6 +371,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   if (in[0].level != l) return HE_ELEVEL;
   const u32 n1 = d->n1, n2 = d->n2;
   if (n1 > std::max<u32>(c->ws_n1, 1) || n2 > std::max<u32>(c->ws_n2, 1)) return HE_ENOMEM;
+  if (n1 > 1 && n1 - 1 > ks_group(c->ws_n1)) return HE_ENOMEM;   // all baby steps in one step-batched switch
   const double out_scale = in[0].scale * d->pt_scale;
   if (d->bias && !same_scale(d->bias_scale, out_scale)) return HE_ESCALE;
   for (u32 b = 0; b < n; ++b)
@@ -374,7 +381,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   for (u32 t = d->n / 2; t >= d->m && t > 0; t /= 2) rs_steps.push_back(t);
   std::vector<const KeySlot*> baby(n1, nullptr), giant(n2, nullptr), rsk(rs_steps.size(), nullptr);
   for (u32 i = 1; i < n1; ++i)
-    if (galois_of(c, i) != 1 && !(baby[i] = find_rot(c, galois_of(c, i)))) return HE_ENOKEY;
+    if (!(baby[i] = find_rot(c, galois_of(c, i)))) return HE_ENOKEY;   // i < n1 <= 64 < N/2: never the identity
   for (u32 j = 1; j < n2; ++j)
     if (galois_of(c, (int64_t)n1 * j) != 1 && !(giant[j] = find_rot(c, galois_of(c, (int64_t)n1 * j)))) return HE_ENOKEY;
   for (size_t u = 0; u < rs_steps.size(); ++u)
@@ -390,28 +397,23 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   u64* c1in[HE_MAXB];
   for (u32 b = 0; b < n; ++b) c1in[b] = in[b].dev + (size_t)(l + 1) * N;
   if (n1 > 1) {
-    // Baby step i (1 <= i < n1) of item b goes to baby + (b (n1-1) + i - 1) csz;
-    // steps 1 .. n1-1 are below N/2, so each has a key.  All of them (in
-    // groups of the workspace's step count) are one step-batched key switch.
+    // Baby steps i = 1 .. n1-1 (all below N/2, so each has a key): one hoisted
+    // ModUp, then one step-batched key switch whose epilogue forms each
+    // rotated ciphertext in registers and folds it straight into the inner
+    // sums s_j (giant region [B][n2][csz]); the rotations are never stored.
+    // The workspace holds ks_group(max_n1) >= n1 - 1 steps.
     if ((rc = modup(c, l, n, c1in, w))) return rc;
-    const u32 group = ks_group(c->ws_n1);
-    for (u32 i0 = 1; i0 < n1; i0 += group) {
-      const u32 S = std::min(group, n1 - i0);
-      StepKeys sk;
-      for (u32 i = 0; i < S; ++i) {
-        sk.key[i] = baby[i0 + i]->dev;
-        sk.galois[i] = baby[i0 + i]->galois;
-      }
-      OutMap om;
-      std::memset(&om, 0, sizeof(om));
-      om.base = w.baby + (size_t)(i0 - 1) * csz;
-      om.os = csz;
-      om.ob = (size_t)(n1 - 1) * csz;
-      if ((rc = ks_steps(c, l, n, S, w, c1in, sk, inI, om))) return rc;
+    const u32 S = n1 - 1;
+    StepKeys sk;
+    for (u32 i = 0; i < S; ++i) {
+      sk.key[i] = baby[i + 1]->dev;
+      sk.galois[i] = baby[i + 1]->galois;
     }
+    if ((rc = ks_steps_inner(c, l, n, S, w, c1in, sk))) return rc;
+    if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
+  } else if ((rc = launch_multplain_acc(c, l, n1, n2, inI, nullptr, d->pts, w.giant))) {
+    return rc;                                     // n1 = 1: s_j = pts[j] (.) in
   }
-  // Inner sums s_j (giant region [B][n2][csz]).
-  if ((rc = launch_multplain_acc(c, l, n1, n2, inI, w.baby, d->pts, w.giant))) return rc;
 
   // Giant steps then rotate-and-sum, each a full key switch; the last one
   // writes the caller's output and adds the bias.

@@ -23,6 +23,22 @@ __device__ __forceinline__ u32 galois_perm(u32 k, u32 g, u32 logn) {
   return brev_n((e2 - 1) >> 1, logn);
 }
 
+// XCD-aware decode of a 1-D grid of inner x T workgroups.  Workgroups are
+// dealt to the 8 XCDs round-robin by id, so id L runs on XCD L mod 8.  When T
+// is a multiple of 8, the `inner` workgroups that share one tile's operands
+// (the items or steps of a batch) all land on that tile's XCD, back to back,
+// and read the shared words from its L2; otherwise inner index fastest.
+__device__ __forceinline__ void xcd_decode(u32 L, u32 inner, u32 T, u32& i, u32& tile) {
+  if (T & 7) {
+    i = L % inner;
+    tile = L / inner;
+    return;
+  }
+  const u32 r = L >> 3;
+  i = r % inner;
+  tile = (r / inner) * 8 + (L & 7);
+}
+
 __global__ void __launch_bounds__(BS) k_copy_polys(PolyBatch pb, u32 N) {
   const u32 b = blockIdx.y, r = blockIdx.z;
   if (pb.prime[r] == 0xFF) return;
@@ -115,14 +131,16 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
   }
 }
 
-// grid: (S, N/BS, ne): the steps of one (k-range, limb) are adjacent, so the
-// extended digits they share come from L2 after the first.
+// 1-D grid over S x (N/BS, ne) tiles: the steps of a tile share its extended
+// digits (xcd_decode).
 __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, Items own, StepKeys keys,
                                                        u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
                                                        u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
-                                                       u32 nitems, u32 alpha) {
-  const u32 s = blockIdx.x, k = blockIdx.y * BS + threadIdx.x, t = blockIdx.z;
-  const u32 ne = l + 1 + np, nt = nq + np;
+                                                       u32 nitems, u32 alpha, u32 nsteps) {
+  const u32 ne = l + 1 + np, nt = nq + np, nkb = N / BS;
+  u32 s, tile;
+  xcd_decode(blockIdx.x, nsteps, nkb * ne, s, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x, t = tile / nkb;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
   const u64 q = pc[pr].q, qneg = pc[pr].qneg;
   const u32 ks = galois_perm(k, keys.galois[s], logn);
@@ -190,6 +208,65 @@ __global__ void __launch_bounds__(BS) k_ks_final_steps(const u64* __restrict__ u
   out[(size_t)(l + 1 + i) * N + k] = r1;
 }
 
+// 1-D grid over B x (N/BS, l+1, n2/JC) tiles (items of a tile share its
+// plaintext words).  One thread: coefficient k of limb li of item b, giant
+// sums jc JC .. jc JC + JC - 1; the baby-step values r_i are formed in
+// registers from the key-switch buffers and consumed at once.
+template <int JC>
+__global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                    StepKeys keys, Items in, const u64* __restrict__ pts,
+                                                    u64* __restrict__ sums, const PrimeConst* __restrict__ pc,
+                                                    const u64* __restrict__ md, u32 N, u32 logn, u32 l, u32 np, u32 nq,
+                                                    u32 n1, u32 n2) {
+  const u32 nkb = N / BS, B = in.n;
+  u32 b, tile;
+  xcd_decode(blockIdx.x, B, nkb * (l + 1) * (n2 / JC), b, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x;
+  const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
+  const u32 ne = l + 1 + np;
+  const u64 q = pc[li].q, qneg = pc[li].qneg;
+  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64 w = pinv[2 * li], wsh = pinv[2 * li + 1];
+  const size_t csz = (size_t)2 * (l + 1) * N;
+  const u64* x = in.p[b];
+  u64 r0 = x[(size_t)li * N + k], r1 = x[(size_t)(l + 1 + li) * N + k];
+  u64 t0[JC], t1[JC];
+  u128v a0[JC], a1[JC];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) { t0[jj] = t1[jj] = 0; a0[jj] = a1[jj] = {0, 0}; }
+  for (u32 i = 0; i < n1; ++i) {
+    if (i > 0) {
+      const u32 z = (i - 1) * B + b;
+      const size_t ui = ((size_t)z * 2 * ne + li) * N + k;
+      const size_t ci = ((size_t)z * 2 * (l + 1) + li) * N + k;
+      r0 = shoup(u[ui] + q - conv[ci], w, wsh, q);
+      r1 = shoup(u[ui + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q);
+      r0 = add_mod(r0, x[(size_t)li * N + galois_perm(k, keys.galois[i - 1], logn)], q);
+    }
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const u32 kk = n1 * (jc * JC + jj) + i;
+      const u64 pt = pts[((size_t)kk * (l + 1) + li) * N + k];
+      acc_wide(a0[jj], r0, pt);
+      acc_wide(a1[jj], r1, pt);
+    }
+    if ((i & 7) == 7 || i + 1 == n1) {
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj) {
+        t0[jj] = add_mod(t0[jj], redc(a0[jj], q, qneg), q);
+        t1[jj] = add_mod(t1[jj], redc(a1[jj], q, qneg), q);
+        a0[jj] = a1[jj] = {0, 0};
+      }
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = sums + ((size_t)b * n2 + jc * JC + jj) * csz;
+    o[(size_t)li * N + k] = t0[jj];
+    o[(size_t)(l + 1 + li) * N + k] = t1[jj];
+  }
+}
+
 // grid: (N/BS, 2, B)
 __global__ void __launch_bounds__(BS) k_moddown_conv(const u64* __restrict__ u, u64* __restrict__ conv,
                                                      const PrimeConst* __restrict__ pc,
@@ -243,16 +320,19 @@ __global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, cons
   fa.out[b][o1] = r1;
 }
 
-// grid: (N/BS, l+1, B * n2/JC)
 template <int JC>
 __global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __restrict__ baby,
                                                       const u64* __restrict__ pts, u64* __restrict__ s,
                                                       const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n1,
                                                       u32 n2) {
-  const u32 k = blockIdx.x * BS + threadIdx.x;
-  const u32 li = blockIdx.y;
+  // 1-D grid over B x (N/BS, l+1, n2/JC) tiles: the items of a tile share
+  // its plaintext words (xcd_decode)
+  const u32 nkb = N / BS;
+  u32 b, tile;
+  xcd_decode(blockIdx.x, in.n, nkb * (l + 1) * (n2 / JC), b, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x;
+  const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
   const u32 nch = n2 / JC;
-  const u32 b = blockIdx.z % in.n, jc = blockIdx.z / in.n;
   const u64 q = pc[li].q, qneg = pc[li].qneg;
   const size_t csz = (size_t)2 * (l + 1) * N;
   u64 t0[JC], t1[JC];
@@ -394,9 +474,9 @@ int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, const 
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
   TraceScope ts(c, TK_KS_INNER_STEPS,
                 (double)S * ((double)B * beta * ne + 2.0 * beta * ne + 2.0 * B * ne) * (8.0 * (double)c->N));
-  dim3 grid(S, c->N / BS, ne);
+  dim3 grid(S * (c->N / BS) * ne);
   hipLaunchKernelGGL(k_ks_inner_steps, grid, dim3(BS), 0, c->stream, ext, own, keys, u, c->d_pc, c->N, c->log_n, l,
-                     c->nq, c->np, beta, c->dnum, B, c->alpha);
+                     c->nq, c->np, beta, c->dnum, B, c->alpha, S);
   return ok();
 }
 
@@ -406,6 +486,29 @@ int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u6
   TraceScope ts(c, TK_KS_FINAL_STEPS, (double)S * B * 7.0 * (l + 1) * (8.0 * (double)c->N));
   hipLaunchKernelGGL(k_ks_final_steps, dim3(c->N / BS, l + 1, S * B), dim3(BS), 0, c->stream, u, conv, keys, add0, om,
                      c->d_pc, c->d_moddown, c->N, c->log_n, l, c->np, c->nq, B);
+  return ok();
+}
+
+int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const u64* conv,
+                              const StepKeys& keys, const Items& in, const u64* pts, u64* s) {
+  const u32 jc = n2 >= 8 ? 8 : (n2 >= 4 ? 4 : (n2 >= 2 ? 2 : 1));
+  if (n2 % jc) return HE_EINVAL;
+  // per item: the input ciphertext, u and conv of every baby step (2 + 2 polys)
+  // and its rotated c0 source limb, the n2 sums written; plaintexts once
+  TraceScope ts(c, TK_KS_FINAL_MP,
+                ((double)B * (2.0 + 5.0 * (n1 - 1) + 2.0 * n2) * (l + 1) + (double)n1 * n2 * (l + 1)) *
+                    (8.0 * (double)c->N));
+  dim3 grid(B * (n2 / jc) * (c->N / BS) * (l + 1));
+#define HE_LAUNCH_MP(J)                                                                                           \
+  hipLaunchKernelGGL(k_ks_final_mp<J>, grid, dim3(BS), 0, c->stream, u, conv, keys, in, pts, s, c->d_pc,           \
+                     c->d_moddown, c->N, c->log_n, l, c->np, c->nq, n1, n2)
+  switch (jc) {
+    case 8: HE_LAUNCH_MP(8); break;
+    case 4: HE_LAUNCH_MP(4); break;
+    case 2: HE_LAUNCH_MP(2); break;
+    default: HE_LAUNCH_MP(1); break;
+  }
+#undef HE_LAUNCH_MP
   return ok();
 }
 
@@ -434,7 +537,7 @@ int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, cons
   // all giant-step sums of a thread in registers (up to 8) so every baby-step
   // ciphertext is read once per batch
   const u32 jc = n2 >= 8 ? 8 : n2;
-  dim3 grid(c->N / BS, l + 1, in.n * (n2 / jc));
+  dim3 grid(in.n * (n2 / jc) * (c->N / BS) * (l + 1));
   switch (jc) {
     case 8: hipLaunchKernelGGL(k_multplain_acc<8>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
     case 4: hipLaunchKernelGGL(k_multplain_acc<4>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;

@@ -66,6 +66,14 @@ struct OutMap {
 int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
                           const Items& add0, const OutMap& om);
 
+// Baby steps folded into the inner sums: with u / conv holding the key
+// switches of baby steps i = 1 .. n1-1 (step s = i - 1) of items b < B,
+//   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b),   r_0(b) = in.p[b],
+//   r_i(b) = the rotation of in.p[b] by i (as launch_ks_final_steps computes it),
+// without writing the rotated ciphertexts.  s = [B][n2][2][l+1][N].
+int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const u64* conv,
+                              const StepKeys& keys, const Items& in, const u64* pts, u64* s);
+
 // Inner sums of the baby-step/giant-step product, item b, j < n2:
 //   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
 // r_0(b) = in.p[b]; r_i(b) = baby + ((b (n1-1) + i - 1) * 2 (l+1)) N for i >= 1.
