@@ -39,15 +39,16 @@ struct PolyBatch {
   u32 src_off, dst_off, npoly, nitems;
   uint8_t prime[HE_MAX_POLYS];   // prime index of poly row r; 0xFF = skip the row
   uint8_t row[HE_MAX_POLYS];     // NTT launches only: grid row -> poly row (rows compacted)
-  size_t stride = 0;             // NTT launches: when nonzero, item b is at src[0] / dst[0] + b * stride
-                                 // (any number of items; the pointer lists are then unused beyond [0])
+  size_t stride = 0;             // NTT launches: when nonzero, item b is at src[0] + b * stride and
+  size_t dst_stride = 0;         // dst[0] + b * (dst_stride ? dst_stride : stride) (any number of
+                                 // items; the pointer lists are then unused beyond [0])
 };
 
 // Kernel classes of the tracer (he_trace_read aggregates per class).
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
   TK_MODUP_CONV, TK_KS_INNER, TK_MODDOWN_CONV, TK_KS_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE,
-  TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_TO_MONT, TK_KS_INNER_STEPS, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_COUNT
+  TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_TO_MONT, TK_KS_INNER_STEPS, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM, TK_MODUP_CONV_STEPS, TK_COUNT
 };
 const char* trace_name(int kind);
 

@@ -40,7 +40,7 @@ __device__ __forceinline__ const u64* item_src(const PolyBatch& pb, u32 b) {
   return pb.stride ? pb.src[0] + (size_t)b * pb.stride : pb.src[b];
 }
 __device__ __forceinline__ u64* item_dst(const PolyBatch& pb, u32 b) {
-  return pb.stride ? pb.dst[0] + (size_t)b * pb.stride : pb.dst[b];
+  return pb.stride ? pb.dst[0] + (size_t)b * (pb.dst_stride ? pb.dst_stride : pb.stride) : pb.dst[b];
 }
 
 // Primes below 2^57 take the forward butterflies without the per-stage

@@ -14,8 +14,10 @@ struct WS {
   u64 *rtmp, *coef, *ext, *u, *conv, *d01, *d2, *red, *baby, *giant, *z0, *z1;
 };
 
-// Rotation steps per step-batched key switch: the baby steps of the widest layer.
+// Rotation steps per step-batched key switch: the baby steps of the widest
+// layer (hoisted, sharing one ModUp) or its giant steps (one ModUp each).
 u32 ks_group(u32 n1) { return n1 > 2 ? std::min<u32>(n1 - 1, HE_MAX_STEPS) : 1; }
+u32 giant_group(u32 n2) { return n2 > 2 ? std::min<u32>(n2 - 1, HE_MAX_STEPS) : 1; }
 
 size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   const size_t N = c->N, L1 = c->nq, E = c->nq + c->np;
@@ -27,11 +29,12 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   };
   WS dummy;
   WS& x = w ? *w : dummy;
+  // coef and ext hold the ModUp of every giant step (GJ steps of B items);
+  // u and conv every step of one step-batched key switch
+  const size_t GJ = giant_group(n2), G = std::max<size_t>(ks_group(n1), GJ);
   take(&x.rtmp, B * csz);
-  take(&x.coef, B * L1 * N);
-  take(&x.ext, B * c->dnum * E * N);
-  // u and conv hold every step of one step-batched key switch (G steps of B items)
-  const size_t G = ks_group(n1);
+  take(&x.coef, GJ * B * L1 * N);
+  take(&x.ext, GJ * B * c->dnum * E * N);
   take(&x.u, G * B * 2 * E * N);
   take(&x.conv, G * B * csz);
   take(&x.d01, B * csz);
@@ -102,6 +105,33 @@ int modup(he_ctx* c, u32 l, u32 B, u64* const* c1, const WS& w) {
   return launch_ntt(c, nt, false);
 }
 
+// ModUp of BB items whose c1 polynomials are at c1_base + z c1_stride (the
+// giant-step inputs): as modup, items z = 0 .. BB-1 of coef / ext.
+int modup_strided(he_ctx* c, u32 l, u32 BB, const u64* c1_base, size_t c1_stride, const WS& w) {
+  const size_t N = c->N;
+  const u32 ne = l + 1 + c->np, beta = digits_at(c, l);
+  PolyBatch pb = batch_of(BB);
+  pb.npoly = l + 1;
+  pb.src[0] = (u64*)c1_base;
+  pb.dst[0] = w.coef;
+  pb.stride = c1_stride;
+  pb.dst_stride = (size_t)(l + 1) * N;
+  for (u32 r = 0; r <= l; ++r) pb.prime[r] = (uint8_t)r;
+  int rc = launch_ntt(c, pb, true);
+  if (!rc) rc = launch_modup_conv(c, l, BB, w.coef, w.ext);
+  if (rc) return rc;
+  PolyBatch nt = batch_of(BB);
+  nt.npoly = beta * ne;
+  nt.src[0] = nt.dst[0] = w.ext;
+  nt.stride = (size_t)c->dnum * ne * N;
+  for (u32 j = 0; j < beta; ++j) {
+    const u32 lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l + 1);
+    for (u32 t = 0; t < ne; ++t)
+      nt.prime[j * ne + t] = (t >= lo && t < hi) ? 0xFF : (uint8_t)ext_prime(c, l, t);
+  }
+  return launch_ntt(c, nt, false);
+}
+
 // Key switch of the digits in w.ext (own limbs from c1) with `key`
 // (automorphism `galois` on the digits), ModDown, combined into fa.out.
 int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key, u32 galois, const FinalArgs& fa,
@@ -131,13 +161,11 @@ int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key
 // from one ModUp): one launch per stage for all S B key switches.
 // Everything of a step-batched key switch but the epilogue: u (NTT form,
 // P-limbs included) and conv (NTT form) of every (step, item) in w.u / w.conv.
-int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys) {
+int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, const OwnMap& own, u32 ext_items,
+                   const StepKeys& keys) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np;
-  Items own;
-  own.n = B;
-  for (u32 b = 0; b < B; ++b) own.p[b] = c1[b];
-  int rc = launch_ks_inner_steps(c, l, B, S, w.ext, own, keys, w.u);
+  int rc = launch_ks_inner_steps(c, l, B, S, w.ext, ext_items, own, keys, w.u);
   if (rc) return rc;
   PolyBatch pi = batch_of(S * B);
   pi.npoly = 2 * ne;
@@ -154,9 +182,16 @@ int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, 
   return launch_ntt(c, pf, false);
 }
 
+OwnMap own_of(u32 B, u64* const* c1) {
+  OwnMap own;
+  std::memset(&own, 0, sizeof(own));
+  for (u32 b = 0; b < B; ++b) own.ptr[b] = c1[b];
+  return own;
+}
+
 int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
              const OutMap& om) {
-  int rc = ks_steps_inner(c, l, B, S, w, c1, keys);
+  int rc = ks_steps_inner(c, l, B, S, w, own_of(B, c1), 0, keys);
   return rc ? rc : launch_ks_final_steps(c, l, B, S, w.u, w.conv, keys, add0, om);
 }
 
@@ -409,7 +444,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       sk.key[i] = baby[i + 1]->dev;
       sk.galois[i] = baby[i + 1]->galois;
     }
-    if ((rc = ks_steps_inner(c, l, n, S, w, c1in, sk))) return rc;
+    if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
     if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
   } else if ((rc = launch_multplain_acc(c, l, n1, n2, inI, nullptr, d->pts, w.giant))) {
     return rc;                                     // n1 = 1: s_j = pts[j] (.) in
@@ -417,9 +452,44 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
 
   // Giant steps then rotate-and-sum, each a full key switch; the last one
   // writes the caller's output and adds the bias.
-  const u32 total = (n2 - 1) + (u32)rs_steps.size();
+  // giant region [n2][B][csz]: s_j of item b at giant + (j n + b) csz
+  u32 total = (n2 - 1) + (u32)rs_steps.size();
   u64* cur[HE_MAXB];
-  for (u32 b = 0; b < n; ++b) cur[b] = w.giant + (size_t)b * n2 * csz;
+  for (u32 b = 0; b < n; ++b) cur[b] = w.giant + (size_t)b * csz;
+  bool giants_batched = n2 > 1 && n2 - 1 <= giant_group(c->ws_n2);
+  for (u32 j = 1; j < n2; ++j) giants_batched = giants_batched && giant[j];
+  if (giants_batched) {
+    // Every giant step at once: ModUp of all s_j (j >= 1), one step-batched
+    // key switch (own digits per (j, b)), and an epilogue that sums
+    // s_0 + rho(s_1) + ... per item.  Equal to the in-order accumulation.
+    const u32 J = n2 - 1;
+    if ((rc = modup_strided(c, l, J * n, w.giant + (size_t)n * csz + (size_t)(l + 1) * N, csz, w))) return rc;
+    StepKeys sk;
+    for (u32 j = 0; j < J; ++j) {
+      sk.key[j] = giant[j + 1]->dev;
+      sk.galois[j] = giant[j + 1]->galois;
+    }
+    OwnMap own;
+    std::memset(&own, 0, sizeof(own));
+    own.base = w.giant + (size_t)n * csz + (size_t)(l + 1) * N;
+    own.os = (size_t)n * csz;
+    own.ob = csz;
+    if ((rc = ks_steps_inner(c, l, n, J, w, own, n, sk))) return rc;
+    const bool last = rs_steps.empty();
+    OutMap om;
+    std::memset(&om, 0, sizeof(om));
+    for (u32 b = 0; b < n; ++b) om.ptr[b] = last ? out[b].dev : w.z0 + (size_t)b * csz;
+    if ((rc = launch_ks_final_sum(c, l, n, J, w.u, w.conv, sk, w.giant, last ? d->bias : nullptr, om))) return rc;
+    if (last) {
+      for (u32 b = 0; b < n; ++b) {
+        out[b].level = l;
+        out[b].scale = out_scale;
+      }
+      return HE_OK;
+    }
+    for (u32 b = 0; b < n; ++b) cur[b] = w.z0 + (size_t)b * csz;
+    total = (u32)rs_steps.size();
+  }
   u32 done = 0;
   auto step = [&](const KeySlot* key, u64* const* src, bool accumulate_in_place) -> int {
     ++done;
@@ -454,9 +524,9 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     for (u32 b = 0; b < n; ++b) cur[b] = dst[b];
     return HE_OK;
   };
-  for (u32 j = 1; j < n2; ++j) {
+  for (u32 j = 1; j < n2 && !giants_batched; ++j) {
     u64* src[HE_MAXB];
-    for (u32 b = 0; b < n; ++b) src[b] = w.giant + ((size_t)b * n2 + j) * csz;
+    for (u32 b = 0; b < n; ++b) src[b] = w.giant + ((size_t)j * n + b) * csz;
     if ((rc = step(giant[j], src, true))) return rc;
   }
   for (size_t u = 0; u < rs_steps.size(); ++u) {

@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
 
 // 1-D grid over S x (N/BS, ne) tiles: the steps of a tile share its extended
 // digits (xcd_decode).
-__global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, Items own, StepKeys keys,
+__global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, u32 ext_items, OwnMap own,
+                                                       StepKeys keys,
                                                        u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
                                                        u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
                                                        u32 nitems, u32 alpha, u32 nsteps) {
@@ -152,15 +153,19 @@ __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ e
   }
   const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
   u64* ub = u + (size_t)s * nitems * 2 * ne * N;
+  const u64* es = ext + (size_t)s * ext_items * dstride * ne * N;
+  const u64* ob = own.base ? own.base + s * own.os : nullptr;
   u32 b = 0;
   for (; b + 2 <= nitems; b += 2) {
     u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
-    const u64* e0 = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e0 = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
     const u64* e1 = e0 + (size_t)dstride * ne * N;
+    const u64* o0 = ob ? ob + b * own.ob : own.ptr[b];
+    const u64* o1 = ob ? ob + (b + 1) * own.ob : own.ptr[b + 1];
     for (u32 j = 0; j < beta; ++j) {
       const bool own_j = j == own_digit;
-      const u64 x0 = own_j ? own.p[b][(size_t)t * N + ks] : e0[(size_t)j * ne * N];
-      const u64 x1 = own_j ? own.p[b + 1][(size_t)t * N + ks] : e1[(size_t)j * ne * N];
+      const u64 x0 = own_j ? o0[(size_t)t * N + ks] : e0[(size_t)j * ne * N];
+      const u64 x1 = own_j ? o1[(size_t)t * N + ks] : e1[(size_t)j * ne * N];
       acc_wide(sb0, x0, kb[j]);
       acc_wide(sa0, x0, ka[j]);
       acc_wide(sb1, x1, kb[j]);
@@ -175,9 +180,10 @@ __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ e
   }
   if (b < nitems) {
     u128v sb = {0, 0}, sa = {0, 0};
-    const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* src = ob ? ob + b * own.ob : own.ptr[b];
     for (u32 j = 0; j < beta; ++j) {
-      const u64 x = j == own_digit ? own.p[b][(size_t)t * N + ks] : e[(size_t)j * ne * N];
+      const u64 x = j == own_digit ? src[(size_t)t * N + ks] : e[(size_t)j * ne * N];
       acc_wide(sb, x, kb[j]);
       acc_wide(sa, x, ka[j]);
     }
@@ -261,10 +267,42 @@ __global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, c
   }
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
-    u64* o = sums + ((size_t)b * n2 + jc * JC + jj) * csz;
+    u64* o = sums + ((size_t)(jc * JC + jj) * B + b) * csz;
     o[(size_t)li * N + k] = t0[jj];
     o[(size_t)(l + 1 + li) * N + k] = t1[jj];
   }
+}
+
+// grid: (N/BS, l+1, B).  One thread: coefficient k of limb i of item b, all
+// J giant steps summed in registers (modular sums are exact, so the order of
+// the terms does not change the result).
+__global__ void __launch_bounds__(BS) k_ks_final_sum(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                     StepKeys keys, const u64* __restrict__ sums,
+                                                     const u64* __restrict__ bias, OutMap om,
+                                                     const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                     u32 N, u32 logn, u32 l, u32 np, u32 nq, u32 B, u32 J) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, b = blockIdx.z;
+  const u32 ne = l + 1 + np;
+  const u64 q = pc[i].q;
+  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
+  const size_t csz = (size_t)2 * (l + 1) * N;
+  const u64* s0 = sums + (size_t)b * csz;
+  u64 r0 = s0[(size_t)i * N + k], r1 = s0[(size_t)(l + 1 + i) * N + k];
+  for (u32 j = 1; j <= J; ++j) {
+    const u32 z = (j - 1) * B + b;
+    const size_t ui = ((size_t)z * 2 * ne + i) * N + k;
+    const size_t ci = ((size_t)z * 2 * (l + 1) + i) * N + k;
+    const u64* sj = sums + ((size_t)j * B + b) * csz;
+    r0 = add_mod(r0, shoup(u[ui] + q - conv[ci], w, wsh, q), q);
+    r0 = add_mod(r0, sj[(size_t)i * N + galois_perm(k, keys.galois[j - 1], logn)], q);
+    r1 = add_mod(r1, shoup(u[ui + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q), q);
+  }
+  if (bias) r0 = add_mod(r0, bias[(size_t)i * N + k], q);
+  u64* out = om.base ? om.base + b * om.ob : om.ptr[b];
+  out[(size_t)i * N + k] = r0;
+  out[(size_t)(l + 1 + i) * N + k] = r1;
 }
 
 // grid: (N/BS, 2, B)
@@ -361,7 +399,7 @@ __global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __res
   (void)nch;
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
-    u64* o = s + ((size_t)b * n2 + jc * JC + jj) * csz;
+    u64* o = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
     o[(size_t)li * N + k] = t0[jj];
     o[(size_t)(l + 1 + li) * N + k] = t1[jj];
   }
@@ -469,13 +507,24 @@ int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& o
   return ok();
 }
 
-int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, const Items& own, const StepKeys& keys,
-                          u64* u) {
+int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
+                        const u64* sums, const u64* bias, const OutMap& om) {
+  // per item: s_0 (2 polys), per step u and conv (2 + 2) and s_j.c0, 2 polys written
+  TraceScope ts(c, TK_KS_FINAL_SUM,
+                ((double)B * (4.0 + 5.0 * S) * (l + 1) + (bias ? l + 1 : 0)) * (8.0 * (double)c->N));
+  hipLaunchKernelGGL(k_ks_final_sum, dim3(c->N / BS, l + 1, B), dim3(BS), 0, c->stream, u, conv, keys, sums, bias, om,
+                     c->d_pc, c->d_moddown, c->N, c->log_n, l, c->np, c->nq, B, S);
+  return ok();
+}
+
+int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ext_items, const OwnMap& own,
+                          const StepKeys& keys, u64* u) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
   TraceScope ts(c, TK_KS_INNER_STEPS,
                 (double)S * ((double)B * beta * ne + 2.0 * beta * ne + 2.0 * B * ne) * (8.0 * (double)c->N));
   dim3 grid(S * (c->N / BS) * ne);
-  hipLaunchKernelGGL(k_ks_inner_steps, grid, dim3(BS), 0, c->stream, ext, own, keys, u, c->d_pc, c->N, c->log_n, l,
+  hipLaunchKernelGGL(k_ks_inner_steps, grid, dim3(BS), 0, c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,
+                     c->log_n, l,
                      c->nq, c->np, beta, c->dnum, B, c->alpha, S);
   return ok();
 }

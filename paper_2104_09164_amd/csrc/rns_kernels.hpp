@@ -52,9 +52,18 @@ struct StepKeys {
   const u64* key[HE_MAX_STEPS];   // rotation key of step s ([dnum][2][L+1+K][N], Montgomery form)
   u32 galois[HE_MAX_STEPS];       // its Galois element
 };
-// u[s B + b] = key-switch inner product of item b with key s (as launch_ks_inner).
-int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, const Items& own, const StepKeys& keys,
-                          u64* u);
+// Source c1 (NTT form) of item (s, b), whose digits' own limbs the inner
+// product reads: base + s os + b ob when base is set, else ptr[b] (same for every s).
+struct OwnMap {
+  u64* ptr[HE_MAXB];
+  const u64* base;
+  size_t os, ob;
+};
+// u[s B + b] = key-switch inner product of item (s, b) with key s (as
+// launch_ks_inner).  Digits: ext item s ext_items + b (ext_items = 0: the
+// steps share item b's digits, the hoisted form; = B: one ModUp per (s, b)).
+int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ext_items, const OwnMap& own,
+                          const StepKeys& keys, u64* u);
 // Output ciphertext of item (s, b): base + s os + b ob when base is set, else ptr[s B + b] (S B <= HE_MAXB).
 struct OutMap {
   u64* ptr[HE_MAXB];
@@ -65,19 +74,24 @@ struct OutMap {
 //                   out(s, b).c1 =                               (u_a - conv_a) P^{-1}.
 int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
                           const Items& add0, const OutMap& om);
+// Giant-step sum of B items with J = S steps, om item b (base + b ob or ptr[b]) =
+//   s_0(b) + sum_{j=1..J} rho^{g_j}(s_j(b)) (+ bias on c0):
+//   s_j(b) = sums + (j B + b) csz, and the key switch of (j, b) in u / conv item (j-1) B + b.
+int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
+                        const u64* sums, const u64* bias, const OutMap& om);
 
 // Baby steps folded into the inner sums: with u / conv holding the key
 // switches of baby steps i = 1 .. n1-1 (step s = i - 1) of items b < B,
-//   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b),   r_0(b) = in.p[b],
+//   s[j][b] = sum_{i < n1} pts[n1 j + i] (.) r_i(b),   r_0(b) = in.p[b],
 //   r_i(b) = the rotation of in.p[b] by i (as launch_ks_final_steps computes it),
-// without writing the rotated ciphertexts.  s = [B][n2][2][l+1][N].
+// without writing the rotated ciphertexts.  s = [n2][B][2][l+1][N].
 int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const u64* conv,
                               const StepKeys& keys, const Items& in, const u64* pts, u64* s);
 
 // Inner sums of the baby-step/giant-step product, item b, j < n2:
-//   s[b][j] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
+//   s[j][b] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
 // r_0(b) = in.p[b]; r_i(b) = baby + ((b (n1-1) + i - 1) * 2 (l+1)) N for i >= 1.
-// s = [B][n2][2][l+1][N].  pts in Montgomery form.
+// s = [n2][B][2][l+1][N].  pts in Montgomery form.
 int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s);
 
 // Tensor for squaring: d01 = [B][2][l+1] (c0^2, 2 c0 c1), d2 = [B][l+1] (c1^2).
