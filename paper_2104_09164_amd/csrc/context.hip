@@ -218,18 +218,15 @@ static bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-TraceScope::TraceScope(he_ctx* ctx, int k, double b) : c(ctx), kind(k), bytes(b) {
+TraceScope::TraceScope(he_ctx* ctx, int k, double by) : c(ctx), kind(k), bytes(by) {
   if (!c->tr.on || capturing(c->stream)) return;
   if (c->tr.next + 2 > c->tr.pool.size()) { ++c->tr.dropped; return; }
   a = c->tr.pool[c->tr.next++];
-  hipEventRecord(a, c->stream);
+  b = c->tr.pool[c->tr.next++];
 }
 
 TraceScope::~TraceScope() {
-  if (!a) return;
-  hipEvent_t b = c->tr.pool[c->tr.next++];
-  hipEventRecord(b, c->stream);
-  c->tr.recs.push_back({kind, a, b, bytes});
+  if (a) c->tr.recs.push_back({kind, a, b, bytes});
 }
 
 static int trace_enable(he_ctx* c, bool on) {

@@ -1,6 +1,7 @@
 // Internal structures of the HIP library behind include/he.h.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 #include <map>
 #include <vector>
@@ -141,14 +142,27 @@ void note_hip_error(const char* where, hipError_t e);
 // Brackets one kernel launch with HIP events on the context stream while
 // tracing is on (and the stream is not being captured into a graph);
 // `bytes` = algorithmic bytes of the launch (each word read or written once).
+// With the tracer on (and the stream not capturing), a scope owns two pool
+// events that the launch inside it carries in its dispatch packet
+// (hipExtLaunchKernelGGL): they are stamped when the kernel starts and ends,
+// so the traced time is the kernel's own execution time.
 struct TraceScope {
   he_ctx* c;
   int kind;
   double bytes;
-  hipEvent_t a = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   TraceScope(he_ctx* ctx, int k, double b);
   ~TraceScope();
 };
+
+// Launch on `stream`, carrying the scope's events when it has them.
+#define HE_LAUNCH(ts, kernel, grid, block, stream, ...)                                              \
+  do {                                                                                              \
+    if ((ts).a)                                                                                     \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, (ts).a, (ts).b, 0, __VA_ARGS__);        \
+    else                                                                                            \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                              \
+  } while (0)
 
 // kernel launchers (ntt.hip)
 int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse);

@@ -398,7 +398,7 @@ void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
                               : (S0 == 0 ? (INV ? TK_NTT_INV_A : TK_NTT_FWD_A) : (INV ? TK_NTT_INV_B : TK_NTT_FWD_B));
   TraceScope ts(c, kind, 16.0 * (double)valid_polys(pb) * (double)(1u << LOGN));
   dim3 grid((1u << (LOGN - LP)) / COLS, pb.nitems, pb.npoly);
-  hipLaunchKernelGGL((k_ntt_phase<LOGN, S0, LP, COLS, NT, INV>), grid, dim3(NT), 0, c->stream, pb, c->d_tw, c->d_pc,
+  HE_LAUNCH(ts, (k_ntt_phase<LOGN, S0, LP, COLS, NT, INV>), grid, dim3(NT), c->stream, pb, c->d_tw, c->d_pc,
                      read_src, final_);
 }
 
@@ -427,8 +427,8 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
     if (c->ntt_single_pass) {
       TraceScope ts(c, inv ? TK_NTT15_INV : TK_NTT15_FWD, 16.0 * (double)valid_polys(pb) * (double)(1u << LOGN));
       dim3 grid(pb.nitems, pb.npoly);
-      if (!inv) hipLaunchKernelGGL(k_ntt15<false>, grid, dim3(1024), 0, c->stream, pb, c->d_tw, c->d_pc);
-      else hipLaunchKernelGGL(k_ntt15<true>, grid, dim3(1024), 0, c->stream, pb, c->d_tw, c->d_pc);
+      if (!inv) HE_LAUNCH(ts, (k_ntt15<false>), grid, dim3(1024), c->stream, pb, c->d_tw, c->d_pc);
+      else HE_LAUNCH(ts, (k_ntt15<true>), grid, dim3(1024), c->stream, pb, c->d_tw, c->d_pc);
       return;
     }
   }

@@ -481,14 +481,14 @@ int launch_copy_polys(he_ctx* c, const PolyBatch& pb) {
   u32 nv = 0;
   for (u32 r = 0; r < pb.npoly; ++r) nv += pb.prime[r] != 0xFF;
   TraceScope ts(c, TK_COPY, 2.0 * nv * pb.nitems * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_copy_polys, dim3(c->N / BS / 4, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->N);
+  HE_LAUNCH(ts, k_copy_polys, dim3(c->N / BS / 4, pb.nitems, pb.npoly), dim3(BS), c->stream, pb, c->N);
   return ok();
 }
 
 int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
   TraceScope ts(c, TK_MODUP_CONV, (double)nitems * ((l + 1) + (beta * ne - (l + 1))) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_modup_conv, dim3(c->N / BS, digits_at(c, l), nitems), dim3(BS), 0, c->stream, coef, ext, c->d_pc,
+  HE_LAUNCH(ts, k_modup_conv, dim3(c->N / BS, digits_at(c, l), nitems), dim3(BS), c->stream, coef, ext, c->d_pc,
                      c->d_modup_hatinv, c->d_modup_hatmod, c->N, l, c->nq, c->np, c->alpha, c->dnum);
   return ok();
 }
@@ -499,10 +499,10 @@ int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& o
   TraceScope ts(c, TK_KS_INNER, ((double)nitems * beta * ne + 2.0 * beta * ne + 2.0 * nitems * ne) * (8.0 * (double)c->N));
   dim3 grid(c->N / BS, l + 1 + c->np, 1);
   if (galois != 1)
-    hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
+    HE_LAUNCH(ts, (k_ks_inner<true>), grid, dim3(BS), c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
                        c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
   else
-    hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(BS), 0, c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
+    HE_LAUNCH(ts, (k_ks_inner<false>), grid, dim3(BS), c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
                        c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
   return ok();
 }
@@ -512,7 +512,7 @@ int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64*
   // per item: s_0 (2 polys), per step u and conv (2 + 2) and s_j.c0, 2 polys written
   TraceScope ts(c, TK_KS_FINAL_SUM,
                 ((double)B * (4.0 + 5.0 * S) * (l + 1) + (bias ? l + 1 : 0)) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_ks_final_sum, dim3(c->N / BS, l + 1, B), dim3(BS), 0, c->stream, u, conv, keys, sums, bias, om,
+  HE_LAUNCH(ts, k_ks_final_sum, dim3(c->N / BS, l + 1, B), dim3(BS), c->stream, u, conv, keys, sums, bias, om,
                      c->d_pc, c->d_moddown, c->N, c->log_n, l, c->np, c->nq, B, S);
   return ok();
 }
@@ -523,7 +523,7 @@ int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ex
   TraceScope ts(c, TK_KS_INNER_STEPS,
                 (double)S * ((double)B * beta * ne + 2.0 * beta * ne + 2.0 * B * ne) * (8.0 * (double)c->N));
   dim3 grid(S * (c->N / BS) * ne);
-  hipLaunchKernelGGL(k_ks_inner_steps, grid, dim3(BS), 0, c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,
+  HE_LAUNCH(ts, k_ks_inner_steps, grid, dim3(BS), c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,
                      c->log_n, l,
                      c->nq, c->np, beta, c->dnum, B, c->alpha, S);
   return ok();
@@ -533,7 +533,7 @@ int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u6
                           const Items& add0, const OutMap& om) {
   // per item: u and conv (2 polys each) and add0.c0 read, 2 polys written
   TraceScope ts(c, TK_KS_FINAL_STEPS, (double)S * B * 7.0 * (l + 1) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_ks_final_steps, dim3(c->N / BS, l + 1, S * B), dim3(BS), 0, c->stream, u, conv, keys, add0, om,
+  HE_LAUNCH(ts, k_ks_final_steps, dim3(c->N / BS, l + 1, S * B), dim3(BS), c->stream, u, conv, keys, add0, om,
                      c->d_pc, c->d_moddown, c->N, c->log_n, l, c->np, c->nq, B);
   return ok();
 }
@@ -549,7 +549,7 @@ int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64
                     (8.0 * (double)c->N));
   dim3 grid(B * (n2 / jc) * (c->N / BS) * (l + 1));
 #define HE_LAUNCH_MP(J)                                                                                           \
-  hipLaunchKernelGGL(k_ks_final_mp<J>, grid, dim3(BS), 0, c->stream, u, conv, keys, in, pts, s, c->d_pc,           \
+  HE_LAUNCH(ts, (k_ks_final_mp<J>), grid, dim3(BS), c->stream, u, conv, keys, in, pts, s, c->d_pc,           \
                      c->d_moddown, c->N, c->log_n, l, c->np, c->nq, n1, n2)
   switch (jc) {
     case 8: HE_LAUNCH_MP(8); break;
@@ -563,7 +563,7 @@ int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64
 
 int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv) {
   TraceScope ts(c, TK_MODDOWN_CONV, (double)nitems * (2.0 * c->np + 2.0 * (l + 1)) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_moddown_conv, dim3(c->N / BS, 2, nitems), dim3(BS), 0, c->stream, u, conv, c->d_pc, c->d_moddown,
+  HE_LAUNCH(ts, k_moddown_conv, dim3(c->N / BS, 2, nitems), dim3(BS), c->stream, u, conv, c->d_pc, c->d_moddown,
                      c->N, l, c->nq, c->np);
   return ok();
 }
@@ -575,7 +575,7 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
   if (fa.add1[0]) per += l + 1;
   if (fa.acc[0]) per += 2.0 * (l + 1);
   TraceScope ts(c, TK_KS_FINAL, ((double)nitems * per + (bias ? l + 1 : 0)) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_ks_final, dim3(c->N / BS, l + 1, nitems), dim3(BS), 0, c->stream, u, conv, fa, bias, c->d_pc,
+  HE_LAUNCH(ts, k_ks_final, dim3(c->N / BS, l + 1, nitems), dim3(BS), c->stream, u, conv, fa, bias, c->d_pc,
                      c->d_moddown, c->N, c->log_n, l, c->nq, c->np, galois);
   return ok();
 }
@@ -588,42 +588,42 @@ int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, cons
   const u32 jc = n2 >= 8 ? 8 : n2;
   dim3 grid(in.n * (n2 / jc) * (c->N / BS) * (l + 1));
   switch (jc) {
-    case 8: hipLaunchKernelGGL(k_multplain_acc<8>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    case 4: hipLaunchKernelGGL(k_multplain_acc<4>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    case 2: hipLaunchKernelGGL(k_multplain_acc<2>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    default: hipLaunchKernelGGL(k_multplain_acc<1>, grid, dim3(BS), 0, c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    case 8: HE_LAUNCH(ts, (k_multplain_acc<8>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    case 4: HE_LAUNCH(ts, (k_multplain_acc<4>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    case 2: HE_LAUNCH(ts, (k_multplain_acc<2>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    default: HE_LAUNCH(ts, (k_multplain_acc<1>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
   }
   return ok();
 }
 
 int launch_tensor(he_ctx* c, u32 l, const Items& in, u64* d01, u64* d2) {
   TraceScope ts(c, TK_TENSOR, (double)in.n * 5.0 * (l + 1) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_tensor, dim3(c->N / BS, l + 1, in.n), dim3(BS), 0, c->stream, in, d01, d2, c->d_pc, c->N, l);
+  HE_LAUNCH(ts, k_tensor, dim3(c->N / BS, l + 1, in.n), dim3(BS), c->stream, in, d01, d2, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_rescale_reduce(he_ctx* c, u32 l, u32 nitems, const u64* last, u64* red) {
   TraceScope ts(c, TK_RESCALE_REDUCE, (double)nitems * (2.0 + 2.0 * l) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_rescale_reduce, dim3(c->N / BS, l, 2 * nitems), dim3(BS), 0, c->stream, last, red, c->d_pc, c->N, l);
+  HE_LAUNCH(ts, k_rescale_reduce, dim3(c->N / BS, l, 2 * nitems), dim3(BS), c->stream, last, red, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_rescale_final(he_ctx* c, u32 l, const Items& in, const u64* red, const Items& out) {
   TraceScope ts(c, TK_RESCALE_FINAL, (double)in.n * 6.0 * l * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_rescale_final, dim3(c->N / BS, l, 2 * in.n), dim3(BS), 0, c->stream, in, red, out, c->d_pc,
+  HE_LAUNCH(ts, k_rescale_final, dim3(c->N / BS, l, 2 * in.n), dim3(BS), c->stream, in, red, out, c->d_pc,
                      c->d_rescale, c->N, l, c->nq);
   return ok();
 }
 
 int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& out) {
   TraceScope ts(c, TK_ADD, (double)a.n * 6.0 * (l + 1) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_add, dim3(c->N / BS, 2 * (l + 1), a.n), dim3(BS), 0, c->stream, a, b, out, c->d_pc, c->N, l);
+  HE_LAUNCH(ts, k_add, dim3(c->N / BS, 2 * (l + 1), a.n), dim3(BS), c->stream, a, b, out, c->d_pc, c->N, l);
   return ok();
 }
 
 int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
   TraceScope ts(c, TK_ADD_PLAIN, ((double)ct.n * 2.0 + 1.0) * (l + 1) * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_add_plain, dim3(c->N / BS, l + 1, ct.n), dim3(BS), 0, c->stream, ct, poly, c->d_pc, c->N);
+  HE_LAUNCH(ts, k_add_plain, dim3(c->N / BS, l + 1, ct.n), dim3(BS), c->stream, ct, poly, c->d_pc, c->N);
   return ok();
 }
 
@@ -631,6 +631,6 @@ int launch_to_mont(he_ctx* c, const PolyBatch& pb) {
   u32 nv = 0;
   for (u32 r = 0; r < pb.npoly; ++r) nv += pb.prime[r] != 0xFF;
   TraceScope ts(c, TK_TO_MONT, 2.0 * nv * pb.nitems * (8.0 * (double)c->N));
-  hipLaunchKernelGGL(k_to_mont, dim3(c->N / BS, pb.nitems, pb.npoly), dim3(BS), 0, c->stream, pb, c->d_pc, c->N);
+  HE_LAUNCH(ts, k_to_mont, dim3(c->N / BS, pb.nitems, pb.npoly), dim3(BS), c->stream, pb, c->d_pc, c->N);
   return ok();
 }
