@@ -214,6 +214,8 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   of polynomials (0 = each phase over the whole batch)
  *   "ntt_cols"      two-phase NTT: sub-transforms per workgroup tile, 8, 16
  *                   (default) or 32
+ *   "ntt_cols_b"    the same for the second (row) phase alone: 8, 16, 32, or
+ *                   0 (default) = as "ntt_cols"
  *   "ntt_single_pass"  N = 2^15: 1 = one register-resident launch per
  *                   transform (one HBM pass), 0 (default) = two phases
  *   "trace"         1 = bracket every kernel launch with HIP events on the

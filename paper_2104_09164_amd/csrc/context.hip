@@ -494,6 +494,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ntt_cols = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ntt_cols_b")) {
+    if (value != 0 && value != 8 && value != 16 && value != 32) return HE_EINVAL;
+    c->ntt_cols_b = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "ntt_single_pass")) {
     if (value > 1) return HE_EINVAL;
     c->ntt_single_pass = value;
@@ -534,6 +539,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!c || !key || !value) return HE_EINVAL;
   if (!std::strcmp(key, "ntt_chunk_mb")) { *value = c->ntt_chunk_mb; return HE_OK; }
   if (!std::strcmp(key, "ntt_cols")) { *value = c->ntt_cols; return HE_OK; }
+  if (!std::strcmp(key, "ntt_cols_b")) { *value = c->ntt_cols_b; return HE_OK; }
   if (!std::strcmp(key, "ntt_single_pass")) { *value = c->ntt_single_pass; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;

@@ -98,6 +98,7 @@ struct he_ctx {
   // execution knobs (bit-preserving)
   int64_t ntt_chunk_mb = 0;
   int64_t ntt_cols = 16;      // sub-transforms per NTT workgroup tile: 8, 16 or 32
+  int64_t ntt_cols_b = 0;     // the same for the row phase (0 = ntt_cols)
   int64_t ntt_single_pass = 0;  // N = 2^15: register-resident single-pass transform (off: VALU-bound either way)
 
   Tracer tr;

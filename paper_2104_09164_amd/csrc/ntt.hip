@@ -407,17 +407,43 @@ void launch_phase(he_ctx* c, const PolyBatch& pb, int read_src, int final_) {
 // on chunks of that many MiB of polynomials, so that the intermediate written
 // by phase A can still be in the Infinity Cache when phase B reads it back.
 
+// Phase A (columns) with COLS sub-transforms per tile; phase B (rows) with
+// CB.  Column tiles want >= 16 so each row segment is a full 128-byte line;
+// row tiles are contiguous at any width, and narrower ones give more,
+// smaller workgroups.
 template <int LOGN, int COLS>
-void ntt_two_phase(he_ctx* c, const PolyBatch& ch, bool inv) {
-  constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+void phase_a(he_ctx* c, const PolyBatch& ch, bool inv, int read_src, int final_) {
+  constexpr int LA = (LOGN + 1) / 2;
   constexpr int NTA = ((COLS << LA) / 16) > 512 ? 512 : ((COLS << LA) / 16);
-  constexpr int NTB = ((COLS << LB) / 16) > 512 ? 512 : ((COLS << LB) / 16);
+  if (!inv) launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, ch, read_src, final_);
+  else launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, ch, read_src, final_);
+}
+template <int LOGN, int CB>
+void phase_b(he_ctx* c, const PolyBatch& ch, bool inv, int read_src, int final_) {
+  constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+  constexpr int NTB = ((CB << LB) / 16) > 512 ? 512 : ((CB << LB) / 16);
+  if (!inv) launch_phase<LOGN, LA, LB, CB, NTB, false>(c, ch, read_src, final_);
+  else launch_phase<LOGN, LA, LB, CB, NTB, true>(c, ch, read_src, final_);
+}
+template <int LOGN>
+void ntt_two_phase(he_ctx* c, const PolyBatch& ch, bool inv) {
+  const int ca = (int)c->ntt_cols, cb = c->ntt_cols_b ? (int)c->ntt_cols_b : ca;
+  auto a = [&](int read_src, int final_) {
+    if (ca == 8) phase_a<LOGN, 8>(c, ch, inv, read_src, final_);
+    else if (ca == 32) phase_a<LOGN, 32>(c, ch, inv, read_src, final_);
+    else phase_a<LOGN, 16>(c, ch, inv, read_src, final_);
+  };
+  auto b = [&](int read_src, int final_) {
+    if (cb == 8) phase_b<LOGN, 8>(c, ch, inv, read_src, final_);
+    else if (cb == 32) phase_b<LOGN, 32>(c, ch, inv, read_src, final_);
+    else phase_b<LOGN, 16>(c, ch, inv, read_src, final_);
+  };
   if (!inv) {
-    launch_phase<LOGN, 0, LA, COLS, NTA, false>(c, ch, 1, 0);
-    launch_phase<LOGN, LA, LB, COLS, NTB, false>(c, ch, 0, 1);
+    a(1, 0);
+    b(0, 1);
   } else {
-    launch_phase<LOGN, LA, LB, COLS, NTB, true>(c, ch, 1, 0);
-    launch_phase<LOGN, 0, LA, COLS, NTA, true>(c, ch, 0, 1);
+    b(1, 0);
+    a(0, 1);
   }
 }
 
@@ -450,10 +476,7 @@ void ntt_dispatch(he_ctx* c, const PolyBatch& pb, bool inv) {
         ch.prime[r] = pb.prime[r0 + r];
         ch.row[r] = pb.row[r0 + r];
       }
-      // tile width: sub-transforms per workgroup (knob ntt_cols)
-      if (c->ntt_cols == 8) ntt_two_phase<LOGN, 8>(c, ch, inv);
-      else if (c->ntt_cols == 32) ntt_two_phase<LOGN, 32>(c, ch, inv);
-      else ntt_two_phase<LOGN, 16>(c, ch, inv);
+      ntt_two_phase<LOGN>(c, ch, inv);     // tile widths: knobs ntt_cols, ntt_cols_b
     }
   }
 }

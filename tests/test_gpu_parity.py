@@ -220,6 +220,43 @@ def test_batched_equals_single(setup10):
             assert np.array_equal(ctx.export_ct(rot[i * 2 + u]), o.rotate(c, s, keys).data)
 
 
+def test_hoisted_rotation_groups(setup10):
+    """More (item, step) pairs than one step-batched switch holds (the
+    workspace holds 7 steps; 3 items x 9 steps run as groups of 7 and 2),
+    with an identity step (N/2) in the list: every output against the oracle."""
+    pr, o, keys, ctx = setup10
+    steps = [1, 2, 3, 5, 7, 64, pr.n // 2, 100, -1, 255]
+    cts = [encrypt(o, keys, pr, 40 + i)[1] for i in range(3)]
+    gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+    rot = ctx.rotate_hoisted_batch(gs, steps)
+    for i, c in enumerate(cts):
+        for u, s in enumerate(steps):
+            want = c.data if s == pr.n // 2 else o.rotate(c, s, keys).data
+            assert np.array_equal(ctx.export_ct(rot[i * len(steps) + u]), want), (i, s)
+
+
+def test_full_batch_of_64():
+    """The largest batch (64 ciphertexts) through a dense layer, square and
+    rescale: every item equals its single-ciphertext evaluation; two items
+    against the oracle."""
+    pr = small(10)
+    m, n, n1 = 8, 64, 4
+    o, keys, ctx = make_setup(pr, plan.rotation_steps(m, n, n1), max_batch=64, max_n1=n1, max_n2=m // n1)
+    W = np.random.default_rng(19).normal(0, 0.05, (m, n))
+    b = np.random.default_rng(20).normal(0, 0.05, m)
+    cts = [encrypt(o, keys, pr, 300 + i, width=n)[1] for i in range(64)]
+    lay = o.prepare_dense(W, b, n1, cts[0].level, cts[0].scale)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale)
+    gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+    out = ctx.rescale_batch(ctx.square_batch(ctx.eval_dense_batch(gs, d)))
+    for i in range(64):
+        single = ctx.rescale(ctx.square(ctx.eval_dense(gs[i], d)))
+        assert np.array_equal(ctx.export_ct(out[i]), ctx.export_ct(single)), i
+    for i in (0, 63):
+        want = o.rescale(o.square(o.dense(cts[i], lay, keys), keys))
+        assert np.array_equal(ctx.export_ct(out[i]), want.data)
+
+
 def test_error_codes(setup10):
     he = _he()
     pr, o, keys, ctx = setup10
@@ -239,6 +276,14 @@ def test_error_codes(setup10):
     with pytest.raises(he.HeError) as e:
         ctx.rotate(g, 1, out=g)                         # output aliases the input
     assert e.value.code == -1
+    with pytest.raises(he.HeError) as e:
+        ctx.rotate_hoisted_batch([g] * 5, [1])          # more items than the bound batch (4)
+    assert e.value.code == -6
+    lay_n1 = 16                                         # baby steps beyond the bound workspace (8)
+    d = ctx.dense_load(pr.L, 16, 16, lay_n1, np.zeros((16, pr.L + 1, pr.n), np.uint64), None, 1.0, 1.0)
+    with pytest.raises(he.HeError) as e:
+        ctx.eval_dense(g, d)
+    assert e.value.code == -6
 
 
 def test_network_cfg1_end_to_end():
