@@ -148,7 +148,9 @@ int he_load_keys(he_ctx* ctx, const uint64_t* relin, uint32_t n_rot, const int32
  *            pt_scale, over q_0..q_level only (level-aware encoding).
  *   bias:    host uint64[level+1][N] (the bias replicated with period m, at
  *            scale bias_scale) or NULL.
- * dev: caller-owned device storage >= he_dense_bytes(ctx, level, m, bias!=0).
+ * dev: caller-owned device storage >= he_dense_bytes(ctx, level, m, bias!=0):
+ *      the diagonals in NTT form, their Shoup companions floor(w 2^64 / q)
+ *      (same shape), then the bias in NTT form.
  * *out receives a host handle (free with he_dense_free). Synchronous. */
 int he_dense_load(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
                   const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes,

@@ -209,7 +209,7 @@ static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
     "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner", "moddown_conv", "ks_final", "multplain_acc", "tensor",
     "rescale_reduce", "rescale_final", "add", "add_plain", "copy_polys", "to_mont", "ks_inner_steps",
-    "ks_final_steps", "ks_final_multplain", "ks_final_sum", "modup_conv_steps"};
+    "ks_final_steps", "ks_final_multplain", "ks_final_sum", "modup_conv_steps", "shoup_companion"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
 
@@ -346,7 +346,7 @@ size_t he_key_bytes(const he_ctx* c, uint32_t n_rot) {
 }
 
 size_t he_dense_bytes(const he_ctx* c, uint32_t level, uint32_t m, int has_bias) {
-  return c ? ((size_t)m + (has_bias ? 1 : 0)) * (level + 1) * c->N * sizeof(u64) : 0;
+  return c ? (2 * (size_t)m + (has_bias ? 1 : 0)) * (level + 1) * c->N * sizeof(u64) : 0;
 }
 
 int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t* steps, const uint64_t* const* rot,
@@ -404,12 +404,13 @@ int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1
     for (u32 b = 0; b < pb.nitems; ++b) pb.src[b] = pb.dst[b] = d + (size_t)(k0 + b) * per;
     for (u32 r = 0; r <= level; ++r) pb.prime[r] = (uint8_t)r;
     int rc = launch_ntt(c, pb, false);
-    if (!rc) rc = launch_to_mont(c, pb);
     if (rc) return rc;
   }
+  int rc = launch_shoup_companion(c, m, level, d, d + (size_t)m * per);
+  if (rc) return rc;
   u64* db = nullptr;
   if (bias) {
-    db = d + (size_t)m * per;
+    db = d + (size_t)2 * m * per;
     if (hipMemcpyAsync(db, bias, per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
     PolyBatch pb = one_item(db, level + 1, level + 1, 0);
     int rc = launch_ntt(c, pb, false);

@@ -214,32 +214,43 @@ __global__ void __launch_bounds__(BS) k_ks_final_steps(const u64* __restrict__ u
   out[(size_t)(l + 1 + i) * N + k] = r1;
 }
 
+// Inner-sum accumulation of products pt (.) x, pt with its Shoup companion
+// ps: each product is in [0, 4q).  LAZY (q < 2^55): plain 64-bit sums — at
+// most 65 terms (the baby-step limit) stay below 260 q < 2^64 — reduced once
+// at the end; otherwise the sum is kept below 4q after every term.
+constexpr u64 kLazyMP = 1ull << 55;
+template <bool LAZY>
+__device__ __forceinline__ u64 mp_add(u64 acc, u64 x, u64 pt, u64 ps, const PrimeConst& k) {
+  const u64 p = shoup_lazy4(x, pt, ps, k.q);
+  return LAZY ? acc + p : csub_neg(acc + p, k.nq4);
+}
+template <bool LAZY>
+__device__ __forceinline__ u64 mp_final(u64 acc, const PrimeConst& k) {
+  if (LAZY) acc = shoup_lazy4(acc, 1, k.mu, k.q);   // Shoup product by 1 -> [0, 4q)
+  return csub_neg(csub_neg(acc, k.nq2), k.nq);
+}
+
 // 1-D grid over B x (N/BS, l+1, n2/JC) tiles (items of a tile share its
 // plaintext words).  One thread: coefficient k of limb li of item b, giant
 // sums jc JC .. jc JC + JC - 1; the baby-step values r_i are formed in
 // registers from the key-switch buffers and consumed at once.
-template <int JC>
-__global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, const u64* __restrict__ conv,
-                                                    StepKeys keys, Items in, const u64* __restrict__ pts,
-                                                    u64* __restrict__ sums, const PrimeConst* __restrict__ pc,
-                                                    const u64* __restrict__ md, u32 N, u32 logn, u32 l, u32 np, u32 nq,
-                                                    u32 n1, u32 n2) {
-  const u32 nkb = N / BS, B = in.n;
-  u32 b, tile;
-  xcd_decode(blockIdx.x, B, nkb * (l + 1) * (n2 / JC), b, tile);
-  const u32 k = (tile % nkb) * BS + threadIdx.x;
-  const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
-  const u32 ne = l + 1 + np;
-  const u64 q = pc[li].q, qneg = pc[li].qneg;
+template <int JC, bool LAZY>
+__device__ __forceinline__ void ks_final_mp_body(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                 const StepKeys& keys, const Items& in, const u64* __restrict__ pts,
+                                                 u64* __restrict__ sums, const PrimeConst& pk,
+                                                 const u64* __restrict__ md, u32 N, u32 logn, u32 l, u32 np,
+                                                 u32 nq, u32 n1, u32 n2, u32 b, u32 k, u32 li, u32 jc) {
+  const u32 B = in.n, ne = l + 1 + np;
+  const u64 q = pk.q;
   const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
   const u64 w = pinv[2 * li], wsh = pinv[2 * li + 1];
   const size_t csz = (size_t)2 * (l + 1) * N;
+  const size_t comp = (size_t)n1 * n2 * (l + 1) * N;  // companions follow the m diagonals
   const u64* x = in.p[b];
   u64 r0 = x[(size_t)li * N + k], r1 = x[(size_t)(l + 1 + li) * N + k];
   u64 t0[JC], t1[JC];
-  u128v a0[JC], a1[JC];
 #pragma unroll
-  for (int jj = 0; jj < JC; ++jj) { t0[jj] = t1[jj] = 0; a0[jj] = a1[jj] = {0, 0}; }
+  for (int jj = 0; jj < JC; ++jj) t0[jj] = t1[jj] = 0;
   for (u32 i = 0; i < n1; ++i) {
     if (i > 0) {
       const u32 z = (i - 1) * B + b;
@@ -251,26 +262,36 @@ __global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, c
     }
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) {
-      const u32 kk = n1 * (jc * JC + jj) + i;
-      const u64 pt = pts[((size_t)kk * (l + 1) + li) * N + k];
-      acc_wide(a0[jj], r0, pt);
-      acc_wide(a1[jj], r1, pt);
-    }
-    if ((i & 7) == 7 || i + 1 == n1) {
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj) {
-        t0[jj] = add_mod(t0[jj], redc(a0[jj], q, qneg), q);
-        t1[jj] = add_mod(t1[jj], redc(a1[jj], q, qneg), q);
-        a0[jj] = a1[jj] = {0, 0};
-      }
+      const size_t o = ((size_t)(n1 * (jc * JC + jj) + i) * (l + 1) + li) * N + k;
+      const u64 pt = pts[o], ps = pts[comp + o];
+      t0[jj] = mp_add<LAZY>(t0[jj], r0, pt, ps, pk);
+      t1[jj] = mp_add<LAZY>(t1[jj], r1, pt, ps, pk);
     }
   }
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
     u64* o = sums + ((size_t)(jc * JC + jj) * B + b) * csz;
-    o[(size_t)li * N + k] = t0[jj];
-    o[(size_t)(l + 1 + li) * N + k] = t1[jj];
+    o[(size_t)li * N + k] = mp_final<LAZY>(t0[jj], pk);
+    o[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(t1[jj], pk);
   }
+}
+
+template <int JC>
+__global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, const u64* __restrict__ conv,
+                                                    StepKeys keys, Items in, const u64* __restrict__ pts,
+                                                    u64* __restrict__ sums, const PrimeConst* __restrict__ pc,
+                                                    const u64* __restrict__ md, u32 N, u32 logn, u32 l, u32 np, u32 nq,
+                                                    u32 n1, u32 n2) {
+  const u32 nkb = N / BS;
+  u32 b, tile;
+  xcd_decode(blockIdx.x, in.n, nkb * (l + 1) * (n2 / JC), b, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x;
+  const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
+  const PrimeConst pk = pc[li];
+  if (pk.q < kLazyMP)
+    ks_final_mp_body<JC, true>(u, conv, keys, in, pts, sums, pk, md, N, logn, l, np, nq, n1, n2, b, k, li, jc);
+  else
+    ks_final_mp_body<JC, false>(u, conv, keys, in, pts, sums, pk, md, N, logn, l, np, nq, n1, n2, b, k, li, jc);
 }
 
 // grid: (N/BS, l+1, B).  One thread: coefficient k of limb i of item b, all
@@ -358,6 +379,34 @@ __global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, cons
   fa.out[b][o1] = r1;
 }
 
+template <int JC, bool LAZY>
+__device__ __forceinline__ void multplain_body(const Items& in, const u64* __restrict__ baby,
+                                               const u64* __restrict__ pts, u64* __restrict__ s, const PrimeConst& pk,
+                                               u32 N, u32 l, u32 n1, u32 n2, u32 b, u32 k, u32 li, u32 jc) {
+  const size_t csz = (size_t)2 * (l + 1) * N;
+  const size_t comp = (size_t)n1 * n2 * (l + 1) * N;
+  u64 t0[JC], t1[JC];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) t0[jj] = t1[jj] = 0;
+  for (u32 i = 0; i < n1; ++i) {
+    const u64* r = i == 0 ? in.p[b] : baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
+    const u64 r0 = r[(size_t)li * N + k], r1 = r[(size_t)(l + 1 + li) * N + k];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const size_t o = ((size_t)(n1 * (jc * JC + jj) + i) * (l + 1) + li) * N + k;
+      const u64 pt = pts[o], ps = pts[comp + o];
+      t0[jj] = mp_add<LAZY>(t0[jj], r0, pt, ps, pk);
+      t1[jj] = mp_add<LAZY>(t1[jj], r1, pt, ps, pk);
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
+    o[(size_t)li * N + k] = mp_final<LAZY>(t0[jj], pk);
+    o[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(t1[jj], pk);
+  }
+}
+
 template <int JC>
 __global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __restrict__ baby,
                                                       const u64* __restrict__ pts, u64* __restrict__ s,
@@ -370,39 +419,9 @@ __global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __res
   xcd_decode(blockIdx.x, in.n, nkb * (l + 1) * (n2 / JC), b, tile);
   const u32 k = (tile % nkb) * BS + threadIdx.x;
   const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
-  const u32 nch = n2 / JC;
-  const u64 q = pc[li].q, qneg = pc[li].qneg;
-  const size_t csz = (size_t)2 * (l + 1) * N;
-  u64 t0[JC], t1[JC];
-  u128v a0[JC], a1[JC];
-#pragma unroll
-  for (int jj = 0; jj < JC; ++jj) { t0[jj] = t1[jj] = 0; a0[jj] = a1[jj] = {0, 0}; }
-  for (u32 i = 0; i < n1; ++i) {
-    const u64* r = i == 0 ? in.p[b] : baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
-    const u64 r0 = r[(size_t)li * N + k], r1 = r[(size_t)(l + 1 + li) * N + k];
-#pragma unroll
-    for (int jj = 0; jj < JC; ++jj) {
-      const u32 kk = n1 * (jc * JC + jj) + i;
-      const u64 pt = pts[((size_t)kk * (l + 1) + li) * N + k];
-      acc_wide(a0[jj], r0, pt);
-      acc_wide(a1[jj], r1, pt);
-    }
-    if ((i & 7) == 7 || i + 1 == n1) {
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj) {
-        t0[jj] = add_mod(t0[jj], redc(a0[jj], q, qneg), q);
-        t1[jj] = add_mod(t1[jj], redc(a1[jj], q, qneg), q);
-        a0[jj] = a1[jj] = {0, 0};
-      }
-    }
-  }
-  (void)nch;
-#pragma unroll
-  for (int jj = 0; jj < JC; ++jj) {
-    u64* o = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
-    o[(size_t)li * N + k] = t0[jj];
-    o[(size_t)(l + 1 + li) * N + k] = t1[jj];
-  }
+  const PrimeConst pk = pc[li];
+  if (pk.q < kLazyMP) multplain_body<JC, true>(in, baby, pts, s, pk, N, l, n1, n2, b, k, li, jc);
+  else multplain_body<JC, false>(in, baby, pts, s, pk, N, l, n1, n2, b, k, li, jc);
 }
 
 // grid: (N/BS, l+1, B)
@@ -470,6 +489,25 @@ __global__ void __launch_bounds__(BS) k_to_mont(PolyBatch pb, const PrimeConst* 
   if (pr == 0xFF) return;
   u64* x = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
   x[k] = redc(mul_wide(x[k], pc[pr].r2), pc[pr].q, pc[pr].qneg);
+}
+
+// comp = floor(w 2^64 / q) by restoring long division of w 2^64 (w < q < 2^61:
+// the running remainder stays below 2q < 2^62).  grid (N/BS, level+1, m).
+__global__ void __launch_bounds__(BS) k_shoup_companion(const u64* __restrict__ pts, u64* __restrict__ comp,
+                                                        const PrimeConst* __restrict__ pc, u32 N, u32 level) {
+  const u32 k = blockIdx.x * BS + threadIdx.x, r = blockIdx.y, i = blockIdx.z;
+  const size_t o = ((size_t)i * (level + 1) + r) * N + k;
+  const u64 q = pc[r].q;
+  u64 rem = pts[o], quo = 0;
+  for (int bit = 63; bit >= 0; --bit) {
+    rem <<= 1;
+    quo <<= 1;
+    if (rem >= q) {
+      rem -= q;
+      quo |= 1;
+    }
+  }
+  comp[o] = quo;
 }
 
 inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
@@ -545,7 +583,7 @@ int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64
   // per item: the input ciphertext, u and conv of every baby step (2 + 2 polys)
   // and its rotated c0 source limb, the n2 sums written; plaintexts once
   TraceScope ts(c, TK_KS_FINAL_MP,
-                ((double)B * (2.0 + 5.0 * (n1 - 1) + 2.0 * n2) * (l + 1) + (double)n1 * n2 * (l + 1)) *
+                ((double)B * (2.0 + 5.0 * (n1 - 1) + 2.0 * n2) * (l + 1) + 2.0 * n1 * n2 * (l + 1)) *
                     (8.0 * (double)c->N));
   dim3 grid(B * (n2 / jc) * (c->N / BS) * (l + 1));
 #define HE_LAUNCH_MP(J)                                                                                           \
@@ -582,7 +620,7 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
 
 int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s) {
   TraceScope ts(c, TK_MULTPLAIN,
-                ((double)in.n * (n1 + n2) * 2.0 * (l + 1) + (double)n1 * n2 * (l + 1)) * (8.0 * (double)c->N));
+                ((double)in.n * (n1 + n2) * 2.0 * (l + 1) + 2.0 * n1 * n2 * (l + 1)) * (8.0 * (double)c->N));
   // all giant-step sums of a thread in registers (up to 8) so every baby-step
   // ciphertext is read once per batch
   const u32 jc = n2 >= 8 ? 8 : n2;
@@ -624,6 +662,12 @@ int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& ou
 int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
   TraceScope ts(c, TK_ADD_PLAIN, ((double)ct.n * 2.0 + 1.0) * (l + 1) * (8.0 * (double)c->N));
   HE_LAUNCH(ts, k_add_plain, dim3(c->N / BS, l + 1, ct.n), dim3(BS), c->stream, ct, poly, c->d_pc, c->N);
+  return ok();
+}
+
+int launch_shoup_companion(he_ctx* c, u32 m, u32 level, const u64* pts, u64* comp) {
+  TraceScope ts(c, TK_SHOUP_COMPANION, 2.0 * m * (level + 1) * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_shoup_companion, dim3(c->N / BS, level + 1, m), dim3(BS), c->stream, pts, comp, c->d_pc, c->N, level);
   return ok();
 }
 
