@@ -70,6 +70,15 @@ u32 galois_of(const he_ctx* c, int64_t step) {
   return (u32)g;
 }
 
+// g^{-1} mod 2N: the group of odd residues mod 2N has order N, so g^{N-1}.
+u32 galois_inverse(const he_ctx* c, u32 g) {
+  const u64 m = 2ull * c->N;
+  u64 r = 1, b = g;
+  for (u64 e = c->N - 1; e; e >>= 1, b = b * b % m)
+    if (e & 1) r = r * b % m;
+  return (u32)r;
+}
+
 PolyBatch batch_of(u32 nitems) {
   PolyBatch pb;
   std::memset(&pb, 0, sizeof(pb));
@@ -291,6 +300,7 @@ int he_rotate_hoisted_batch(he_ctx* c, uint32_t n, const he_ct* in, uint32_t n_s
       const u32 s = keyed[g0 + i];
       sk.key[i] = keys[s]->dev;
       sk.galois[i] = keys[s]->galois;
+      sk.galois_inv[i] = galois_inverse(c, keys[s]->galois);
       for (u32 b = 0; b < n; ++b) om.ptr[i * n + b] = out[b * n_steps + s].dev;
     }
     if ((rc = ks_steps(c, l, n, S, w, c1, sk, add0, om))) return rc;
@@ -443,6 +453,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     for (u32 i = 0; i < S; ++i) {
       sk.key[i] = baby[i + 1]->dev;
       sk.galois[i] = baby[i + 1]->galois;
+      sk.galois_inv[i] = galois_inverse(c, baby[i + 1]->galois);
     }
     if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
     if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
@@ -468,6 +479,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     for (u32 j = 0; j < J; ++j) {
       sk.key[j] = giant[j + 1]->dev;
       sk.galois[j] = giant[j + 1]->galois;
+      sk.galois_inv[j] = galois_inverse(c, giant[j + 1]->galois);
     }
     OwnMap own;
     std::memset(&own, 0, sizeof(own));

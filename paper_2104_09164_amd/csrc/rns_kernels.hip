@@ -132,7 +132,11 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
 }
 
 // 1-D grid over S x (N/BS, ne) tiles: the steps of a tile share its extended
-// digits (xcd_decode).
+// digits (xcd_decode).  The automorphism moves to the output side: with
+// k' = perm_{g^{-1}}(k), u_s[k'] = sum_j d_j[k] ksk_{s,j}[k'] equals
+// sum_j d_j[perm_g(k')] ksk_{s,j}[k'], so every step reads the same
+// (unpermuted) digit words of a tile, from L2 after the first step, and
+// gathers its key and scatters its output within the same aligned groups.
 __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, u32 ext_items, OwnMap own,
                                                        StepKeys keys,
                                                        u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
@@ -144,12 +148,12 @@ __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ e
   const u32 k = (tile % nkb) * BS + threadIdx.x, t = tile / nkb;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
   const u64 q = pc[pr].q, qneg = pc[pr].qneg;
-  const u32 ks = galois_perm(k, keys.galois[s], logn);
+  const u32 ko = galois_perm(k, keys.galois_inv[s], logn);    // output (and key) position
   const u64* key = keys.key[s];
   u64 kb[8], ka[8];
   for (u32 j = 0; j < beta; ++j) {
-    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + k];
-    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
+    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + ko];
+    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + ko];
   }
   const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
   u64* ub = u + (size_t)s * nitems * 2 * ne * N;
@@ -158,20 +162,20 @@ __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ e
   u32 b = 0;
   for (; b + 2 <= nitems; b += 2) {
     u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
-    const u64* e0 = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e0 = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + k;
     const u64* e1 = e0 + (size_t)dstride * ne * N;
     const u64* o0 = ob ? ob + b * own.ob : own.ptr[b];
     const u64* o1 = ob ? ob + (b + 1) * own.ob : own.ptr[b + 1];
     for (u32 j = 0; j < beta; ++j) {
       const bool own_j = j == own_digit;
-      const u64 x0 = own_j ? o0[(size_t)t * N + ks] : e0[(size_t)j * ne * N];
-      const u64 x1 = own_j ? o1[(size_t)t * N + ks] : e1[(size_t)j * ne * N];
+      const u64 x0 = own_j ? o0[(size_t)t * N + k] : e0[(size_t)j * ne * N];
+      const u64 x1 = own_j ? o1[(size_t)t * N + k] : e1[(size_t)j * ne * N];
       acc_wide(sb0, x0, kb[j]);
       acc_wide(sa0, x0, ka[j]);
       acc_wide(sb1, x1, kb[j]);
       acc_wide(sa1, x1, ka[j]);
     }
-    u64* o = ub + ((size_t)b * 2 * ne + t) * N + k;
+    u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
     o[0] = redc(sb0, q, qneg);
     o[(size_t)ne * N] = redc(sa0, q, qneg);
     o += (size_t)2 * ne * N;
@@ -180,14 +184,14 @@ __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ e
   }
   if (b < nitems) {
     u128v sb = {0, 0}, sa = {0, 0};
-    const u64* e = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
+    const u64* e = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + k;
     const u64* src = ob ? ob + b * own.ob : own.ptr[b];
     for (u32 j = 0; j < beta; ++j) {
-      const u64 x = j == own_digit ? src[(size_t)t * N + ks] : e[(size_t)j * ne * N];
+      const u64 x = j == own_digit ? src[(size_t)t * N + k] : e[(size_t)j * ne * N];
       acc_wide(sb, x, kb[j]);
       acc_wide(sa, x, ka[j]);
     }
-    u64* o = ub + ((size_t)b * 2 * ne + t) * N + k;
+    u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
     o[0] = redc(sb, q, qneg);
     o[(size_t)ne * N] = redc(sa, q, qneg);
   }
@@ -558,8 +562,9 @@ int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64*
 int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ext_items, const OwnMap& own,
                           const StepKeys& keys, u64* u) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
-  TraceScope ts(c, TK_KS_INNER_STEPS,
-                (double)S * ((double)B * beta * ne + 2.0 * beta * ne + 2.0 * B * ne) * (8.0 * (double)c->N));
+  // digits: once per item when the steps share them (hoisted), once per (step, item) otherwise
+  const double digits = (double)(ext_items ? S : 1) * B * beta * ne;
+  TraceScope ts(c, TK_KS_INNER_STEPS, (digits + (double)S * (2.0 * beta * ne + 2.0 * B * ne)) * (8.0 * (double)c->N));
   dim3 grid(S * (c->N / BS) * ne);
   HE_LAUNCH(ts, k_ks_inner_steps, grid, dim3(BS), c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,
                      c->log_n, l,

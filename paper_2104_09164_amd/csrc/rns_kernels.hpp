@@ -50,7 +50,8 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
 #define HE_MAX_STEPS 64
 struct StepKeys {
   const u64* key[HE_MAX_STEPS];   // rotation key of step s ([dnum][2][L+1+K][N], Montgomery form)
-  u32 galois[HE_MAX_STEPS];       // its Galois element
+  u32 galois[HE_MAX_STEPS];       // its Galois element g
+  u32 galois_inv[HE_MAX_STEPS];   // g^{-1} mod 2N
 };
 // Source c1 (NTT form) of item (s, b), whose digits' own limbs the inner
 // product reads: base + s os + b ob when base is set, else ptr[b] (same for every s).
