@@ -255,7 +255,8 @@ KERNEL_LABEL = {
     "ks_final": "key-switch epilogue ((u - conv) P^-1 + sigma(c0) + accumulators)",
     "ks_inner_steps": "key-switch inner product, all hoisted steps of a batch in one launch",
     "ks_final_steps": "key-switch epilogue, all hoisted steps of a batch in one launch",
-    "multplain_acc": "MultPlain inner sums over baby-step ciphertexts",
+    "multplain": "MultPlain inner sums (one baby step)",
+    "ks_final_multplain": "baby-step key-switch epilogue folded into the MultPlain inner sums",
 }
 
 
@@ -439,8 +440,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one MI355X: this build has no multi-GPU path (requests shard across GPUs "
-              "with no exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one MI355X: the library has no multi-GPU path (requests would shard across "
+              "GPUs with no exchange between them). Run with --gpus 1.", file=sys.stderr)
         return 2
     import torch
     if args.ntt_only:

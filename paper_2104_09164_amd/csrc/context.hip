@@ -207,7 +207,7 @@ thread_local char g_last_error[256] = "";
 
 static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
-    "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner", "moddown_conv", "ks_final", "multplain_acc", "tensor",
+    "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner", "moddown_conv", "ks_final", "multplain", "tensor",
     "rescale_reduce", "rescale_final", "add", "add_plain", "copy_polys", "to_mont", "ks_inner_steps",
     "ks_final_steps", "ks_final_multplain", "ks_final_sum", "modup_conv_steps", "shoup_companion"};
 

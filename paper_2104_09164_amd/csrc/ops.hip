@@ -11,7 +11,7 @@ namespace {
 // Workspace regions for a batch of up to B ciphertexts (sizes in limb-polys,
 // computed at the top level L so that the layout does not depend on the level).
 struct WS {
-  u64 *rtmp, *coef, *ext, *u, *conv, *d01, *d2, *red, *baby, *giant, *z0, *z1;
+  u64 *rtmp, *coef, *ext, *u, *conv, *d01, *d2, *red, *giant, *z0, *z1;
 };
 
 // Rotation steps per step-batched key switch: the baby steps of the widest
@@ -40,7 +40,6 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   take(&x.d01, B * csz);
   take(&x.d2, B * L1 * N);
   take(&x.red, B * csz);
-  take(&x.baby, 0);   // baby-step rotations are folded into the inner sums, never stored
   take(&x.giant, B * (n2 ? n2 : 1) * csz);
   take(&x.z0, B * csz);
   take(&x.z1, B * csz);
@@ -445,7 +444,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     // Baby steps i = 1 .. n1-1 (all below N/2, so each has a key): one hoisted
     // ModUp, then one step-batched key switch whose epilogue forms each
     // rotated ciphertext in registers and folds it straight into the inner
-    // sums s_j (giant region [B][n2][csz]); the rotations are never stored.
+    // sums s_j (giant region [n2][B][csz]); the rotations are never stored.
     // The workspace holds ks_group(max_n1) >= n1 - 1 steps.
     if ((rc = modup(c, l, n, c1in, w))) return rc;
     const u32 S = n1 - 1;
@@ -457,7 +456,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     }
     if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
     if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
-  } else if ((rc = launch_multplain_acc(c, l, n1, n2, inI, nullptr, d->pts, w.giant))) {
+  } else if ((rc = launch_multplain(c, l, n2, inI, d->pts, w.giant))) {
     return rc;                                     // n1 = 1: s_j = pts[j] (.) in
   }
 

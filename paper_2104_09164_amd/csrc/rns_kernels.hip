@@ -383,49 +383,27 @@ __global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, cons
   fa.out[b][o1] = r1;
 }
 
-template <int JC, bool LAZY>
-__device__ __forceinline__ void multplain_body(const Items& in, const u64* __restrict__ baby,
-                                               const u64* __restrict__ pts, u64* __restrict__ s, const PrimeConst& pk,
-                                               u32 N, u32 l, u32 n1, u32 n2, u32 b, u32 k, u32 li, u32 jc) {
-  const size_t csz = (size_t)2 * (l + 1) * N;
-  const size_t comp = (size_t)n1 * n2 * (l + 1) * N;
-  u64 t0[JC], t1[JC];
-#pragma unroll
-  for (int jj = 0; jj < JC; ++jj) t0[jj] = t1[jj] = 0;
-  for (u32 i = 0; i < n1; ++i) {
-    const u64* r = i == 0 ? in.p[b] : baby + ((size_t)b * (n1 - 1) + (i - 1)) * csz;
-    const u64 r0 = r[(size_t)li * N + k], r1 = r[(size_t)(l + 1 + li) * N + k];
-#pragma unroll
-    for (int jj = 0; jj < JC; ++jj) {
-      const size_t o = ((size_t)(n1 * (jc * JC + jj) + i) * (l + 1) + li) * N + k;
-      const u64 pt = pts[o], ps = pts[comp + o];
-      t0[jj] = mp_add<LAZY>(t0[jj], r0, pt, ps, pk);
-      t1[jj] = mp_add<LAZY>(t1[jj], r1, pt, ps, pk);
-    }
-  }
-#pragma unroll
-  for (int jj = 0; jj < JC; ++jj) {
-    u64* o = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
-    o[(size_t)li * N + k] = mp_final<LAZY>(t0[jj], pk);
-    o[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(t1[jj], pk);
-  }
-}
-
+// 1-D grid over B x (N/BS, l+1, n2/JC) tiles: the items of a tile share its
+// plaintext words (xcd_decode).  One product per giant sum: s_j = pts[j] (.) in.
 template <int JC>
-__global__ void __launch_bounds__(BS) k_multplain_acc(Items in, const u64* __restrict__ baby,
-                                                      const u64* __restrict__ pts, u64* __restrict__ s,
-                                                      const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n1,
-                                                      u32 n2) {
-  // 1-D grid over B x (N/BS, l+1, n2/JC) tiles: the items of a tile share
-  // its plaintext words (xcd_decode)
+__global__ void __launch_bounds__(BS) k_multplain(Items in, const u64* __restrict__ pts, u64* __restrict__ s,
+                                                  const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n2) {
   const u32 nkb = N / BS;
   u32 b, tile;
   xcd_decode(blockIdx.x, in.n, nkb * (l + 1) * (n2 / JC), b, tile);
   const u32 k = (tile % nkb) * BS + threadIdx.x;
   const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
   const PrimeConst pk = pc[li];
-  if (pk.q < kLazyMP) multplain_body<JC, true>(in, baby, pts, s, pk, N, l, n1, n2, b, k, li, jc);
-  else multplain_body<JC, false>(in, baby, pts, s, pk, N, l, n1, n2, b, k, li, jc);
+  const size_t csz = (size_t)2 * (l + 1) * N, comp = (size_t)n2 * (l + 1) * N;
+  const u64 r0 = in.p[b][(size_t)li * N + k], r1 = in.p[b][(size_t)(l + 1 + li) * N + k];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    const size_t o = ((size_t)(jc * JC + jj) * (l + 1) + li) * N + k;
+    const u64 pt = pts[o], ps = pts[comp + o];
+    u64* out = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
+    out[(size_t)li * N + k] = mp_final<false>(shoup_lazy4(r0, pt, ps, pk.q), pk);
+    out[(size_t)(l + 1 + li) * N + k] = mp_final<false>(shoup_lazy4(r1, pt, ps, pk.q), pk);
+  }
 }
 
 // grid: (N/BS, l+1, B)
@@ -623,18 +601,16 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
   return ok();
 }
 
-int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s) {
-  TraceScope ts(c, TK_MULTPLAIN,
-                ((double)in.n * (n1 + n2) * 2.0 * (l + 1) + 2.0 * n1 * n2 * (l + 1)) * (8.0 * (double)c->N));
-  // all giant-step sums of a thread in registers (up to 8) so every baby-step
-  // ciphertext is read once per batch
-  const u32 jc = n2 >= 8 ? 8 : n2;
+int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u64* s) {
+  TraceScope ts(c, TK_MULTPLAIN, ((double)in.n * (1 + n2) * 2.0 * (l + 1) + 2.0 * n2 * (l + 1)) * (8.0 * (double)c->N));
+  const u32 jc = n2 >= 8 ? 8 : (n2 >= 4 ? 4 : (n2 >= 2 ? 2 : 1));
+  if (n2 % jc) return HE_EINVAL;
   dim3 grid(in.n * (n2 / jc) * (c->N / BS) * (l + 1));
   switch (jc) {
-    case 8: HE_LAUNCH(ts, (k_multplain_acc<8>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    case 4: HE_LAUNCH(ts, (k_multplain_acc<4>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    case 2: HE_LAUNCH(ts, (k_multplain_acc<2>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
-    default: HE_LAUNCH(ts, (k_multplain_acc<1>), grid, dim3(BS), c->stream, in, baby, pts, s, c->d_pc, c->N, l, n1, n2); break;
+    case 8: HE_LAUNCH(ts, (k_multplain<8>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
+    case 4: HE_LAUNCH(ts, (k_multplain<4>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
+    case 2: HE_LAUNCH(ts, (k_multplain<2>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
+    default: HE_LAUNCH(ts, (k_multplain<1>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
   }
   return ok();
 }

@@ -89,12 +89,10 @@ int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64*
 int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const u64* conv,
                               const StepKeys& keys, const Items& in, const u64* pts, u64* s);
 
-// Inner sums of the baby-step/giant-step product, item b, j < n2:
-//   s[j][b] = sum_{i < n1} pts[n1 j + i] (.) r_i(b)      (both polynomials)
-// r_0(b) = in.p[b]; r_i(b) = baby + ((b (n1-1) + i - 1) * 2 (l+1)) N for i >= 1.
-// s = [n2][B][2][l+1][N].  pts in NTT form followed by their Shoup
-// companions (he_dense layout).
-int launch_multplain_acc(he_ctx* c, u32 l, u32 n1, u32 n2, const Items& in, const u64* baby, const u64* pts, u64* s);
+// Inner sums with one baby step (n1 = 1), item b, j < n2:
+//   s[j][b] = pts[j] (.) in.p[b]   (both polynomials), s = [n2][B][2][l+1][N];
+// pts in NTT form followed by their Shoup companions (he_dense layout).
+int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u64* s);
 
 // comp[i][r][k] = floor(pts[i][r][k] 2^64 / q_r) for m diagonals of limbs r <= level
 // (the Shoup companions of the plaintext words; exact long division).
