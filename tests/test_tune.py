@@ -54,3 +54,41 @@ def test_knobs_preserve_bits():
         out = ctx.rescale_batch(ctx.square_batch(ctx.eval_dense_batch(gs, d)))
         for g, w in zip(out, want):
             assert np.array_equal(ctx.export_ct(g), w), knobs
+
+
+def test_knob_space_is_bit_preserving_and_valid():
+    # every tuned key is a documented knob and every value one the library accepts
+    assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass"}
+    assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
+    assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
+    assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
+
+
+@pytest.mark.gpu
+def test_knob_api_validation():
+    from paper_2104_09164_amd import he
+    q, p = he.prime_chain(12, [50, 40], [50])
+    ctx = he.Context(12, q, p, 1)
+    defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "trace": 0}
+    for k, v in defaults.items():
+        assert ctx.get_knob(k) == v
+    for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("trace", 3), ("ntt_chunk_mb", -1),
+                   ("no_such_knob", 1)]:
+        with pytest.raises(he.HeError) as e:
+            ctx.set_knob(k, bad)
+        assert e.value.code == -1
+        if k in defaults:
+            assert ctx.get_knob(k) == defaults[k]          # a rejected value leaves the knob unchanged
+    ctx.set_knob("ntt_cols_b", 32)
+    assert ctx.get_knob("ntt_cols_b") == 32
+    # the tracer records nothing while off and everything while on
+    assert ctx.trace_read() == {}
+    import torch
+    x = torch.zeros(2 * (1 << 12), dtype=torch.int64, device="cuda")
+    ctx.set_knob("trace", 1)
+    ctx.ntt([x], 0, 2, inverse=False)
+    tab = ctx.trace_read()
+    ctx.set_knob("trace", 0)
+    assert tab["ntt_fwd_onepass"][0] == 1 and tab["ntt_fwd_onepass"][2] == 2 * (1 << 12) * 16
+    ctx.ntt([x], 0, 2, inverse=False)
+    assert ctx.trace_read() == {}
