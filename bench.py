@@ -251,9 +251,8 @@ KERNEL_LABEL = {
     "ntt_fwd_phaseB": "forward NTT, phase B (row transforms)",
     "ntt_inv_phaseB": "inverse NTT, phase B (row transforms)",
     "ntt_inv_phaseA": "inverse NTT, phase A (column transforms, N^-1)",
-    "ks_inner": "key-switch inner product (eval-key x extended digits, automorphism gather)",
     "ks_final": "key-switch epilogue ((u - conv) P^-1 + sigma(c0) + accumulators)",
-    "ks_inner_steps": "key-switch inner product, all hoisted steps of a batch in one launch",
+    "ks_inner_steps": "key-switch inner product (eval keys x extended digits, automorphism), every step of a batch in one launch",
     "ks_final_steps": "key-switch epilogue, all hoisted steps of a batch in one launch",
     "multplain": "MultPlain inner sums (one baby step)",
     "ks_final_multplain": "baby-step key-switch epilogue folded into the MultPlain inner sums",

@@ -134,7 +134,9 @@ int he_ctx_bind(he_ctx* ctx, void* workspace_dev, size_t bytes, uint32_t max_bat
  * q_0..q_L then p_0..p_{K-1}, with b_j = -a_j s + e_j + g_j s' and gadget
  * g_j = P (Q/Q_j) [(Q/Q_j)^{-1}]_{Q_j}.  relin (s' = s^2) may be NULL if
  * he_square is never called.  rot[u] is the key of the left rotation by
- * steps[u] (s' = s(X^(5^steps[u]))).  Synchronous; replaces earlier keys. */
+ * steps[u] (s' = s(X^(5^steps[u]))).  Stored per key: the NTT form, then
+ * the Shoup companions floor(w 2^64 / q) of its words (2x the host size).
+ * Synchronous; replaces earlier keys. */
 int he_load_keys(he_ctx* ctx, const uint64_t* relin, uint32_t n_rot, const int32_t* steps,
                  const uint64_t* const* rot, void* key_dev, size_t key_bytes);
 

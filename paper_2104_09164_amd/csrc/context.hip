@@ -207,9 +207,9 @@ thread_local char g_last_error[256] = "";
 
 static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
-    "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner", "moddown_conv", "ks_final", "multplain", "tensor",
-    "rescale_reduce", "rescale_final", "add", "add_plain", "copy_polys", "to_mont", "ks_inner_steps",
-    "ks_final_steps", "ks_final_multplain", "ks_final_sum", "modup_conv_steps", "shoup_companion"};
+    "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner_steps", "moddown_conv", "ks_final", "ks_final_steps",
+    "ks_final_multplain", "ks_final_sum", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
+    "add_plain", "copy_polys", "shoup_companion"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
 
@@ -342,7 +342,7 @@ size_t he_ct_bytes(const he_ctx* c, uint32_t level) {
 }
 
 size_t he_key_bytes(const he_ctx* c, uint32_t n_rot) {
-  return c ? (size_t)(1 + n_rot) * c->dnum * 2 * nt_of(c) * c->N * sizeof(u64) : 0;
+  return c ? (size_t)(1 + n_rot) * 2 * c->dnum * 2 * nt_of(c) * c->N * sizeof(u64) : 0;
 }
 
 size_t he_dense_bytes(const he_ctx* c, uint32_t level, uint32_t m, int has_bias) {
@@ -366,7 +366,8 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
     PolyBatch pb = one_item(dst, npoly, nt_of(c), 0);
     int rc = launch_ntt(c, pb, false);
     if (rc) return rc;
-    return launch_to_mont(c, pb);
+    // Shoup companions of every key word, limb t over prime t of q_0..q_L, p_0..p_{K-1}
+    return launch_shoup_companion(c, c->dnum * 2, nt_of(c) - 1, dst, dst + words);
   };
   int rc;
   if (relin) {
@@ -376,7 +377,7 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
   }
   const u64 two_n = 2ull * c->N;
   for (u32 u = 0; u < n_rot; ++u) {
-    u64* dst = base + (size_t)(1 + u) * words;
+    u64* dst = base + (size_t)(1 + u) * 2 * words;
     if ((rc = put(dst, rot[u]))) return rc;
     const int64_t half = c->N / 2;
     const u64 r = (u64)(((steps[u] % half) + half) % half);

@@ -48,8 +48,9 @@ struct PolyBatch {
 // Kernel classes of the tracer (he_trace_read aggregates per class).
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
-  TK_MODUP_CONV, TK_KS_INNER, TK_MODDOWN_CONV, TK_KS_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE,
-  TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_TO_MONT, TK_KS_INNER_STEPS, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM, TK_MODUP_CONV_STEPS, TK_SHOUP_COMPANION, TK_COUNT
+  TK_MODUP_CONV, TK_KS_INNER_STEPS, TK_MODDOWN_CONV, TK_KS_FINAL, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM,
+  TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
+  TK_COUNT
 };
 const char* trace_name(int kind);
 
@@ -70,7 +71,7 @@ struct Tracer {
 struct KeySlot {
   int32_t step;
   u32 galois;
-  u64* dev;         // [dnum][2][L+1+K][N], NTT form, Montgomery form
+  u64* dev;         // [dnum][2][L+1+K][N] NTT form, then their Shoup companions (same shape)
 };
 
 struct he_ctx {

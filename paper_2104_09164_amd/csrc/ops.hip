@@ -140,16 +140,24 @@ int modup_strided(he_ctx* c, u32 l, u32 BB, const u64* c1_base, size_t c1_stride
   return launch_ntt(c, nt, false);
 }
 
+OwnMap own_of(u32 B, u64* const* c1) {
+  OwnMap own;
+  std::memset(&own, 0, sizeof(own));
+  for (u32 b = 0; b < B; ++b) own.ptr[b] = c1[b];
+  return own;
+}
+
 // Key switch of the digits in w.ext (own limbs from c1) with `key`
 // (automorphism `galois` on the digits), ModDown, combined into fa.out.
 int ks_core(he_ctx* c, u32 l, u32 B, const WS& w, u64* const* c1, const u64* key, u32 galois, const FinalArgs& fa,
             const u64* bias) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np;
-  Items own;
-  own.n = B;
-  for (u32 b = 0; b < B; ++b) own.p[b] = c1[b];
-  int rc = launch_ks_inner(c, l, B, w.ext, own, key, galois, w.u);
+  StepKeys sk;
+  sk.key[0] = key;
+  sk.galois[0] = galois;
+  sk.galois_inv[0] = galois_inverse(c, galois);
+  int rc = launch_ks_inner_steps(c, l, B, 1, w.ext, 0, own_of(B, c1), sk, w.u);
   if (rc) return rc;
   PolyBatch pi = batch_of(B);
   pi.npoly = 2 * ne;
@@ -188,13 +196,6 @@ int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, const OwnMap& ow
   pf.stride = (size_t)2 * (l + 1) * N;
   for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
   return launch_ntt(c, pf, false);
-}
-
-OwnMap own_of(u32 B, u64* const* c1) {
-  OwnMap own;
-  std::memset(&own, 0, sizeof(own));
-  for (u32 b = 0; b < B; ++b) own.ptr[b] = c1[b];
-  return own;
 }
 
 int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,

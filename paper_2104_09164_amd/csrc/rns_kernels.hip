@@ -4,8 +4,10 @@
 // threads per block, consecutive threads on consecutive words of a limb-poly
 // (limb-major [.][limb][N] layouts), so each wavefront reads and writes
 // contiguous 512-byte runs.  Per-prime constants come from small device tables
-// (broadcast loads).  Arithmetic: Shoup products by constants, lazy 128-bit
-// sums of products closed by one Montgomery reduction.
+// (broadcast loads).  Arithmetic: Shoup products by constants, keys and
+// plaintexts (stored with their companions, sums kept lazily below a bound),
+// and lazy 128-bit sums of products closed by one Montgomery reduction for
+// the base conversions and the tensor.
 #include "rns_kernels.hpp"
 #include "modarith.hpp"
 
@@ -75,60 +77,31 @@ __global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef,
   }
 }
 
-// grid: (N/BS, ne, 1); loops over items so key words are loaded once per batch.
-// A digit's own limbs are not copied into ext: they are read from the source
-// polynomial (NTT form) given per item in `own`.
-template <bool PERM>
-__global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, Items own, const u64* __restrict__ key,
-                                                 u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
-                                                 u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
-                                                 u32 nitems, u32 galois, u32 alpha) {
-  const u32 k = blockIdx.x * BS + threadIdx.x;
-  const u32 t = blockIdx.y;
-  const u32 ne = l + 1 + np, nt = nq + np;
-  const u32 pr = t <= l ? t : nq + (t - l - 1);
-  const u64 q = pc[pr].q, qneg = pc[pr].qneg;
-  const u32 ks = PERM ? galois_perm(k, galois, logn) : k;
-  u64 kb[8], ka[8];
-  for (u32 j = 0; j < beta; ++j) {
-    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + k];
-    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + k];
-  }
-  const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
-  // Items two at a time: both items' digit words are in flight together.
-  u32 b = 0;
-  for (; b + 2 <= nitems; b += 2) {
-    u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
-    const u64* e0 = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
-    const u64* e1 = e0 + (size_t)dstride * ne * N;
-    for (u32 j = 0; j < beta; ++j) {
-      const bool own_j = j == own_digit;
-      const u64 x0 = own_j ? own.p[b][(size_t)t * N + ks] : e0[(size_t)j * ne * N];
-      const u64 x1 = own_j ? own.p[b + 1][(size_t)t * N + ks] : e1[(size_t)j * ne * N];
-      acc_wide(sb0, x0, kb[j]);
-      acc_wide(sa0, x0, ka[j]);
-      acc_wide(sb1, x1, kb[j]);
-      acc_wide(sa1, x1, ka[j]);
+// Key inner product of one item: u_b = sum_j x_j ksk_{b,j}, u_a = sum_j x_j ksk_{a,j}
+// with Shoup products by the key words (companions kbs / kas), the sum
+// folded into the product's low-word chain (add_shoup4).  LAZY (q < 2^59):
+// at most 8 terms below 4q each, reduced once; otherwise kept below 4q.
+constexpr u64 kLazyKS = 1ull << 59;
+template <int BETA, bool LAZY>
+__device__ __forceinline__ void ks_dot(const u64 (&x)[BETA], const u64 (&kb)[BETA], const u64 (&kbs)[BETA],
+                                       const u64 (&ka)[BETA], const u64 (&kas)[BETA], const PrimeConst& P, u64& ob,
+                                       u64& oa) {
+  u64 sb = 0, sa = 0;
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    sb = add_shoup4(sb, x[j], kb[j], kbs[j], P.nq);
+    sa = add_shoup4(sa, x[j], ka[j], kas[j], P.nq);
+    if (!LAZY) {
+      sb = csub_neg(sb, P.nq4);
+      sa = csub_neg(sa, P.nq4);
     }
-    u64* o = u + ((size_t)b * 2 * ne + t) * N + k;
-    o[0] = redc(sb0, q, qneg);
-    o[(size_t)ne * N] = redc(sa0, q, qneg);
-    o += (size_t)2 * ne * N;
-    o[0] = redc(sb1, q, qneg);
-    o[(size_t)ne * N] = redc(sa1, q, qneg);
   }
-  if (b < nitems) {
-    u128v sb = {0, 0}, sa = {0, 0};
-    const u64* e = ext + ((size_t)b * dstride) * ne * N + (size_t)t * N + ks;
-    for (u32 j = 0; j < beta; ++j) {
-      const u64 x = j == own_digit ? own.p[b][(size_t)t * N + ks] : e[(size_t)j * ne * N];
-      acc_wide(sb, x, kb[j]);
-      acc_wide(sa, x, ka[j]);
-    }
-    u64* o = u + ((size_t)b * 2 * ne + t) * N + k;
-    o[0] = redc(sb, q, qneg);
-    o[(size_t)ne * N] = redc(sa, q, qneg);
+  if (LAZY) {
+    sb = shoup_lazy4(sb, 1, P.mu, P.q);
+    sa = shoup_lazy4(sa, 1, P.mu, P.q);
   }
+  ob = csub_neg(csub_neg(sb, P.nq2), P.nq);
+  oa = csub_neg(csub_neg(sa, P.nq2), P.nq);
 }
 
 // 1-D grid over S x (N/BS, ne) tiles: the steps of a tile share its extended
@@ -137,64 +110,59 @@ __global__ void __launch_bounds__(BS) k_ks_inner(const u64* __restrict__ ext, It
 // sum_j d_j[perm_g(k')] ksk_{s,j}[k'], so every step reads the same
 // (unpermuted) digit words of a tile, from L2 after the first step, and
 // gathers its key and scatters its output within the same aligned groups.
+// BETA = digits at this level.
+template <int BETA, bool LAZY>
+__device__ __forceinline__ void ks_inner_body(const u64* __restrict__ ext, u32 ext_items, const OwnMap& own,
+                                              const u64* __restrict__ key, u64* __restrict__ u, const PrimeConst& P,
+                                              u32 N, u32 l, u32 nt, u32 ne, u32 pr, u32 dstride, u32 nitems,
+                                              u32 alpha, u32 s, u32 k, u32 ko, u32 t) {
+  const size_t kw = (size_t)dstride * 2 * nt * N;          // companions follow the key words
+  u64 kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    const size_t ob = (((size_t)j * 2 + 0) * nt + pr) * N + ko, oa = (((size_t)j * 2 + 1) * nt + pr) * N + ko;
+    kb[j] = key[ob];
+    kbs[j] = key[kw + ob];
+    ka[j] = key[oa];
+    kas[j] = key[kw + oa];
+  }
+  const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
+  u64* ub = u + (size_t)s * nitems * 2 * ne * N;
+  const u64* es = ext + (size_t)s * ext_items * dstride * ne * N;
+  const u64* obase = own.base ? own.base + s * own.os : nullptr;
+  for (u32 b = 0; b < nitems; ++b) {
+    const u64* e = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + k;
+    const u64* src = obase ? obase + b * own.ob : own.ptr[b];
+    u64 x[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) x[j] = (u32)j == own_digit ? src[(size_t)t * N + k] : e[(size_t)j * ne * N];
+    u64 rb, ra;
+    ks_dot<BETA, LAZY>(x, kb, kbs, ka, kas, P, rb, ra);
+    u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
+    o[0] = rb;
+    o[(size_t)ne * N] = ra;
+  }
+}
+
+template <int BETA>
 __global__ void __launch_bounds__(BS) k_ks_inner_steps(const u64* __restrict__ ext, u32 ext_items, OwnMap own,
-                                                       StepKeys keys,
-                                                       u64* __restrict__ u, const PrimeConst* __restrict__ pc, u32 N,
-                                                       u32 logn, u32 l, u32 nq, u32 np, u32 beta, u32 dstride,
-                                                       u32 nitems, u32 alpha, u32 nsteps) {
+                                                       StepKeys keys, u64* __restrict__ u,
+                                                       const PrimeConst* __restrict__ pc, u32 N, u32 logn, u32 l,
+                                                       u32 nq, u32 np, u32 dstride, u32 nitems, u32 alpha,
+                                                       u32 nsteps) {
   const u32 ne = l + 1 + np, nt = nq + np, nkb = N / BS;
   u32 s, tile;
   xcd_decode(blockIdx.x, nsteps, nkb * ne, s, tile);
   const u32 k = (tile % nkb) * BS + threadIdx.x, t = tile / nkb;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
-  const u64 q = pc[pr].q, qneg = pc[pr].qneg;
+  const PrimeConst P = pc[pr];
   const u32 ko = galois_perm(k, keys.galois_inv[s], logn);    // output (and key) position
-  const u64* key = keys.key[s];
-  u64 kb[8], ka[8];
-  for (u32 j = 0; j < beta; ++j) {
-    kb[j] = key[(((size_t)j * 2 + 0) * nt + pr) * N + ko];
-    ka[j] = key[(((size_t)j * 2 + 1) * nt + pr) * N + ko];
-  }
-  const u32 own_digit = t <= l ? t / alpha : 0xFFFFFFFFu;
-  u64* ub = u + (size_t)s * nitems * 2 * ne * N;
-  const u64* es = ext + (size_t)s * ext_items * dstride * ne * N;
-  const u64* ob = own.base ? own.base + s * own.os : nullptr;
-  u32 b = 0;
-  for (; b + 2 <= nitems; b += 2) {
-    u128v sb0 = {0, 0}, sa0 = {0, 0}, sb1 = {0, 0}, sa1 = {0, 0};
-    const u64* e0 = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + k;
-    const u64* e1 = e0 + (size_t)dstride * ne * N;
-    const u64* o0 = ob ? ob + b * own.ob : own.ptr[b];
-    const u64* o1 = ob ? ob + (b + 1) * own.ob : own.ptr[b + 1];
-    for (u32 j = 0; j < beta; ++j) {
-      const bool own_j = j == own_digit;
-      const u64 x0 = own_j ? o0[(size_t)t * N + k] : e0[(size_t)j * ne * N];
-      const u64 x1 = own_j ? o1[(size_t)t * N + k] : e1[(size_t)j * ne * N];
-      acc_wide(sb0, x0, kb[j]);
-      acc_wide(sa0, x0, ka[j]);
-      acc_wide(sb1, x1, kb[j]);
-      acc_wide(sa1, x1, ka[j]);
-    }
-    u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
-    o[0] = redc(sb0, q, qneg);
-    o[(size_t)ne * N] = redc(sa0, q, qneg);
-    o += (size_t)2 * ne * N;
-    o[0] = redc(sb1, q, qneg);
-    o[(size_t)ne * N] = redc(sa1, q, qneg);
-  }
-  if (b < nitems) {
-    u128v sb = {0, 0}, sa = {0, 0};
-    const u64* e = es + ((size_t)b * dstride) * ne * N + (size_t)t * N + k;
-    const u64* src = ob ? ob + b * own.ob : own.ptr[b];
-    for (u32 j = 0; j < beta; ++j) {
-      const u64 x = j == own_digit ? src[(size_t)t * N + k] : e[(size_t)j * ne * N];
-      acc_wide(sb, x, kb[j]);
-      acc_wide(sa, x, ka[j]);
-    }
-    u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
-    o[0] = redc(sb, q, qneg);
-    o[(size_t)ne * N] = redc(sa, q, qneg);
-  }
+  if (P.q < kLazyKS)
+    ks_inner_body<BETA, true>(ext, ext_items, own, keys.key[s], u, P, N, l, nt, ne, pr, dstride, nitems, alpha, s, k,
+                              ko, t);
+  else
+    ks_inner_body<BETA, false>(ext, ext_items, own, keys.key[s], u, P, N, l, nt, ne, pr, dstride, nitems, alpha, s,
+                               k, ko, t);
 }
 
 // grid: (N/BS, l+1, S B), item z = s B + b
@@ -464,15 +432,6 @@ __global__ void __launch_bounds__(BS) k_add_plain(Items ct, const u64* __restric
 }
 
 // grid: (N/BS, nitems, npoly)
-__global__ void __launch_bounds__(BS) k_to_mont(PolyBatch pb, const PrimeConst* __restrict__ pc, u32 N) {
-  const u32 k = blockIdx.x * BS + threadIdx.x;
-  const u32 b = blockIdx.y, r = blockIdx.z;
-  const u32 pr = pb.prime[r];
-  if (pr == 0xFF) return;
-  u64* x = pb.dst[b] + (size_t)(pb.dst_off + r) * N;
-  x[k] = redc(mul_wide(x[k], pc[pr].r2), pc[pr].q, pc[pr].qneg);
-}
-
 // comp = floor(w 2^64 / q) by restoring long division of w 2^64 (w < q < 2^61:
 // the running remainder stays below 2q < 2^62).  grid (N/BS, level+1, m).
 __global__ void __launch_bounds__(BS) k_shoup_companion(const u64* __restrict__ pts, u64* __restrict__ comp,
@@ -513,20 +472,6 @@ int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
   return ok();
 }
 
-int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& own, const u64* key, u32 galois,
-                    u64* u) {
-  const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
-  TraceScope ts(c, TK_KS_INNER, ((double)nitems * beta * ne + 2.0 * beta * ne + 2.0 * nitems * ne) * (8.0 * (double)c->N));
-  dim3 grid(c->N / BS, l + 1 + c->np, 1);
-  if (galois != 1)
-    HE_LAUNCH(ts, (k_ks_inner<true>), grid, dim3(BS), c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
-                       c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
-  else
-    HE_LAUNCH(ts, (k_ks_inner<false>), grid, dim3(BS), c->stream, ext, own, key, u, c->d_pc, c->N, c->log_n, l,
-                       c->nq, c->np, digits_at(c, l), c->dnum, nitems, galois, c->alpha);
-  return ok();
-}
-
 int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
                         const u64* sums, const u64* bias, const OutMap& om) {
   // per item: s_0 (2 polys), per step u and conv (2 + 2) and s_j.c0, 2 polys written
@@ -540,13 +485,26 @@ int launch_ks_final_sum(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64*
 int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ext_items, const OwnMap& own,
                           const StepKeys& keys, u64* u) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
-  // digits: once per item when the steps share them (hoisted), once per (step, item) otherwise
+  // digits: once per item when the steps share them (hoisted), once per (step, item) otherwise;
+  // keys: value and Shoup companion per word
   const double digits = (double)(ext_items ? S : 1) * B * beta * ne;
-  TraceScope ts(c, TK_KS_INNER_STEPS, (digits + (double)S * (2.0 * beta * ne + 2.0 * B * ne)) * (8.0 * (double)c->N));
+  TraceScope ts(c, TK_KS_INNER_STEPS, (digits + (double)S * (4.0 * beta * ne + 2.0 * B * ne)) * (8.0 * (double)c->N));
   dim3 grid(S * (c->N / BS) * ne);
-  HE_LAUNCH(ts, k_ks_inner_steps, grid, dim3(BS), c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,
-                     c->log_n, l,
-                     c->nq, c->np, beta, c->dnum, B, c->alpha, S);
+#define HE_LAUNCH_KS(BT)                                                                                          \
+  HE_LAUNCH(ts, (k_ks_inner_steps<BT>), grid, dim3(BS), c->stream, ext, ext_items, own, keys, u, c->d_pc, c->N,     \
+            c->log_n, l, c->nq, c->np, c->dnum, B, c->alpha, S)
+  switch (beta) {
+    case 1: HE_LAUNCH_KS(1); break;
+    case 2: HE_LAUNCH_KS(2); break;
+    case 3: HE_LAUNCH_KS(3); break;
+    case 4: HE_LAUNCH_KS(4); break;
+    case 5: HE_LAUNCH_KS(5); break;
+    case 6: HE_LAUNCH_KS(6); break;
+    case 7: HE_LAUNCH_KS(7); break;
+    case 8: HE_LAUNCH_KS(8); break;
+    default: return HE_EPARAM;
+  }
+#undef HE_LAUNCH_KS
   return ok();
 }
 
@@ -652,10 +610,3 @@ int launch_shoup_companion(he_ctx* c, u32 m, u32 level, const u64* pts, u64* com
   return ok();
 }
 
-int launch_to_mont(he_ctx* c, const PolyBatch& pb) {
-  u32 nv = 0;
-  for (u32 r = 0; r < pb.npoly; ++r) nv += pb.prime[r] != 0xFF;
-  TraceScope ts(c, TK_TO_MONT, 2.0 * nv * pb.nitems * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_to_mont, dim3(c->N / BS, pb.nitems, pb.npoly), dim3(BS), c->stream, pb, c->d_pc, c->N);
-  return ok();
-}

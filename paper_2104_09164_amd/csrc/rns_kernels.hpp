@@ -17,13 +17,6 @@ int launch_copy_polys(he_ctx* c, const PolyBatch& pb);
 // except the digit's own limbs (coefficient form; those stay in the source).
 int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext);
 
-// Key inner product at level l: for item b and key part p in {b, a}:
-//   u[b][p][t][k] = sum_j ext[b][j][t][perm_g(k)] * key[j][p][prime(t)][k]   (Montgomery)
-// galois == 1: no permutation.  ext = [B][beta][l+1+K][N], u = [B][2][l+1+K][N].
-// The limbs of digit j that belong to j itself are read from own.p[b] (the
-// NTT-form source polynomial, [l+1][N]) instead of ext.
-int launch_ks_inner(he_ctx* c, u32 l, u32 nitems, const u64* ext, const Items& own, const u64* key, u32 galois,
-                    u64* u);
 
 // ModDown conversion: u = [B][2][l+1+K][N] with the P-limbs already in
 // coefficient form; conv = [B][2][l+1][N] coefficient form.
@@ -49,7 +42,7 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
 // the u / conv workspaces is s B + b.
 #define HE_MAX_STEPS 64
 struct StepKeys {
-  const u64* key[HE_MAX_STEPS];   // rotation key of step s ([dnum][2][L+1+K][N], Montgomery form)
+  const u64* key[HE_MAX_STEPS];   // key of step s ([dnum][2][L+1+K][N] NTT form, then Shoup companions)
   u32 galois[HE_MAX_STEPS];       // its Galois element g
   u32 galois_inv[HE_MAX_STEPS];   // g^{-1} mod 2N
 };
@@ -111,5 +104,3 @@ int launch_rescale_final(he_ctx* c, u32 l, const Items& in, const u64* red, cons
 int launch_add(he_ctx* c, u32 l, const Items& a, const Items& b, const Items& out);
 // c0(b) += poly (a plaintext at level l, NTT form).
 int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly);
-// x <- x 2^64 mod q (Montgomery form) in place, poly r of pb.dst item b with prime pb.prime[r].
-int launch_to_mont(he_ctx* c, const PolyBatch& pb);

@@ -111,9 +111,9 @@ def test_tracer_counts_launches_and_bytes(setup10):
     N, l, K = pr.n, ct.level, len(pr.p)
     beta = -(-(l + 1) // pr.alpha)
     ne = l + 1 + K
-    # the extended digits read once (shared by both steps); per step its key (2 polys per digit)
-    # read and u (2 polys) written
-    assert tab["ks_inner_steps"][2] == (beta * ne + 2 * (2 * beta * ne + 2 * ne)) * N * 8
+    # the extended digits read once (shared by both steps); per step its key (2 polys per digit,
+    # each with its Shoup companions) read and u (2 polys) written
+    assert tab["ks_inner_steps"][2] == (beta * ne + 2 * (4 * beta * ne + 2 * ne)) * N * 8
     for name, (n, ms, by) in tab.items():
         assert n > 0 and ms > 0 and by > 0, name
 
