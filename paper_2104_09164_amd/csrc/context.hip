@@ -73,7 +73,6 @@ PrimeConst make_pc(u64 q, u32 N) {
   p.mu = ~(u64)0 / q;
   p.rmod = (u64)(((u128)1 << 64) % q);
   p.rmod_sh = shoup_of(p.rmod, q);
-  p.r2 = mul_mod(p.rmod, p.rmod, q);
   p.ninv = inv_mod(N, q);
   p.ninv_sh = shoup_of(p.ninv, q);
   p.nq = (u64)0 - q;
@@ -81,8 +80,6 @@ PrimeConst make_pc(u64 q, u32 N) {
   p.nq4 = (u64)0 - 4 * q;
   return p;
 }
-// x 2^64 mod m (Montgomery form of a host constant)
-u64 to_mont_host(u64 x, u64 m) { return (u64)(((u128)(x % m) << 64) % m); }
 
 template <class T>
 int upload(he_ctx* c, T** dptr, const std::vector<T>& h) {
@@ -118,7 +115,7 @@ int build_tables(he_ctx* c) {
 
   // ModUp: for every level l and digit j, D = [j alpha, min((j+1) alpha, l+1)).
   const u32 nq = c->nq, np = c->np, A = c->alpha, dn = c->dnum;
-  std::vector<u64> hinv((size_t)nq * dn * A * 2, 0), hmod((size_t)nq * dn * A * nt, 0);
+  std::vector<u64> hinv((size_t)nq * dn * A * 2, 0), hmod((size_t)nq * dn * A * nt * 2, 0);
   for (u32 l = 0; l < nq; ++l)
     for (u32 j = 0; j < dn; ++j) {
       const u32 lo = j * A, hi = std::min((j + 1) * A, l + 1);
@@ -135,7 +132,8 @@ int build_tables(he_ctx* c) {
           u64 h = 1 % m;
           for (u32 i2 = lo; i2 < hi; ++i2)
             if (i2 != i) h = mul_mod(h, c->primes[i2] % m, m);
-          hmod[e * nt + t] = to_mont_host(h, m);
+          hmod[2 * (e * nt + t)] = h;                    // (Q_D / q_i) mod p_t and its Shoup companion
+          hmod[2 * (e * nt + t) + 1] = shoup_of(h, m);
         }
       }
     }
@@ -143,7 +141,8 @@ int build_tables(he_ctx* c) {
   if ((rc = upload(c, &c->d_modup_hatmod, hmod))) return rc;
 
   // ModDown.
-  std::vector<u64> md((size_t)np * 2 + (size_t)np * nq + (size_t)nq * 2);
+  // [np][2] (P/p_k)^{-1} mod p_k; [np][nq][2] (P/p_k) mod q_i; [nq][2] P^{-1} mod q_i (Shoup pairs)
+  std::vector<u64> md((size_t)np * 2 + (size_t)np * nq * 2 + (size_t)nq * 2);
   for (u32 k = 0; k < np; ++k) {
     const u64 pk = c->primes[nq + k];
     u64 inv = 1;
@@ -156,7 +155,8 @@ int build_tables(he_ctx* c) {
       u64 h = 1;
       for (u32 k2 = 0; k2 < np; ++k2)
         if (k2 != k) h = mul_mod(h, c->primes[nq + k2] % qi, qi);
-      md[2 * np + (size_t)k * nq + i] = to_mont_host(h, qi);
+      md[2 * np + 2 * ((size_t)k * nq + i)] = h;
+      md[2 * np + 2 * ((size_t)k * nq + i) + 1] = shoup_of(h, qi);
     }
   }
   for (u32 i = 0; i < nq; ++i) {
@@ -164,8 +164,8 @@ int build_tables(he_ctx* c) {
     u64 P = 1;
     for (u32 k = 0; k < np; ++k) P = mul_mod(P, c->primes[nq + k] % qi, qi);
     const u64 pinv = inv_mod(P, qi);
-    md[2 * np + (size_t)np * nq + 2 * i] = pinv;
-    md[2 * np + (size_t)np * nq + 2 * i + 1] = shoup_of(pinv, qi);
+    md[2 * np + 2 * (size_t)np * nq + 2 * i] = pinv;
+    md[2 * np + 2 * (size_t)np * nq + 2 * i + 1] = shoup_of(pinv, qi);
   }
   if ((rc = upload(c, &c->d_moddown, md))) return rc;
 

@@ -20,7 +20,6 @@ struct PrimeConst {
   u64 q;
   u64 qneg;        // -q^{-1} mod 2^64 (Montgomery)
   u64 mu;          // floor(2^64 / q) (Barrett-style reduce64)
-  u64 r2;          // 2^128 mod q: REDC(x * r2) = x 2^64 mod q
   u64 ninv, ninv_sh;   // N^{-1} mod q and its Shoup companion
   u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
   u64 nq, nq2, nq4;    // 2^64 - q, 2^64 - 2q, 2^64 - 4q

@@ -49,31 +49,59 @@ __global__ void __launch_bounds__(BS) k_copy_polys(PolyBatch pb, u32 N) {
   for (u32 k = blockIdx.x * BS + threadIdx.x; k < N; k += gridDim.x * BS) dst[k] = src[k];
 }
 
-// grid: (N/BS, beta, B)
+// Lazy sum of up to 8 Shoup products (each in [0, 4q)) into acc: below 32q
+// for q < 2^59 (reduced once by conv_final); otherwise kept below 4q.
+template <bool LAZY>
+__device__ __forceinline__ u64 conv_add(u64 acc, u64 v, const u64* __restrict__ pair, const PrimeConst& P) {
+  acc = add_shoup4(acc, v, pair[0], pair[1], P.nq);
+  return LAZY ? acc : csub_neg(acc, P.nq4);
+}
+template <bool LAZY>
+__device__ __forceinline__ u64 conv_final(u64 acc, const PrimeConst& P) {
+  if (LAZY) acc = shoup_lazy4(acc, 1, P.mu, P.q);
+  return csub_neg(csub_neg(acc, P.nq2), P.nq);
+}
+
+// grid: (N/BS, beta, B); A = digit size alpha (the last digit may hold fewer limbs)
+template <int A>
 __global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef, u64* __restrict__ ext,
                                                    const PrimeConst* __restrict__ pc, const u64* __restrict__ hatinv,
                                                    const u64* __restrict__ hatmod, u32 N, u32 l, u32 nq, u32 np,
-                                                   u32 alpha, u32 dnum) {
+                                                   u32 dnum) {
   const u32 k = blockIdx.x * BS + threadIdx.x;
   const u32 j = blockIdx.y, b = blockIdx.z;
   const u32 ne = l + 1 + np, nt = nq + np;
-  const u32 lo = j * alpha, hi = min((j + 1) * alpha, l + 1), cnt = hi - lo;
-  const size_t tab = ((size_t)l * dnum + j) * alpha;
-  u64 v[8];
-  for (u32 i = 0; i < cnt; ++i) {
-    const u64 q = pc[lo + i].q;
-    const u64 x = coef[((size_t)b * (l + 1) + lo + i) * N + k];
-    v[i] = shoup(x, hatinv[(tab + i) * 2], hatinv[(tab + i) * 2 + 1], q);
+  const u32 lo = j * A, hi = min((j + 1) * A, l + 1), cnt = hi - lo;
+  const size_t tab = ((size_t)l * dnum + j) * A;
+  u64 v[A];
+#pragma unroll
+  for (int i = 0; i < A; ++i) {
+    v[i] = 0;
+    if ((u32)i < cnt) {
+      const u64 q = pc[lo + i].q;
+      const u64 x = coef[((size_t)b * (l + 1) + lo + i) * N + k];
+      v[i] = shoup(x, hatinv[(tab + i) * 2], hatinv[(tab + i) * 2 + 1], q);
+    }
   }
   u64* out = ext + ((size_t)b * dnum + j) * ne * N;
   // dnum here is the allocation stride of digits per item (maximum digits)
   for (u32 t = 0; t < ne; ++t) {
     if (t >= lo && t < hi) continue;
     const u32 pr = t <= l ? t : nq + (t - l - 1);
-    const u64 q = pc[pr].q, qneg = pc[pr].qneg;
-    u128v s = {0, 0};
-    for (u32 i = 0; i < cnt; ++i) acc_wide(s, v[i], hatmod[(tab + i) * nt + pr]);
-    out[(size_t)t * N + k] = redc(s, q, qneg);
+    const PrimeConst P = pc[pr];
+    u64 s = 0;
+    if (P.q < (1ull << 59)) {
+#pragma unroll
+      for (int i = 0; i < A; ++i)
+        if ((u32)i < cnt) s = conv_add<true>(s, v[i], hatmod + 2 * ((tab + i) * nt + pr), P);
+      s = conv_final<true>(s, P);
+    } else {
+#pragma unroll
+      for (int i = 0; i < A; ++i)
+        if ((u32)i < cnt) s = conv_add<false>(s, v[i], hatmod + 2 * ((tab + i) * nt + pr), P);
+      s = conv_final<false>(s, P);
+    }
+    out[(size_t)t * N + k] = s;
   }
 }
 
@@ -174,7 +202,7 @@ __global__ void __launch_bounds__(BS) k_ks_final_steps(const u64* __restrict__ u
   const u32 i = blockIdx.y, z = blockIdx.z, s = z / B, b = z % B;
   const u32 ne = l + 1 + np;
   const u64 q = pc[i].q;
-  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64* pinv = md + 2 * np + 2 * (size_t)np * nq;   // [nq][2]
   const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
   const size_t ui = ((size_t)z * 2 * ne + i) * N + k;
   const size_t ci = ((size_t)z * 2 * (l + 1) + i) * N + k;
@@ -214,7 +242,7 @@ __device__ __forceinline__ void ks_final_mp_body(const u64* __restrict__ u, cons
                                                  u32 nq, u32 n1, u32 n2, u32 b, u32 k, u32 li, u32 jc) {
   const u32 B = in.n, ne = l + 1 + np;
   const u64 q = pk.q;
-  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64* pinv = md + 2 * np + 2 * (size_t)np * nq;   // [nq][2]
   const u64 w = pinv[2 * li], wsh = pinv[2 * li + 1];
   const size_t csz = (size_t)2 * (l + 1) * N;
   const size_t comp = (size_t)n1 * n2 * (l + 1) * N;  // companions follow the m diagonals
@@ -278,7 +306,7 @@ __global__ void __launch_bounds__(BS) k_ks_final_sum(const u64* __restrict__ u, 
   const u32 i = blockIdx.y, b = blockIdx.z;
   const u32 ne = l + 1 + np;
   const u64 q = pc[i].q;
-  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64* pinv = md + 2 * np + 2 * (size_t)np * nq;   // [nq][2]
   const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
   const size_t csz = (size_t)2 * (l + 1) * N;
   const u64* s0 = sums + (size_t)b * csz;
@@ -298,26 +326,37 @@ __global__ void __launch_bounds__(BS) k_ks_final_sum(const u64* __restrict__ u, 
   out[(size_t)(l + 1 + i) * N + k] = r1;
 }
 
-// grid: (N/BS, 2, B)
+// grid: (N/BS, 2, B); K = number of special primes
+template <int K>
 __global__ void __launch_bounds__(BS) k_moddown_conv(const u64* __restrict__ u, u64* __restrict__ conv,
                                                      const PrimeConst* __restrict__ pc,
-                                                     const u64* __restrict__ md, u32 N, u32 l, u32 nq, u32 np) {
+                                                     const u64* __restrict__ md, u32 N, u32 l, u32 nq) {
   const u32 k = blockIdx.x * BS + threadIdx.x;
   const u32 p = blockIdx.y, b = blockIdx.z;
-  const u32 ne = l + 1 + np;
-  const u64* phatinv = md;                     // [np][2]
-  const u64* phatmod = md + 2 * np;            // [np][nq]
+  const u32 ne = l + 1 + K;
+  const u64* phatinv = md;                     // [K][2]
+  const u64* phatmod = md + 2 * K;             // [K][nq][2]
   const u64* src = u + ((size_t)b * 2 + p) * ne * N;
-  u64 v[8];
-  for (u32 kk = 0; kk < np; ++kk) {
+  u64 v[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
     const u64 q = pc[nq + kk].q;
     v[kk] = shoup(src[(size_t)(l + 1 + kk) * N + k], phatinv[2 * kk], phatinv[2 * kk + 1], q);
   }
   u64* dst = conv + ((size_t)b * 2 + p) * (l + 1) * N;
   for (u32 i = 0; i <= l; ++i) {
-    u128v s = {0, 0};
-    for (u32 kk = 0; kk < np; ++kk) acc_wide(s, v[kk], phatmod[(size_t)kk * nq + i]);
-    dst[(size_t)i * N + k] = redc(s, pc[i].q, pc[i].qneg);
+    const PrimeConst P = pc[i];
+    u64 s = 0;
+    if (P.q < (1ull << 59)) {
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) s = conv_add<true>(s, v[kk], phatmod + 2 * ((size_t)kk * nq + i), P);
+      s = conv_final<true>(s, P);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) s = conv_add<false>(s, v[kk], phatmod + 2 * ((size_t)kk * nq + i), P);
+      s = conv_final<false>(s, P);
+    }
+    dst[(size_t)i * N + k] = s;
   }
 }
 
@@ -330,7 +369,7 @@ __global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, cons
   const u32 i = blockIdx.y, b = blockIdx.z;
   const u32 ne = l + 1 + np;
   const u64 q = pc[i].q;
-  const u64* pinv = md + 2 * np + (size_t)np * nq;   // [nq][2]
+  const u64* pinv = md + 2 * np + 2 * (size_t)np * nq;   // [nq][2]
   const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
   const size_t ui = ((size_t)b * 2 * ne + i) * N + k;
   const size_t ci = ((size_t)b * 2 * (l + 1) + i) * N + k;
@@ -467,8 +506,22 @@ int launch_copy_polys(he_ctx* c, const PolyBatch& pb) {
 int launch_modup_conv(he_ctx* c, u32 l, u32 nitems, const u64* coef, u64* ext) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np;
   TraceScope ts(c, TK_MODUP_CONV, (double)nitems * ((l + 1) + (beta * ne - (l + 1))) * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_modup_conv, dim3(c->N / BS, digits_at(c, l), nitems), dim3(BS), c->stream, coef, ext, c->d_pc,
-                     c->d_modup_hatinv, c->d_modup_hatmod, c->N, l, c->nq, c->np, c->alpha, c->dnum);
+  const dim3 grid(c->N / BS, digits_at(c, l), nitems);
+#define HE_LAUNCH_UP(A)                                                                                           \
+  HE_LAUNCH(ts, (k_modup_conv<A>), grid, dim3(BS), c->stream, coef, ext, c->d_pc, c->d_modup_hatinv,               \
+            c->d_modup_hatmod, c->N, l, c->nq, c->np, c->dnum)
+  switch (c->alpha) {
+    case 1: HE_LAUNCH_UP(1); break;
+    case 2: HE_LAUNCH_UP(2); break;
+    case 3: HE_LAUNCH_UP(3); break;
+    case 4: HE_LAUNCH_UP(4); break;
+    case 5: HE_LAUNCH_UP(5); break;
+    case 6: HE_LAUNCH_UP(6); break;
+    case 7: HE_LAUNCH_UP(7); break;
+    case 8: HE_LAUNCH_UP(8); break;
+    default: return HE_EPARAM;
+  }
+#undef HE_LAUNCH_UP
   return ok();
 }
 
@@ -542,8 +595,21 @@ int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64
 
 int launch_moddown_conv(he_ctx* c, u32 l, u32 nitems, const u64* u, u64* conv) {
   TraceScope ts(c, TK_MODDOWN_CONV, (double)nitems * (2.0 * c->np + 2.0 * (l + 1)) * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_moddown_conv, dim3(c->N / BS, 2, nitems), dim3(BS), c->stream, u, conv, c->d_pc, c->d_moddown,
-                     c->N, l, c->nq, c->np);
+  const dim3 grid(c->N / BS, 2, nitems);
+#define HE_LAUNCH_DN(K) \
+  HE_LAUNCH(ts, (k_moddown_conv<K>), grid, dim3(BS), c->stream, u, conv, c->d_pc, c->d_moddown, c->N, l, c->nq)
+  switch (c->np) {
+    case 1: HE_LAUNCH_DN(1); break;
+    case 2: HE_LAUNCH_DN(2); break;
+    case 3: HE_LAUNCH_DN(3); break;
+    case 4: HE_LAUNCH_DN(4); break;
+    case 5: HE_LAUNCH_DN(5); break;
+    case 6: HE_LAUNCH_DN(6); break;
+    case 7: HE_LAUNCH_DN(7); break;
+    case 8: HE_LAUNCH_DN(8); break;
+    default: return HE_EPARAM;
+  }
+#undef HE_LAUNCH_DN
   return ok();
 }
 
