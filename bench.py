@@ -422,7 +422,7 @@ def main():
     ap.add_argument("--large-batch", type=int, default=32, help="requests per launch, large net")
     ap.add_argument("--plain", type=int, default=8, help="one-request inferences timed for the plain leg")
     ap.add_argument("--serve-rates", default="50,200,400")
-    ap.add_argument("--serve-seconds", type=float, default=2.5)
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tuning", action="store_true", help="ignore committed tuning files")
     ap.add_argument("--no-cpu", action="store_true")
