@@ -95,9 +95,24 @@ struct Phase {
     }
   }
 
-  template <int U, int RB, bool NOCSUB>
+  // Output word of the phase: reduced to [0, q) (and scaled by N^{-1} for the
+  // inverse) when final_, else the lazy value as is.
+  template <bool NOCSUB>
+  __device__ static __forceinline__ u64 out_word(u64 a, const PrimeConst& k, int final_) {
+    if (!final_) return a;
+    if (INV) return csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, k.q), k.nq2), k.nq);
+    if (NOCSUB) return csub_neg(csub_neg(shoup_lazy4(a, 1, k.mu, k.q), k.nq2), k.nq);   // below 76q
+    return csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
+  }
+
+  // One pass of RB stages.  FROM_G: the group is read straight from the
+  // phase's source in HBM instead of the LDS tile; TO_G: written straight to
+  // the destination (with out_word) instead of back to LDS.  Both are used by
+  // the column phase, whose groups are coalesced rows of COLS words.
+  template <int U, int RB, bool NOCSUB, bool FROM_G = false, bool TO_G = false>
   __device__ static __forceinline__ void pass(u64* lds, const ulonglong2* __restrict__ tw, const PrimeConst& k,
-                                              u32 sub0) {
+                                              u32 sub0, const u64* src = nullptr, u64* dst = nullptr,
+                                              int final_ = 0) {
     const u64 q = k.q;
     constexpr int R = 1 << RB;
     constexpr int KL = 1 << (LP - U - RB);
@@ -114,7 +129,10 @@ struct Phase {
       const u32 hi = ROWS ? sub0 + col : 0;
       u64 x[R];
 #pragma unroll
-      for (int m = 0; m < R; ++m) x[m] = lds[pidx(local(col, kt * (R * KL) + m * KL + kl))];
+      for (int m = 0; m < R; ++m) {
+        const u32 li = local(col, kt * (R * KL) + m * KL + kl);
+        x[m] = FROM_G ? src[gaddr(sub0, li)] : lds[pidx(li)];
+      }
       const u64 q4 = 4 * q;
       if (!INV) {
         fwd_stages<U, RB, NOCSUB>(x, tw, k, hi, kt);
@@ -138,7 +156,11 @@ struct Phase {
         }
       }
 #pragma unroll
-      for (int m = 0; m < R; ++m) lds[pidx(local(col, kt * (R * KL) + m * KL + kl))] = x[m];
+      for (int m = 0; m < R; ++m) {
+        const u32 li = local(col, kt * (R * KL) + m * KL + kl);
+        if (TO_G) dst[gaddr(sub0, li)] = out_word<NOCSUB>(x[m], k, final_);
+        else lds[pidx(li)] = x[m];
+      }
     }
   }
 
@@ -163,9 +185,16 @@ struct Phase {
   // a row), the phase's stages, tile out.  final_: reduce to [0, q) (and
   // scale by N^{-1} for the inverse) on the way out.
   template <bool NOCSUB>
-  __device__ static __forceinline__ void body(u64* lds, const u64* __restrict__ src, u64* __restrict__ dst,
-                                              const ulonglong2* __restrict__ tw, const PrimeConst& k, u32 sub0,
-                                              int final_) {
+  __device__ static __forceinline__ void body(u64* lds, const u64* src, u64* dst, const ulonglong2* __restrict__ tw,
+                                              const PrimeConst& k, u32 sub0, int final_) {
+    if constexpr (!ROWS && npasses(LP) == 2) {
+      // column phase: first pass from HBM, second pass to HBM, LDS only in between
+      constexpr int P0 = INV ? 1 : 0, P1 = INV ? 0 : 1;
+      pass<pass_start(LP, P0), pass_bits(LP, P0), NOCSUB, true, false>(lds, tw, k, sub0, src);
+      __syncthreads();
+      pass<pass_start(LP, P1), pass_bits(LP, P1), NOCSUB, false, true>(lds, tw, k, sub0, nullptr, dst, final_);
+      return;
+    }
     const u64 q = k.q;
     for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
       const ulonglong2 v = *(const ulonglong2*)(src + gaddr(sub0, i));
