@@ -196,14 +196,24 @@ struct Phase {
       return;
     }
     const u64 q = k.q;
-    for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-      const ulonglong2 v = *(const ulonglong2*)(src + gaddr(sub0, i));
-      lds[pidx(i)] = v.x;
-      lds[pidx(i + 1)] = v.y;
+    if constexpr (ROWS && npasses(LP) == 2) {
+      // row phase: first pass straight from HBM (its groups read runs of 2^(LP-RB) words);
+      // the last pass goes back through LDS so the tile leaves in full 16-byte rows
+      constexpr int P0 = INV ? 1 : 0, P1 = INV ? 0 : 1;
+      pass<pass_start(LP, P0), pass_bits(LP, P0), NOCSUB, true, false>(lds, tw, k, sub0, src);
+      __syncthreads();
+      pass<pass_start(LP, P1), pass_bits(LP, P1), NOCSUB>(lds, tw, k, sub0);
+      __syncthreads();
+    } else {
+      for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
+        const ulonglong2 v = *(const ulonglong2*)(src + gaddr(sub0, i));
+        lds[pidx(i)] = v.x;
+        lds[pidx(i + 1)] = v.y;
+      }
+      __syncthreads();
+      if (!INV) passes_fwd<0, NOCSUB>(lds, tw, k, sub0);
+      else passes_inv<npasses(LP) - 1>(lds, tw, k, sub0);
     }
-    __syncthreads();
-    if (!INV) passes_fwd<0, NOCSUB>(lds, tw, k, sub0);
-    else passes_inv<npasses(LP) - 1>(lds, tw, k, sub0);
     ulonglong2 v;
     if (final_) {
       for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
