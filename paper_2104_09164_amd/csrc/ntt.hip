@@ -196,9 +196,12 @@ struct Phase {
       return;
     }
     const u64 q = k.q;
-    if constexpr (ROWS && npasses(LP) == 2) {
-      // row phase: first pass straight from HBM (its groups read runs of 2^(LP-RB) words);
-      // the last pass goes back through LDS so the tile leaves in full 16-byte rows
+    if constexpr (ROWS && npasses(LP) == 2 && (!INV || pass_bits(LP, 1) <= 3)) {
+      // row phase: first pass straight from HBM; the last pass goes back
+      // through LDS so the tile leaves in full 16-byte rows.  Lanes of the
+      // forward's first pass read runs of 2^(LP-RB) consecutive words; the
+      // inverse starts with the last stages, whose lanes sit 2^RB words apart,
+      // so it reads directly only when that gap is at most 8 words (64 bytes).
       constexpr int P0 = INV ? 1 : 0, P1 = INV ? 0 : 1;
       pass<pass_start(LP, P0), pass_bits(LP, P0), NOCSUB, true, false>(lds, tw, k, sub0, src);
       __syncthreads();
