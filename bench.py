@@ -10,7 +10,8 @@ baby-step rotations,
 MultPlain inner sums, giant-step and rotate-and-sum key switches, bias),
 replayed from a captured HIP graph, inputs resident in HBM.  `value` is that
 leg's inferences/s.  Reported beside it, in the same JSON line:
-  * plain one-request-at-a-time inferences/s and p50/p99 latency;
+  * plain one-request-at-a-time inferences/s and p50/p99 latency (a batch of
+    one replayed from its own graph; the eager-launch latency beside it);
   * the small net again with the autotuner's baby-step counts;
   * the same two legs for the large network (N=2^16, 4096->256->64->2);
   * serving: Poisson arrivals at several rates, 70% small / 30% large
@@ -341,11 +342,17 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"{name}: plain leg")
+    lat_eager = [float("nan")]
     if plain_n > 0:
+        # one request at a time: the same network for a batch of one, replayed
+        # from its own graph (and, for reference, launched eagerly)
+        one = runner.capture(1).replay if graph else (lambda: runner.run(1))
         for _ in range(2):
+            one()
             runner.run(1)
         torch.cuda.synchronize()
-        lat = time_events(lambda: runner.run(1), plain_n)
+        lat = time_events(one, plain_n)
+        lat_eager = time_events(lambda: runner.run(1), plain_n)
     else:
         lat = [float("nan")]
     c = netplan.PRESETS[name]
@@ -353,6 +360,7 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
            "batched_p50_ms": float(np.percentile(per_step, 50)), "batched_p99_ms": float(np.percentile(per_step, 99)),
            "plain_inferences_per_s": 1000.0 / float(np.mean(lat)),
            "plain_p50_ms": float(np.percentile(lat, 50)), "plain_p99_ms": float(np.percentile(lat, 99)),
+           "plain_eager_p50_ms": float(np.percentile(lat_eager, 50)),
            "workload": (f"{name}: N=2^{plan.log_n}, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
                         f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
                         + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers) + ", x^2 between"),
