@@ -107,13 +107,17 @@ __global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef,
 
 // Key inner product of one item: u_b = sum_j x_j ksk_{b,j}, u_a = sum_j x_j ksk_{a,j}
 // with Shoup products by the key words (companions kbs / kas), the sum
-// folded into the product's low-word chain (add_shoup4).  LAZY (q < 2^59):
-// at most 8 terms below 4q each, reduced once; otherwise kept below 4q.
-constexpr u64 kLazyKS = 1ull << 59;
+// folded into the product's low-word chain (add_shoup4).  LAZY (q < 2^58):
+// at most 8 terms below 4q each, so the sum stays below 32q; otherwise it is
+// kept below 4q after every term.  The outputs are left lazy for their
+// consumers: Q-limbs (below 32q) are read only as u + q - conv by a Shoup
+// product, which takes any 64-bit input; P-limbs feed the inverse NTT, which
+// takes inputs below 4q (one Shoup product by 1 brings a lazy sum there).
+constexpr u64 kLazyKS = 1ull << 58;
 template <int BETA, bool LAZY>
 __device__ __forceinline__ void ks_dot(const u64 (&x)[BETA], const u64 (&kb)[BETA], const u64 (&kbs)[BETA],
-                                       const u64 (&ka)[BETA], const u64 (&kas)[BETA], const PrimeConst& P, u64& ob,
-                                       u64& oa) {
+                                       const u64 (&ka)[BETA], const u64 (&kas)[BETA], const PrimeConst& P,
+                                       bool p_limb, u64& ob, u64& oa) {
   u64 sb = 0, sa = 0;
 #pragma unroll
   for (int j = 0; j < BETA; ++j) {
@@ -124,12 +128,12 @@ __device__ __forceinline__ void ks_dot(const u64 (&x)[BETA], const u64 (&kb)[BET
       sa = csub_neg(sa, P.nq4);
     }
   }
-  if (LAZY) {
+  if (LAZY && p_limb) {
     sb = shoup_lazy4(sb, 1, P.mu, P.q);
     sa = shoup_lazy4(sa, 1, P.mu, P.q);
   }
-  ob = csub_neg(csub_neg(sb, P.nq2), P.nq);
-  oa = csub_neg(csub_neg(sa, P.nq2), P.nq);
+  ob = sb;
+  oa = sa;
 }
 
 // 1-D grid over S x (N/BS, ne) tiles: the steps of a tile share its extended
@@ -165,7 +169,7 @@ __device__ __forceinline__ void ks_inner_body(const u64* __restrict__ ext, u32 e
 #pragma unroll
     for (int j = 0; j < BETA; ++j) x[j] = (u32)j == own_digit ? src[(size_t)t * N + k] : e[(size_t)j * ne * N];
     u64 rb, ra;
-    ks_dot<BETA, LAZY>(x, kb, kbs, ka, kas, P, rb, ra);
+    ks_dot<BETA, LAZY>(x, kb, kbs, ka, kas, P, t > l, rb, ra);
     u64* o = ub + ((size_t)b * 2 * ne + t) * N + ko;
     o[0] = rb;
     o[(size_t)ne * N] = ra;

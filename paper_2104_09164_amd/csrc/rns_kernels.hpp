@@ -53,9 +53,12 @@ struct OwnMap {
   const u64* base;
   size_t os, ob;
 };
-// u[s B + b] = key-switch inner product of item (s, b) with key s (as
-// launch_ks_inner).  Digits: ext item s ext_items + b (ext_items = 0: the
-// steps share item b's digits, the hoisted form; = B: one ModUp per (s, b)).
+// u[s B + b] = key-switch inner product of item (s, b) with key s:
+//   u[.][p][t][k'] = sum_j ext[.][j][t][perm_g(k')] * key[j][p][prime(t)][k'],  p in {b, a},
+// left lazy: Q-limbs below 32 q_t (read by the epilogues as u + q - conv),
+// P-limbs below 4 p_t (inputs of the inverse NTT).  Digits: ext item
+// s ext_items + b (ext_items = 0: the steps share item b's digits, the
+// hoisted form; = B: one ModUp per (s, b)).
 int launch_ks_inner_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* ext, u32 ext_items, const OwnMap& own,
                           const StepKeys& keys, u64* u);
 // Output ciphertext of item (s, b): base + s os + b ob when base is set, else ptr[s B + b] (S B <= HE_MAXB).
