@@ -62,6 +62,17 @@ __device__ __forceinline__ u64 add_shoup4(u64 X, u64 x, u64 w, u64 wsh, u64 nq) 
   const u32 hi = (u32)(t >> 32) + x1 * w0 + x0 * w1 + h1 * n0 + h0 * n1;
   return ((u64)hi << 32) | (u32)t;
 }
+// x mod q up to a small multiple: [0, 4q) for any 64-bit x, from the Shoup
+// product by 1 (companion mu = floor(2^64/q)).  When q > 2^32, mu fits 32
+// bits and one 32-bit high product of the top word estimates the quotient:
+// qh = floor(x1 mu / 2^32) <= floor(x/q) <= qh + 2 (the dropped x0 mu / 2^64
+// and the rounding of mu each cost less than 1), so x - qh q is in [0, 3q).
+__device__ __forceinline__ u64 reduce_lazy(u64 x, u64 q, u64 mu) {
+  if (mu >> 32) return shoup_lazy4(x, 1, mu, q);
+  const u32 qh = __umulhi((u32)(x >> 32), (u32)mu);
+  return x - (u64)qh * q;
+}
+
 // x < 2m (m <= 2^63): x - m if x >= m; negm = 2^64 - m supplied from memory so
 // that the difference is one 64-bit add (v_lshl_add_u64) instead of a
 // subtract-with-borrow pair.

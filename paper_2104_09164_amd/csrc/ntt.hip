@@ -101,7 +101,7 @@ struct Phase {
   __device__ static __forceinline__ u64 out_word(u64 a, const PrimeConst& k, int final_) {
     if (!final_) return a;
     if (INV) return csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, k.q), k.nq2), k.nq);
-    if (NOCSUB) return csub_neg(csub_neg(shoup_lazy4(a, 1, k.mu, k.q), k.nq2), k.nq);   // below 76q
+    if (NOCSUB) return csub_neg(csub_neg(reduce_lazy(a, k.q, k.mu), k.nq2), k.nq);   // lazy value below 76q
     return csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
   }
 
@@ -225,9 +225,9 @@ struct Phase {
           v.x = csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
           v.y = csub_neg(csub_neg(shoup_lazy4(b, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
         } else if (NOCSUB) {
-          // below 76q: Shoup product by 1 (companion floor(2^64/q)) -> [0, 4q), then two steps
-          v.x = csub_neg(csub_neg(shoup_lazy4(a, 1, k.mu, q), k.nq2), k.nq);
-          v.y = csub_neg(csub_neg(shoup_lazy4(b, 1, k.mu, q), k.nq2), k.nq);
+          // below 76q: reduce_lazy -> [0, 4q), then two conditional subtractions
+          v.x = csub_neg(csub_neg(reduce_lazy(a, q, k.mu), k.nq2), k.nq);
+          v.y = csub_neg(csub_neg(reduce_lazy(b, q, k.mu), k.nq2), k.nq);
         } else {
           v.x = csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
           v.y = csub_neg(csub_neg(csub_neg(b, k.nq4), k.nq2), k.nq);

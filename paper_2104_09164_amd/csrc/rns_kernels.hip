@@ -58,7 +58,7 @@ __device__ __forceinline__ u64 conv_add(u64 acc, u64 v, const u64* __restrict__ 
 }
 template <bool LAZY>
 __device__ __forceinline__ u64 conv_final(u64 acc, const PrimeConst& P) {
-  if (LAZY) acc = shoup_lazy4(acc, 1, P.mu, P.q);
+  if (LAZY) acc = reduce_lazy(acc, P.q, P.mu);
   return csub_neg(csub_neg(acc, P.nq2), P.nq);
 }
 
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(BS) k_modup_conv(const u64* __restrict__ coef,
 // kept below 4q after every term.  The outputs are left lazy for their
 // consumers: Q-limbs (below 32q) are read only as u + q - conv by a Shoup
 // product, which takes any 64-bit input; P-limbs feed the inverse NTT, which
-// takes inputs below 4q (one Shoup product by 1 brings a lazy sum there).
+// takes inputs below 4q (reduce_lazy brings a lazy sum there).
 constexpr u64 kLazyKS = 1ull << 58;
 template <int BETA, bool LAZY>
 __device__ __forceinline__ void ks_dot(const u64 (&x)[BETA], const u64 (&kb)[BETA], const u64 (&kbs)[BETA],
@@ -129,8 +129,8 @@ __device__ __forceinline__ void ks_dot(const u64 (&x)[BETA], const u64 (&kb)[BET
     }
   }
   if (LAZY && p_limb) {
-    sb = shoup_lazy4(sb, 1, P.mu, P.q);
-    sa = shoup_lazy4(sa, 1, P.mu, P.q);
+    sb = reduce_lazy(sb, P.q, P.mu);
+    sa = reduce_lazy(sa, P.q, P.mu);
   }
   ob = sb;
   oa = sa;
@@ -230,7 +230,7 @@ __device__ __forceinline__ u64 mp_add(u64 acc, u64 x, u64 pt, u64 ps, const Prim
 }
 template <bool LAZY>
 __device__ __forceinline__ u64 mp_final(u64 acc, const PrimeConst& k) {
-  if (LAZY) acc = shoup_lazy4(acc, 1, k.mu, k.q);   // Shoup product by 1 -> [0, 4q)
+  if (LAZY) acc = reduce_lazy(acc, k.q, k.mu);   // -> [0, 4q)
   return csub_neg(csub_neg(acc, k.nq2), k.nq);
 }
 

@@ -29,7 +29,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
-KNOB_SPACE = {"ntt_cols": [16, 32], "ntt_cols_b": [8, 16, 32], "ntt_chunk_mb": [0, 256]}
+KNOB_SPACE = {"ntt_cols": [16, 32], "ntt_cols_b": [8, 16, 32], "ntt_chunk_mb": [0, 64, 128, 256]}
 
 
 def n1_candidates(m: int, max_n1: int = 64) -> list[int]:
