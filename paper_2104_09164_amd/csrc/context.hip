@@ -100,6 +100,8 @@ int build_tables(he_ctx* c) {
     std::vector<u64> pw(N), ipw(N);
     pw[0] = ipw[0] = 1;
     for (u32 k = 1; k < N; ++k) { pw[k] = mul_mod(pw[k - 1], psi, q); ipw[k] = mul_mod(ipw[k - 1], ipsi, q); }
+    c->h_pc[i].w0ni = mul_mod(ipw[N / 2], c->h_pc[i].ninv, q);   // brev(1) = N/2
+    c->h_pc[i].w0ni_sh = shoup_of(c->h_pc[i].w0ni, q);
     u64* t = tw.data() + (size_t)i * 4 * N;
     for (u32 k = 0; k < N; ++k) {
       const u32 e = bitrev(k, c->log_n);

@@ -21,6 +21,7 @@ struct PrimeConst {
   u64 qneg;        // -q^{-1} mod 2^64 (Montgomery)
   u64 mu;          // floor(2^64 / q) (Barrett-style reduce64)
   u64 ninv, ninv_sh;   // N^{-1} mod q and its Shoup companion
+  u64 w0ni, w0ni_sh;   // inverse stage-0 twiddle psi^{-N/2} times N^{-1}, and its companion
   u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
   u64 nq, nq2, nq4;    // 2^64 - q, 2^64 - 2q, 2^64 - 4q
 };

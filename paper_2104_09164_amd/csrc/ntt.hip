@@ -100,7 +100,7 @@ struct Phase {
   template <bool NOCSUB>
   __device__ static __forceinline__ u64 out_word(u64 a, const PrimeConst& k, int final_) {
     if (!final_) return a;
-    if (INV) return csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, k.q), k.nq2), k.nq);
+    if (INV) return csub_neg(csub_neg(a, k.nq2), k.nq);   // N^{-1} already applied at stage 0
     if (NOCSUB) return csub_neg(csub_neg(reduce_lazy(a, k.q, k.mu), k.nq2), k.nq);   // lazy value below 76q
     return csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
   }
@@ -149,8 +149,15 @@ struct Phase {
             for (int e = 0; e < half; ++e) {
               const int m0 = blk * 2 * half + e, m1 = m0 + half;
               const u64 A = x[m0], B = x[m1];                            // < 4q
-              x[m0] = csub_neg(A + B, k.nq4);                            // < 4q
-              x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);            // < 4q
+              if (s == 0) {
+                // last stage of the inverse: N^{-1} folded into both outputs
+                // (the phase holding stage 0 is always the final one)
+                x[m0] = shoup_lazy4(A + B, k.ninv, k.ninv_sh, q);        // < 4q
+                x[m1] = shoup_lazy4(A + q4 - B, k.w0ni, k.w0ni_sh, q);   // < 4q
+              } else {
+                x[m0] = csub_neg(A + B, k.nq4);                          // < 4q
+                x[m1] = shoup_lazy4(A + q4 - B, wp.x, wp.y, q);          // < 4q
+              }
             }
           }
         }
@@ -220,18 +227,8 @@ struct Phase {
     ulonglong2 v;
     if (final_) {
       for (u32 i = 2 * threadIdx.x; i < (u32)TILE; i += 2 * NT) {
-        const u64 a = lds[pidx(i)], b = lds[pidx(i + 1)];
-        if (INV) {
-          v.x = csub_neg(csub_neg(shoup_lazy4(a, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
-          v.y = csub_neg(csub_neg(shoup_lazy4(b, k.ninv, k.ninv_sh, q), k.nq2), k.nq);
-        } else if (NOCSUB) {
-          // below 76q: reduce_lazy -> [0, 4q), then two conditional subtractions
-          v.x = csub_neg(csub_neg(reduce_lazy(a, q, k.mu), k.nq2), k.nq);
-          v.y = csub_neg(csub_neg(reduce_lazy(b, q, k.mu), k.nq2), k.nq);
-        } else {
-          v.x = csub_neg(csub_neg(csub_neg(a, k.nq4), k.nq2), k.nq);
-          v.y = csub_neg(csub_neg(csub_neg(b, k.nq4), k.nq2), k.nq);
-        }
+        v.x = out_word<NOCSUB>(lds[pidx(i)], k, 1);
+        v.y = out_word<NOCSUB>(lds[pidx(i + 1)], k, 1);
         *(ulonglong2*)(dst + gaddr(sub0, i)) = v;
       }
     } else {
