@@ -81,9 +81,11 @@ def lib():
         L.orc_galois_elt.argtypes = [C.c_void_p, C.c_int64]
         L.orc_rotate.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int64, U64P, U64P]
         L.orc_square.argtypes = [C.c_void_p, U64P, C.c_int, U64P, U64P]
-        L.orc_dense.restype = C.c_int
-        L.orc_dense.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int, C.c_int, C.c_int, U64P, U64P,
-                                C.c_int, I64P, C.POINTER(U64P), U64P]
+        L.orc_rotate_ext.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int64, U64P, U64P]
+        for f in (L.orc_dense, L.orc_dense_qp):
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int, C.c_int, C.c_int, U64P, U64P,
+                          C.c_int, I64P, C.POINTER(U64P), U64P]
         _lib = L
     return _lib
 
@@ -254,6 +256,16 @@ class Oracle:
         self.L.orc_rotate(self._h, _p(a.data), a.level, int(r), kp, _p(out))
         return Ciphertext(out, a.level, a.scale)
 
+    def rotate_ext(self, a: Ciphertext, r: int, keys: Keys) -> np.ndarray:
+        """rho^r(a) kept over Q_l u P (no ModDown): uint64 [2][l+1+K][N]."""
+        out = np.empty((2, a.level + 1 + self.pr.K, self.N), dtype=np.uint64)
+        key = keys.rot.get(int(r))
+        if key is None and self.galois(r) != 1:
+            raise KeyError(f"no rotation key for step {r}")
+        kp = _p(key) if key is not None else None
+        self.L.orc_rotate_ext(self._h, _p(a.data), a.level, int(r), kp, _p(out))
+        return out
+
     def square(self, a: Ciphertext, keys: Keys) -> Ciphertext:
         out = np.empty_like(a.data)
         self.L.orc_square(self._h, _p(a.data), a.level, _p(keys.rlk), _p(out))
@@ -281,35 +293,38 @@ class Oracle:
         key_ptrs = (U64P * max(1, len(steps)))(*[_p(keys.rot[s]) for s in steps])
         out = np.empty_like(a.data)
         bias = _p(layer.bias) if layer.bias is not None else None
-        rc = self.L.orc_dense(self._h, _p(a.data), a.level, layer.m, layer.n, layer.n1, _p(layer.pts), bias,
-                              len(steps), _p(step_arr, I64P), key_ptrs, _p(out))
+        fn = self.L.orc_dense_qp if layer.qp else self.L.orc_dense
+        rc = fn(self._h, _p(a.data), a.level, layer.m, layer.n, layer.n1, _p(layer.pts), bias,
+                len(steps), _p(step_arr, I64P), key_ptrs, _p(out))
         if rc != 0:
             raise RuntimeError(f"orc_dense failed ({rc})")
         return Ciphertext(out, a.level, a.scale * layer.pt_scale)
 
     # ----------------------------------------------------------- network
     def prepare_dense(self, W: np.ndarray, b: np.ndarray | None, n1: int, level: int, in_scale: float,
-                      pt_scale: float | None = None) -> "DenseLayer":
+                      pt_scale: float | None = None, qp: bool = False) -> "DenseLayer":
         """Encode the pre-rotated diagonals (scale Delta_w, limbs q_0..q_l only:
-        level-aware encoding) and the bias (scale in_scale * Delta_w, period m)."""
+        level-aware encoding; with qp, also p_0..p_{K-1} for the lazy-ModDown
+        form) and the bias (scale in_scale * Delta_w, period m, limbs q_0..q_l)."""
         pr = self.pr
         pt_scale = pr.scale if pt_scale is None else pt_scale
         m, n = W.shape
         slots = planmod.plaintext_slots(W, n1, pr.slots)
-        pts = np.stack([self.encode(slots[k], pt_scale, level) for k in range(m)])
+        primes = self.qs(level) + (list(pr.p) if qp else [])
+        pts = np.stack([enc.encode(slots[k], pt_scale, primes, self.N) for k in range(m)])
         bias = None
         if b is not None:
             bias = self.encode(planmod.bias_slots(b, pr.slots), in_scale * pt_scale, level)
-        return DenseLayer(m, n, n1, level, pts, bias, pt_scale, in_scale * pt_scale)
+        return DenseLayer(m, n, n1, level, pts, bias, pt_scale, in_scale * pt_scale, qp)
 
-    def prepare_network(self, weights, biases, n1s, level=None, in_scale=None) -> list:
+    def prepare_network(self, weights, biases, n1s, level=None, in_scale=None, qps=None) -> list:
         """Walk levels and scales: dense -> rescale -> (square -> rescale) ..."""
         pr = self.pr
         level = pr.L if level is None else level
         scale = pr.scale if in_scale is None else in_scale
         layers = []
         for li, (W, b, n1) in enumerate(zip(weights, biases, n1s)):
-            lay = self.prepare_dense(W, b, n1, level, scale)
+            lay = self.prepare_dense(W, b, n1, level, scale, qp=bool(qps[li]) if qps else False)
             layers.append(lay)
             scale = scale * lay.pt_scale
             scale = scale / pr.q[level]
@@ -334,10 +349,11 @@ class DenseLayer:
     n: int
     n1: int
     level: int
-    pts: np.ndarray            # uint64 [m][level+1][N], coefficient form, pre-rotated diagonals
+    pts: np.ndarray            # uint64 [m][level+1(+K)][N], coefficient form, pre-rotated diagonals
     bias: np.ndarray | None    # uint64 [level+1][N]
     pt_scale: float
     bias_scale: float
+    qp: bool = False           # diagonals over Q_l u P: lazy-ModDown evaluation (orc_dense_qp)
 
 
 def network_steps(layers_shape) -> list[int]:

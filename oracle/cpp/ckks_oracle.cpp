@@ -364,15 +364,17 @@ void orc_moddown(void* h, const u64* y, int level, u64* out) {
   }
 }
 
-// Key switching of d ([l+1][N]) with key ksk ([dnum][2][L+1+K][N]).  Every
-// non-empty digit is extended by ModUp, optionally permuted by the
-// automorphism g (g == 1: none), multiplied by (b_j, a_j) restricted to
-// Q_l u P, summed over digits, then brought down by ModDown.  out: [2][l+1][N].
-static void keyswitch_core(Ctx& c, const u64* d, int level, const u64* ksk, u64 g, u64* out) {
+// Key-switch inner product of d ([l+1][N]) with key ksk ([dnum][2][L+1+K][N])
+// over the extended basis Q_l u P, before ModDown.  Every non-empty digit is
+// extended by ModUp, optionally permuted by the automorphism g (g == 1: none),
+// multiplied by (b_j, a_j) restricted to Q_l u P and summed over digits.
+// ub, ua: [l+1+K][N].
+static void keyswitch_ext(Ctx& c, const u64* d, int level, const u64* ksk, u64 g, u64* ub, u64* ua) {
   const size_t N = c.N; const int ne = level + 1 + c.np, nt = c.nq + c.np;
   const int ndig = (level + 1 + c.alpha - 1) / c.alpha;
   std::vector<int> eidx(ne); for (int t = 0; t < ne; ++t) eidx[t] = ext_prime(c, level, t);
-  std::vector<u64> ub(ne * N, 0), ua(ne * N, 0), ext(ne * N), tmp(ne * N), prod(ne * N), kb(ne * N), ka(ne * N);
+  std::vector<u64> ext(ne * N), tmp(ne * N), prod(ne * N), kb(ne * N), ka(ne * N);
+  std::fill(ub, ub + ne * N, 0); std::fill(ua, ua + ne * N, 0);
   for (int j = 0; j < ndig; ++j) {
     orc_modup(&c, d, level, j, ext.data());
     if (g != 1) { orc_automorph(&c, ne, eidx.data(), g, ext.data(), tmp.data()); ext.swap(tmp); }
@@ -386,8 +388,15 @@ static void keyswitch_core(Ctx& c, const u64* d, int level, const u64* ksk, u64 
     orc_polymul(&c, ne, eidx.data(), ext.data(), ka.data(), prod.data());
     for (int t = 0; t < ne; ++t) for (size_t k = 0; k < N; ++k) ua[t * N + k] = addmod(ua[t * N + k], prod[t * N + k], c.primes[eidx[t]]);
   }
+}
+
+// Key switching: the extended inner product, then ModDown of both halves.  out: [2][l+1][N].
+static void keyswitch_core(Ctx& c, const u64* d, int level, const u64* ksk, u64 g, u64* out) {
+  const size_t ne = level + 1 + c.np;
+  std::vector<u64> ub(ne * c.N), ua(ne * c.N);
+  keyswitch_ext(c, d, level, ksk, g, ub.data(), ua.data());
   orc_moddown(&c, ub.data(), level, out);
-  orc_moddown(&c, ua.data(), level, out + (size_t)(level + 1) * N);
+  orc_moddown(&c, ua.data(), level, out + (size_t)(level + 1) * c.N);
 }
 
 void orc_keyswitch(void* h, const u64* d, int level, const u64* ksk, u64* out) {
@@ -435,10 +444,42 @@ void orc_square(void* h, const u64* ct, int level, const u64* rlk, u64* out) {
     } }
 }
 
+// Rotation kept over the extended basis (no ModDown), the baby-step form of
+// the lazy-ModDown dense layer: out = (P sigma(c0) + u_b, u_a) over
+// Q_l u P ([2][l+1+K][N]), where (u_b, u_a) is the extended key-switch inner
+// product of c1 and P sigma(c0) is zero on the P-limbs.  ModDown of it equals
+// Rotate(ct, r): [P sigma(c0) + u_b]_P = [u_b]_P, so the conversion is the same,
+// and (P sigma(c0) + u_b - Conv) P^{-1} = sigma(c0) + ModDown(u_b) exactly.
+// r == 0 (mod N/2): (P c0, P c1).
+void orc_rotate_ext(void* h, const u64* ct, int level, i64 r, const u64* ksk, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, ne = nl + c.np;
+  u64 g = orc_galois_elt(h, r);
+  std::vector<u64> ub(ne * N, 0), ua(ne * N, 0), c0r(nl * N);
+  std::vector<int> idx(nl); for (size_t i = 0; i < nl; ++i) idx[i] = (int)i;
+  const u64* c0 = ct;
+  if (g != 1) {
+    keyswitch_ext(c, ct + nl * N, level, ksk, g, ub.data(), ua.data());
+    orc_automorph(h, (int)nl, idx.data(), g, ct, c0r.data());
+    c0 = c0r.data();
+  } else {
+    // identity: the lift of c1 is the a-half
+    for (size_t i = 0; i < nl; ++i) { u64 q = c.primes[i]; u64 Pq = 1;
+      for (int k = 0; k < c.np; ++k) Pq = mulmod(Pq, c.primes[c.nq + k] % q, q);
+      for (size_t k = 0; k < N; ++k) ua[i * N + k] = mulmod(ct[(nl + i) * N + k], Pq, q); }
+  }
+  for (size_t i = 0; i < nl; ++i) {
+    u64 q = c.primes[i]; u64 Pq = 1;
+    for (int k = 0; k < c.np; ++k) Pq = mulmod(Pq, c.primes[c.nq + k] % q, q);
+    for (size_t k = 0; k < N; ++k) ub[i * N + k] = addmod(ub[i * N + k], mulmod(c0[i * N + k], Pq, q), q);
+  }
+  std::memcpy(out, ub.data(), ne * N * sizeof(u64));
+  std::memcpy(out + ne * N, ua.data(), ne * N * sizeof(u64));
+}
+
 // Dense layer y = W x + b on a ciphertext whose slots hold x with period n.
 // Baby-step form (paper: "Algorithmic and cryptographic optimizations", the
 // baby-step rewriting of the convolution sum): diagonal k = n1*j + i of W,
-// pre-rotated by -n1*j, is plaintext pts[k] ([m][l+1][N]).
+// pre-rotated by -n1*j, is plaintext pts[k].
 //   r_i = rho^i(ct), i < n1                    (baby steps; r_0 = ct)
 //   s_j = sum_i MultPlain(r_i, pts[n1 j + i])  (inner sums)
 //   z   = s_0 + sum_{j >= 1} rho^{n1 j}(s_j)   (giant steps, increasing j)
@@ -449,32 +490,83 @@ static const u64* find_key(int nrot, const i64* steps, const u64* const* keys, i
   for (int u = 0; u < nrot; ++u) if (steps[u] == r) return keys[u];
   throw std::runtime_error("missing rotation key");
 }
+static bool dense_shape_ok(const Ctx& c, int m, int n, int n1) {
+  return m > 0 && n > 0 && n1 > 0 && n % m == 0 && m % n1 == 0 && (c.N / 2) % n == 0;
+}
+// Giant steps, rotate-and-sum and bias from the inner sums s[0..n2-1].
+static void dense_tail(void* h, const std::vector<std::vector<u64>>& s, int level, int m, int n, int n1,
+                       const u64* bias, int nrot, const i64* steps, const u64* const* keys, u64* out) {
+  const size_t csz = s[0].size();
+  std::vector<u64> z = s[0], rot(csz);
+  for (size_t j = 1; j < s.size(); ++j) {
+    orc_rotate(h, s[j].data(), level, (i64)n1 * j, find_key(nrot, steps, keys, (i64)n1 * j), rot.data());
+    orc_add(h, z.data(), rot.data(), level, z.data());
+  }
+  for (int t = n / 2; t >= m; t /= 2) {
+    orc_rotate(h, z.data(), level, t, find_key(nrot, steps, keys, t), rot.data());
+    orc_add(h, z.data(), rot.data(), level, z.data());
+  }
+  if (bias) orc_add_plain(h, z.data(), bias, level, z.data());
+  std::memcpy(out, z.data(), csz * sizeof(u64));
+}
+
+// pts: [m][l+1][N].
 int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
               int nrot, const i64* steps, const u64* const* keys, u64* out) {
   Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, csz = 2 * nl * N;
-  if (m <= 0 || n <= 0 || n1 <= 0 || n % m || m % n1 || (c.N / 2) % n) return -1;
+  if (!dense_shape_ok(c, m, n, n1)) return -1;
   const int n2 = m / n1;
   try {
     std::vector<std::vector<u64>> baby(n1, std::vector<u64>(csz));
     std::memcpy(baby[0].data(), ct, csz * sizeof(u64));
     for (int i = 1; i < n1; ++i) orc_rotate(h, ct, level, i, find_key(nrot, steps, keys, i), baby[i].data());
-    std::vector<u64> z(csz, 0), s(csz), prod(csz), rot(csz);
-    for (int j = 0; j < n2; ++j) {
-      std::fill(s.begin(), s.end(), 0);
+    std::vector<std::vector<u64>> s(n2, std::vector<u64>(csz, 0));
+    std::vector<u64> prod(csz);
+    for (int j = 0; j < n2; ++j)
       for (int i = 0; i < n1; ++i) {
         orc_mult_plain(h, baby[i].data(), pts + (size_t)(n1 * j + i) * nl * N, level, prod.data());
-        orc_add(h, s.data(), prod.data(), level, s.data());
+        orc_add(h, s[j].data(), prod.data(), level, s[j].data());
       }
-      if (j == 0) { z = s; continue; }
-      orc_rotate(h, s.data(), level, (i64)n1 * j, find_key(nrot, steps, keys, (i64)n1 * j), rot.data());
-      orc_add(h, z.data(), rot.data(), level, z.data());
+    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, out);
+  } catch (const std::exception&) { return -3; }
+  return 0;
+}
+
+// Dense layer with lazy ModDown (double hoisting): the baby-step rotations stay
+// over Q_l u P (orc_rotate_ext; r_0 = (P c0, P c1)), the inner sums are taken
+// there with plaintexts encoded over Q_l u P (pts: [m][l+1+K][N]), and each
+// inner sum is brought down once:
+//   s_j = ModDown(sum_i r_i^ext (.) pts[n1 j + i])   (both polynomials)
+// then giant steps, rotate-and-sum and bias as in orc_dense.  Not in the paper:
+// a reordering of its baby-step/giant-step evaluation that moves the ModDown
+// behind the plaintext products (one per inner sum instead of one per baby step).
+int orc_dense_qp(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+                 int nrot, const i64* steps, const u64* const* keys, u64* out) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, ne = nl + c.np, csz = 2 * nl * N, esz = 2 * ne * N;
+  if (!dense_shape_ok(c, m, n, n1)) return -1;
+  const int n2 = m / n1;
+  try {
+    std::vector<int> eidx(ne); for (size_t t = 0; t < ne; ++t) eidx[t] = ext_prime(c, level, (int)t);
+    std::vector<std::vector<u64>> baby(n1, std::vector<u64>(esz));
+    for (int i = 0; i < n1; ++i)
+      orc_rotate_ext(h, ct, level, i, i ? find_key(nrot, steps, keys, i) : nullptr, baby[i].data());
+    std::vector<std::vector<u64>> s(n2, std::vector<u64>(csz));
+    std::vector<u64> acc(esz), prod(ne * N);
+    for (int j = 0; j < n2; ++j) {
+      std::fill(acc.begin(), acc.end(), 0);
+      for (int i = 0; i < n1; ++i) {
+        const u64* pt = pts + (size_t)(n1 * j + i) * ne * N;
+        for (int p = 0; p < 2; ++p) {
+          orc_polymul(h, (int)ne, eidx.data(), baby[i].data() + p * ne * N, pt, prod.data());
+          u64* a = acc.data() + p * ne * N;
+          for (size_t t = 0; t < ne; ++t) for (size_t k = 0; k < N; ++k)
+            a[t * N + k] = addmod(a[t * N + k], prod[t * N + k], c.primes[eidx[t]]);
+        }
+      }
+      orc_moddown(h, acc.data(), level, s[j].data());
+      orc_moddown(h, acc.data() + ne * N, level, s[j].data() + nl * N);
     }
-    for (int t = n / 2; t >= m; t /= 2) {
-      orc_rotate(h, z.data(), level, t, find_key(nrot, steps, keys, t), rot.data());
-      orc_add(h, z.data(), rot.data(), level, z.data());
-    }
-    if (bias) orc_add_plain(h, z.data(), bias, level, z.data());
-    std::memcpy(out, z.data(), csz * sizeof(u64));
+    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, out);
   } catch (const std::exception&) { return -3; }
   return 0;
 }

@@ -253,7 +253,8 @@ class Tiny:
             out.append([((y[i][k] - big[k]) * pinv) % q for k in range(self.n)])
         return out
 
-    def _ks(self, d, level, ksk, g):
+    def _ks_ext(self, d, level, ksk, g):
+        """Key-switch inner product over Q_l u P, before ModDown."""
         ext_mods = self._ext(level)
         ext_idx = list(range(level + 1)) + [len(self.q) + k for k in range(len(self.p))]
         ub = [[0] * self.n for _ in ext_mods]
@@ -267,6 +268,10 @@ class Tiny:
                 pa = negacyclic_mul(ext[t], ksk[j][1][ki], m)
                 ub[t] = [(x + y) % m for x, y in zip(ub[t], pb)]
                 ua[t] = [(x + y) % m for x, y in zip(ua[t], pa)]
+        return ub, ua
+
+    def _ks(self, d, level, ksk, g):
+        ub, ua = self._ks_ext(d, level, ksk, g)
         return [self.moddown(ub, level), self.moddown(ua, level)]
 
     def keyswitch(self, d, level, ksk):
@@ -289,16 +294,25 @@ class Tiny:
         return [[[(x + y) % q for x, y in zip(d0[i], ks[0][i])] for i, q in enumerate(mods)],
                 [[(x + y) % q for x, y in zip(d1[i], ks[1][i])] for i, q in enumerate(mods)]]
 
-    def dense(self, ct, level, m, n, n1, pts, bias, rot):
-        n2 = m // n1
-        baby = [ct] + [self.rotate(ct, level, i, rot) for i in range(1, n1)]
-        z = None
-        for j in range(n2):
-            s = None
-            for i in range(n1):
-                prod = self.mult_plain(baby[i], pts[n1 * j + i], level)
-                s = prod if s is None else self.add(s, prod, level)
-            z = s if j == 0 else self.add(z, self.rotate(s, level, n1 * j, rot), level)
+    def rotate_ext(self, ct, level, r, rot):
+        """rho^r(ct) over Q_l u P without ModDown: (P sigma(c0) + u_b, u_a);
+        P times anything vanishes modulo the p_k.  r = 0: (P c0, P c1)."""
+        P = math.prod(self.p)
+        mods = self.q[: level + 1]
+        zeros = [[0] * self.n for _ in self.p]
+        g = self.galois(r)
+        if g == 1:
+            return [[[v * P % q for v in ct[k][i]] for i, q in enumerate(mods)] + [row[:] for row in zeros]
+                    for k in range(2)]
+        ub, ua = self._ks_ext(ct[1], level, rot[int(r)], g)
+        c0 = [automorph(row, g, q) for row, q in zip(ct[0], mods)]
+        b = [[(x + v * P) % q for x, v in zip(ub[i], c0[i])] for i, q in enumerate(mods)] + ub[level + 1:]
+        return [b, ua]
+
+    def _dense_tail(self, sums, level, m, n, n1, bias, rot):
+        z = sums[0]
+        for j in range(1, len(sums)):
+            z = self.add(z, self.rotate(sums[j], level, n1 * j, rot), level)
         t = n // 2
         while t >= m:
             z = self.add(z, self.rotate(z, level, t, rot), level)
@@ -306,3 +320,33 @@ class Tiny:
         if bias is not None:
             z = self.add_plain(z, bias, level)
         return z
+
+    def dense(self, ct, level, m, n, n1, pts, bias, rot):
+        n2 = m // n1
+        baby = [ct] + [self.rotate(ct, level, i, rot) for i in range(1, n1)]
+        sums = []
+        for j in range(n2):
+            s = None
+            for i in range(n1):
+                prod = self.mult_plain(baby[i], pts[n1 * j + i], level)
+                s = prod if s is None else self.add(s, prod, level)
+            sums.append(s)
+        return self._dense_tail(sums, level, m, n, n1, bias, rot)
+
+    def dense_qp(self, ct, level, m, n, n1, pts, bias, rot):
+        """Lazy-ModDown dense: inner sums over Q_l u P (pts over Q_l u P), one
+        ModDown per inner sum, then the same giant steps / rotate-and-sum / bias."""
+        n2 = m // n1
+        mods = self._ext(level)
+        baby = [self.rotate_ext(ct, level, i, rot) for i in range(n1)]
+        sums = []
+        for j in range(n2):
+            acc = [[[0] * self.n for _ in mods] for _ in range(2)]
+            for i in range(n1):
+                pt = pts[n1 * j + i]
+                for k in range(2):
+                    for t, q in enumerate(mods):
+                        pr = negacyclic_mul(baby[i][k][t], pt[t], q)
+                        acc[k][t] = [(x + y) % q for x, y in zip(acc[k][t], pr)]
+            sums.append([self.moddown(acc[0], level), self.moddown(acc[1], level)])
+        return self._dense_tail(sums, level, m, n, n1, bias, rot)

@@ -326,6 +326,84 @@ def test_dense_slots(o10, keys10, m, n, n1):
     assert np.max(np.abs(got - want)) < 2.0 ** -14
 
 
+# ------------------------------------------ lazy-ModDown (double-hoisted) dense
+@pytest.mark.parametrize("r", [0, 1, 3, -1])
+def test_rotate_ext_moddown_is_rotate(o10, keys10, r):
+    # ModDown(P sigma(c0) + u_b) = sigma(c0) + ModDown(u_b) exactly: the
+    # extended baby step brought down equals the ordinary rotation bit for bit.
+    z = np.random.default_rng(40 + r).uniform(-1, 1, o10.pr.slots)
+    ct = o10.encrypt(z, keys10.pk, 90)
+    ext = o10.rotate_ext(ct, r, keys10)
+    L = ct.level
+    assert ext.shape == (2, L + 1 + o10.pr.K, o10.N)
+    assert not ext[:, L + 1:].any() if r == 0 else True
+    down = np.stack([o10.moddown(ext[0], L), o10.moddown(ext[1], L)])
+    assert np.array_equal(down, o10.rotate(ct, r, keys10).data)
+
+
+def _unit_layer(o, level, m, n, n1, taps):
+    """Diagonals over Q_l u P equal to the constant polynomial 1 at the listed
+    indices and 0 elsewhere (no encoding involved)."""
+    ne = level + 1 + o.pr.K
+    pts = np.zeros((m, ne, o.N), dtype=np.uint64)
+    for k in taps:
+        pts[k, :, 0] = 1
+    return ckks.DenseLayer(m, n, n1, level, pts, None, 1.0, 1.0, qp=True)
+
+
+def test_dense_qp_unit_diagonals_exact(o10, keys10):
+    # With 0/1 constant diagonals the P-limbs of every product are those of
+    # the extended rotations themselves, so one ModDown per inner sum is the
+    # sum of exact rotations: closed forms in terms of the ordinary rotate.
+    z = np.random.default_rng(41).uniform(-1, 1, o10.pr.slots)
+    ct = o10.encrypt(z, keys10.pk, 91)
+    R1 = o10.rotate(ct, 1, keys10)
+    got = o10.dense(ct, _unit_layer(o10, ct.level, 2, 2, 2, [1]), keys10)
+    assert np.array_equal(got.data, R1.data)
+    got = o10.dense(ct, _unit_layer(o10, ct.level, 2, 2, 2, [0, 1]), keys10)
+    assert np.array_equal(got.data, o10.add(ct, R1).data)
+    # two inner sums, both = rho^1(ct): z = s_0 + rho^2(s_1)
+    got = o10.dense(ct, _unit_layer(o10, ct.level, 4, 4, 2, [1, 3]), keys10)
+    assert np.array_equal(got.data, o10.add(R1, o10.rotate(R1, 2, keys10)).data)
+
+
+@pytest.mark.parametrize("m,n", [(8, 64), (16, 16)])
+def test_dense_qp_one_baby_step_equals_dense(o10, keys10, m, n):
+    # n1 = 1: the only extended "rotation" is P ct, and ModDown(P x) = x
+    # exactly, so the lazy form reproduces the ordinary dense layer bit for bit.
+    rng = np.random.default_rng(42 + m)
+    W, b, x = rng.normal(0, 0.1, (m, n)), rng.normal(0, 0.1, m), rng.uniform(-1, 1, n)
+    steps = plan.rotation_steps(m, n, 1)
+    keys = o10.keygen(11, steps=steps) if not set(steps) <= set(keys10.rot) else keys10
+    ct = o10.encrypt(plan.input_slots(x, o10.pr.slots), keys.pk, 92)
+    std = o10.dense(ct, o10.prepare_dense(W, b, 1, ct.level, ct.scale), keys)
+    lazy = o10.dense(ct, o10.prepare_dense(W, b, 1, ct.level, ct.scale, qp=True), keys)
+    assert np.array_equal(std.data, lazy.data)
+
+
+@pytest.mark.parametrize("m,n,n1", [(8, 64, 2), (8, 64, 8), (16, 16, 4), (16, 64, 16)])
+def test_dense_qp_slots(o10, keys10, m, n, n1):
+    # General diagonals: the result decrypts to W x + b (FP64) and to the
+    # ordinary dense layer's value within the rounding of one ModDown.
+    pr = o10.pr
+    rng = np.random.default_rng(m * 100 + n + n1 + 7)
+    W, b, x = rng.normal(0, 0.1, (m, n)), rng.normal(0, 0.1, m), rng.uniform(-1, 1, n)
+    steps = plan.rotation_steps(m, n, n1)
+    keys = o10.keygen(11, steps=steps) if not set(steps) <= set(keys10.rot) else keys10
+    ct = o10.encrypt(plan.input_slots(x, pr.slots), keys.pk, 93)
+    lay = o10.prepare_dense(W, b, n1, ct.level, ct.scale, qp=True)
+    assert lay.pts.shape == (m, ct.level + 1 + pr.K, pr.n)
+    out = o10.dense(ct, lay, keys)
+    got = o10.decrypt_decode(o10.rescale(out), keys.sk).real
+    want = plan.bias_slots(W @ x + b, pr.slots)
+    assert np.max(np.abs(got - want)) < 2.0 ** -14
+    std = o10.dense(ct, o10.prepare_dense(W, b, n1, ct.level, ct.scale), keys)
+    ref = o10.decrypt_decode(o10.rescale(std), keys.sk).real
+    assert np.max(np.abs(got - ref)) < 2.0 ** -18
+    if n1 > 1:
+        assert not np.array_equal(out.data, std.data)   # a different rounding point
+
+
 def test_dense_plan_slot_algebra():
     # The plan's diagonals and pre-rotation reproduce W x in plain slot arithmetic.
     rng = np.random.default_rng(16)
@@ -408,6 +486,13 @@ def test_tiny_bit_exact(oracle_lib, log_n):
     lay = o.prepare_dense(W, b, n1, L, ct.scale)
     got = o.dense(ct, lay, K)
     want = T.dense(c, L, m, n, n1, lay.pts.tolist(), lay.bias.tolist(), rot)
+    assert np.array_equal(got.data, A(want))
+    # lazy-ModDown form: extended rotation and the dense layer
+    assert np.array_equal(o.rotate_ext(ct, 3, K), A(T.rotate_ext(c, L, 3, rot)))
+    assert np.array_equal(o.rotate_ext(ct, 0, K), A(T.rotate_ext(c, L, 0, rot)))
+    lay_qp = o.prepare_dense(W, b, n1, L, ct.scale, qp=True)
+    got = o.dense(ct, lay_qp, K)
+    want = T.dense_qp(c, L, m, n, n1, lay_qp.pts.tolist(), lay_qp.bias.tolist(), rot)
     assert np.array_equal(got.data, A(want))
     # Two-layer network: dense -> rescale -> square -> rescale -> dense.
     W2 = rng.normal(0, 0.1, (2, m))
