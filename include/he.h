@@ -159,6 +159,26 @@ int he_dense_load(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32_t 
                   he_dense** out);
 int he_dense_free(he_dense* d);
 
+/* Lazy-ModDown form of a dense layer (double hoisting; an evaluation order
+ * the paper does not use, chosen per layer as a plan parameter because it
+ * changes the rounding).  With flags = HE_DENSE_QP, pt_diag is
+ * uint64[m][level+1+K][N]: the same integer diagonals reduced over
+ * q_0..q_level then p_0..p_{K-1}.  he_eval_dense(_batch) then keeps every
+ * baby-step rotation over Q_level u P without its ModDown,
+ *   r_0 = (P c0, P c1),  r_i = (P sigma_i(c0) + u_b, u_a)  ((u_b, u_a): the
+ *   key-switch inner product of c1 for step i over Q_level u P),
+ * forms s_j = ModDown(sum_i MultPlain(r_i, pt_{n1 j + i})) (both
+ * polynomials; one ModDown per inner sum instead of one per baby step), and
+ * continues with the giant steps, rotate-and-sum and bias as above.  The
+ * bias stays uint64[level+1][N].  flags = 0 is he_dense_load /
+ * he_dense_bytes; other bits: HE_EINVAL.  dev: the diagonals (NTT form), their
+ * Shoup companions, then the bias, as above. */
+#define HE_DENSE_QP 1u
+size_t he_dense_bytes_ex(const he_ctx* ctx, uint32_t level, uint32_t m, int has_bias, uint32_t flags);
+int he_dense_load_ex(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
+                     const uint64_t* bias, double pt_scale, double bias_scale, uint32_t flags, void* dev,
+                     size_t bytes, he_dense** out);
+
 /* Ciphertext import/export.  *_import: host coefficient form -> inout->dev
  * (caller sets inout->dev; level and scale are written).  *_export: blocking
  * (synchronises the stream), writes host coefficient form [2][level+1][N].

@@ -143,8 +143,9 @@ int build_tables(he_ctx* c) {
   if ((rc = upload(c, &c->d_modup_hatmod, hmod))) return rc;
 
   // ModDown.
-  // [np][2] (P/p_k)^{-1} mod p_k; [np][nq][2] (P/p_k) mod q_i; [nq][2] P^{-1} mod q_i (Shoup pairs)
-  std::vector<u64> md((size_t)np * 2 + (size_t)np * nq * 2 + (size_t)nq * 2);
+  // [np][2] (P/p_k)^{-1} mod p_k; [np][nq][2] (P/p_k) mod q_i; [nq][2] P^{-1} mod q_i;
+  // [nq][2] P mod q_i (Shoup pairs)
+  std::vector<u64> md((size_t)np * 2 + (size_t)np * nq * 2 + (size_t)nq * 4);
   for (u32 k = 0; k < np; ++k) {
     const u64 pk = c->primes[nq + k];
     u64 inv = 1;
@@ -168,6 +169,8 @@ int build_tables(he_ctx* c) {
     const u64 pinv = inv_mod(P, qi);
     md[2 * np + 2 * (size_t)np * nq + 2 * i] = pinv;
     md[2 * np + 2 * (size_t)np * nq + 2 * i + 1] = shoup_of(pinv, qi);
+    md[2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq + 2 * i] = P;
+    md[2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq + 2 * i + 1] = shoup_of(P, qi);
   }
   if ((rc = upload(c, &c->d_moddown, md))) return rc;
 
@@ -210,7 +213,7 @@ thread_local char g_last_error[256] = "";
 static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
     "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner_steps", "moddown_conv", "ks_final", "ks_final_steps",
-    "ks_final_multplain", "ks_final_sum", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
+    "ks_final_multplain", "ks_final_sum", "ext_multplain", "moddown_final", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
     "add_plain", "copy_polys", "shoup_companion"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
@@ -347,8 +350,14 @@ size_t he_key_bytes(const he_ctx* c, uint32_t n_rot) {
   return c ? (size_t)(1 + n_rot) * 2 * c->dnum * 2 * nt_of(c) * c->N * sizeof(u64) : 0;
 }
 
+size_t he_dense_bytes_ex(const he_ctx* c, uint32_t level, uint32_t m, int has_bias, uint32_t flags) {
+  if (!c) return 0;
+  const size_t pl = level + 1 + ((flags & HE_DENSE_QP) ? c->np : 0);
+  return (2 * (size_t)m * pl + (has_bias ? level + 1 : 0)) * c->N * sizeof(u64);
+}
+
 size_t he_dense_bytes(const he_ctx* c, uint32_t level, uint32_t m, int has_bias) {
-  return c ? (2 * (size_t)m + (has_bias ? 1 : 0)) * (level + 1) * c->N * sizeof(u64) : 0;
+  return he_dense_bytes_ex(c, level, m, has_bias, 0);
 }
 
 int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t* steps, const uint64_t* const* rot,
@@ -369,7 +378,7 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
     int rc = launch_ntt(c, pb, false);
     if (rc) return rc;
     // Shoup companions of every key word, limb t over prime t of q_0..q_L, p_0..p_{K-1}
-    return launch_shoup_companion(c, c->dnum * 2, nt_of(c) - 1, dst, dst + words);
+    return launch_shoup_companion(c, c->dnum * 2, nt_of(c), nt_of(c) - 1, dst, dst + words);
   };
   int rc;
   if (relin) {
@@ -388,14 +397,16 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
   return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
 }
 
-int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
-                  const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes, he_dense** out) {
-  if (!c || !pt_diag || !dev || !out) return HE_EINVAL;
+int he_dense_load_ex(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
+                     const uint64_t* bias, double pt_scale, double bias_scale, uint32_t flags, void* dev, size_t bytes,
+                     he_dense** out) {
+  if (!c || !pt_diag || !dev || !out || (flags & ~(uint32_t)HE_DENSE_QP)) return HE_EINVAL;
   auto pow2 = [](u32 v) { return v && !(v & (v - 1)); };
   if (level >= c->nq) return HE_ELEVEL;
   if (!pow2(m) || !pow2(n) || !pow2(n1) || n % m || m % n1 || (c->N / 2) % n) return HE_EINVAL;
-  if (bytes < he_dense_bytes(c, level, m, bias != nullptr)) return HE_ENOMEM;
-  const size_t limb = c->N, per = (size_t)(level + 1) * limb;
+  if (bytes < he_dense_bytes_ex(c, level, m, bias != nullptr, flags)) return HE_ENOMEM;
+  const u32 pl = level + 1 + ((flags & HE_DENSE_QP) ? c->np : 0);
+  const size_t limb = c->N, per = (size_t)pl * limb;
   u64* d = (u64*)dev;
   if (hipMemcpyAsync(d, pt_diag, (size_t)m * per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return HE_EDEVICE;
@@ -403,18 +414,19 @@ int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1
     PolyBatch pb;
     std::memset(&pb, 0, sizeof(pb));
     pb.nitems = std::min<u32>(HE_MAXB, m - k0);
-    pb.npoly = level + 1;
+    pb.npoly = pl;
     for (u32 b = 0; b < pb.nitems; ++b) pb.src[b] = pb.dst[b] = d + (size_t)(k0 + b) * per;
-    for (u32 r = 0; r <= level; ++r) pb.prime[r] = (uint8_t)r;
+    for (u32 r = 0; r < pl; ++r) pb.prime[r] = (uint8_t)ext_prime(c, level, r);
     int rc = launch_ntt(c, pb, false);
     if (rc) return rc;
   }
-  int rc = launch_shoup_companion(c, m, level, d, d + (size_t)m * per);
+  int rc = launch_shoup_companion(c, m, pl, level, d, d + (size_t)m * per);
   if (rc) return rc;
   u64* db = nullptr;
   if (bias) {
     db = d + (size_t)2 * m * per;
-    if (hipMemcpyAsync(db, bias, per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
+    const size_t bper = (size_t)(level + 1) * limb;
+    if (hipMemcpyAsync(db, bias, bper * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
     PolyBatch pb = one_item(db, level + 1, level + 1, 0);
     int rc = launch_ntt(c, pb, false);
     if (rc) return rc;
@@ -422,9 +434,14 @@ int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1
   if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
   he_dense* h = new (std::nothrow) he_dense;
   if (!h) return HE_ENOMEM;
-  *h = he_dense{c, level, m, n, n1, m / n1, pt_scale, bias_scale, d, db};
+  *h = he_dense{c, level, m, n, n1, m / n1, pt_scale, bias_scale, pl, d, db};
   *out = h;
   return HE_OK;
+}
+
+int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
+                  const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes, he_dense** out) {
+  return he_dense_load_ex(c, level, m, n, n1, pt_diag, bias, pt_scale, bias_scale, 0, dev, bytes, out);
 }
 
 int he_dense_free(he_dense* d) {

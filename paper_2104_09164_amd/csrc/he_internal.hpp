@@ -49,7 +49,7 @@ struct PolyBatch {
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
   TK_MODUP_CONV, TK_KS_INNER_STEPS, TK_MODDOWN_CONV, TK_KS_FINAL, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM,
-  TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
+  TK_EXT_MP, TK_MODDOWN_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
   TK_COUNT
 };
 const char* trace_name(int kind);
@@ -119,7 +119,8 @@ struct he_dense {
   he_ctx* ctx;
   u32 level, m, n, n1, n2;
   double pt_scale, bias_scale;
-  u64* pts;    // [m][level+1][N], NTT form, then their Shoup companions floor(w 2^64 / q), same shape
+  u32 pl;      // limbs per diagonal: level+1, or level+1+K over Q_l u P (lazy-ModDown evaluation)
+  u64* pts;    // [m][pl][N], NTT form, then their Shoup companions floor(w 2^64 / q), same shape
   u64* bias;   // [level+1][N], NTT form, or null
 };
 

@@ -30,13 +30,15 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   WS dummy;
   WS& x = w ? *w : dummy;
   // coef and ext hold the ModUp of every giant step (GJ steps of B items);
-  // u and conv every step of one step-batched key switch
-  const size_t GJ = giant_group(n2), G = std::max<size_t>(ks_group(n1), GJ);
+  // u and conv every step of one step-batched key switch.  ext also holds the
+  // n2 B lazy-ModDown inner sums over Q u P (the digits are dead by then), and
+  // conv their conversions.
+  const size_t GJ = giant_group(n2), G = std::max<size_t>(ks_group(n1), GJ), J2 = n2 ? n2 : 1;
   take(&x.rtmp, B * csz);
   take(&x.coef, GJ * B * L1 * N);
-  take(&x.ext, GJ * B * c->dnum * E * N);
+  take(&x.ext, std::max(GJ * c->dnum, 2 * J2) * B * E * N);
   take(&x.u, G * B * 2 * E * N);
-  take(&x.conv, G * B * csz);
+  take(&x.conv, std::max(G, J2) * B * csz);
   take(&x.d01, B * csz);
   take(&x.d2, B * L1 * N);
   take(&x.red, B * csz);
@@ -196,6 +198,29 @@ int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, const OwnMap& ow
   pf.stride = (size_t)2 * (l + 1) * N;
   for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
   return launch_ntt(c, pf, false);
+}
+
+// ModDown of Z ciphertexts over Q_l u P (y = [Z][2][l+1+K][N], NTT form, limbs
+// in [0, q)) into out + z 2 (l+1) N: inverse NTT of the P-limbs in place,
+// conversion to Q_l (conv, coefficient form), its NTT, and the combine.
+int moddown_items(he_ctx* c, u32 l, u32 Z, u64* y, u64* conv, u64* out) {
+  const size_t N = c->N;
+  const u32 ne = l + 1 + c->np;
+  PolyBatch pi = batch_of(Z);
+  pi.npoly = 2 * ne;
+  pi.src[0] = pi.dst[0] = y;
+  pi.stride = (size_t)2 * ne * N;
+  for (u32 r = 0; r < 2 * ne; ++r) pi.prime[r] = (r % ne) > l ? (uint8_t)ext_prime(c, l, r % ne) : 0xFF;
+  int rc = launch_ntt(c, pi, true);
+  if (!rc) rc = launch_moddown_conv(c, l, Z, y, conv);
+  if (rc) return rc;
+  PolyBatch pf = batch_of(Z);
+  pf.npoly = 2 * (l + 1);
+  pf.src[0] = pf.dst[0] = conv;
+  pf.stride = (size_t)2 * (l + 1) * N;
+  for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
+  if ((rc = launch_ntt(c, pf, false))) return rc;
+  return launch_moddown_final(c, l, Z, y, conv, out);
 }
 
 int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
@@ -455,10 +480,19 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       sk.galois[i] = baby[i + 1]->galois;
       sk.galois_inv[i] = galois_inverse(c, baby[i + 1]->galois);
     }
-    if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
-    if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
-  } else if ((rc = launch_multplain(c, l, n2, inI, d->pts, w.giant))) {
-    return rc;                                     // n1 = 1: s_j = pts[j] (.) in
+    if (d->pl > l + 1) {
+      // lazy ModDown: the inner products stay over Q_l u P; the inner sums
+      // are formed there (the extended rotations only in registers) into
+      // the dead digit region, then each sum is brought down once
+      if ((rc = launch_ks_inner_steps(c, l, n, S, w.ext, 0, own_of(n, c1in), sk, w.u))) return rc;
+      if ((rc = launch_ext_multplain(c, l, n, n1, n2, w.u, sk, inI, d->pts, w.ext))) return rc;
+      if ((rc = moddown_items(c, l, n2 * n, w.ext, w.conv, w.giant))) return rc;
+    } else {
+      if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
+      if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
+    }
+  } else if ((rc = launch_multplain(c, l, n2, inI, d->pts, d->pl, w.giant))) {
+    return rc;                                     // n1 = 1: s_j = pts[j] (.) in (= ModDown(pts[j] (.) P in))
   }
 
   // Giant steps then rotate-and-sum, each a full key switch; the last one

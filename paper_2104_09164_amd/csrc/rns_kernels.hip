@@ -298,6 +298,99 @@ __global__ void __launch_bounds__(BS) k_ks_final_mp(const u64* __restrict__ u, c
     ks_final_mp_body<JC, false>(u, conv, keys, in, pts, sums, pk, md, N, logn, l, np, nq, n1, n2, b, k, li, jc);
 }
 
+// Lazy-ModDown inner sums over Q_l u P.  With u holding the extended
+// key-switch inner products of baby steps i = 1 .. n1-1 (step s = i - 1):
+//   r_0 = (P c0, P c1),  r_i = (P c0[perm_{g_i}] + u_b, u_a)  (P x is 0 on the P-limbs),
+//   sqp[j][b] = sum_i pts[n1 j + i] (.) r_i,  limb t of ne = l+1+K.
+// The extended rotations exist only in registers.  One thread: coefficient
+// k of limb t of item b, giant sums jc JC .. jc JC + JC - 1.  u's Q-limbs are
+// lazy (below 32q, or 4q for q >= 2^58); adding the lazy P c0 product (below
+// 2q) stays below 2^64 and the plaintext product takes any 64-bit input.
+template <int JC, bool LAZY>
+__device__ __forceinline__ void ext_mp_body(const u64* __restrict__ u, const StepKeys& keys, const Items& in,
+                                            const u64* __restrict__ pts, u64* __restrict__ sqp, const PrimeConst& pk,
+                                            u64 pw, u64 pws, u32 N, u32 logn, u32 l, u32 ne, u32 n1, u32 n2, u32 b,
+                                            u32 k, u32 t, u32 jc) {
+  const u32 B = in.n;
+  const bool qlimb = t <= l;
+  const u64 q = pk.q;
+  const size_t comp = (size_t)n1 * n2 * ne * N;   // companions follow the m diagonals
+  const u64* x = in.p[b];
+  u64 t0[JC], t1[JC];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) t0[jj] = t1[jj] = 0;
+  if (qlimb) {
+    const u64 r0 = shoup(x[(size_t)t * N + k], pw, pws, q), r1 = shoup(x[(size_t)(l + 1 + t) * N + k], pw, pws, q);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const size_t o = ((size_t)n1 * (jc * JC + jj) * ne + t) * N + k;
+      const u64 pt = pts[o], ps = pts[comp + o];
+      t0[jj] = mp_add<LAZY>(t0[jj], r0, pt, ps, pk);
+      t1[jj] = mp_add<LAZY>(t1[jj], r1, pt, ps, pk);
+    }
+  }
+  for (u32 i = 1; i < n1; ++i) {
+    const size_t ui = ((size_t)((i - 1) * B + b) * 2 * ne + t) * N + k;
+    u64 r0 = u[ui];
+    const u64 r1 = u[ui + (size_t)ne * N];
+    if (qlimb) r0 += shoup_lazy(x[(size_t)t * N + galois_perm(k, keys.galois[i - 1], logn)], pw, pws, q);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const size_t o = (((size_t)n1 * (jc * JC + jj) + i) * ne + t) * N + k;
+      const u64 pt = pts[o], ps = pts[comp + o];
+      t0[jj] = mp_add<LAZY>(t0[jj], r0, pt, ps, pk);
+      t1[jj] = mp_add<LAZY>(t1[jj], r1, pt, ps, pk);
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = sqp + ((size_t)(jc * JC + jj) * B + b) * 2 * ne * N;
+    o[(size_t)t * N + k] = mp_final<LAZY>(t0[jj], pk);
+    o[(size_t)(ne + t) * N + k] = mp_final<LAZY>(t1[jj], pk);
+  }
+}
+
+// 1-D grid over B x (N/BS, ne, n2/JC) tiles: the items of a tile share its
+// plaintext words (xcd_decode).
+template <int JC>
+__global__ void __launch_bounds__(BS) k_ext_mp(const u64* __restrict__ u, StepKeys keys, Items in,
+                                               const u64* __restrict__ pts, u64* __restrict__ sqp,
+                                               const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                               u32 N, u32 logn, u32 l, u32 np, u32 nq, u32 n1, u32 n2) {
+  const u32 nkb = N / BS, ne = l + 1 + np;
+  u32 b, tile;
+  xcd_decode(blockIdx.x, in.n, nkb * ne * (n2 / JC), b, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x;
+  const u32 t = (tile / nkb) % ne, jc = tile / (nkb * ne);
+  const u32 pr = t <= l ? t : nq + (t - l - 1);
+  const PrimeConst pk = pc[pr];
+  const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
+  const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
+  if (pk.q < kLazyMP)
+    ext_mp_body<JC, true>(u, keys, in, pts, sqp, pk, pw, pws, N, logn, l, ne, n1, n2, b, k, t, jc);
+  else
+    ext_mp_body<JC, false>(u, keys, in, pts, sqp, pk, pw, pws, N, logn, l, ne, n1, n2, b, k, t, jc);
+}
+
+// ModDown output of Z extended ciphertexts: out(z) = (y_Q - conv) P^{-1} over
+// limbs i <= l (NTT domain), y = [Z][2][ne][N] (Q-limbs in [0, q)), conv =
+// [Z][2][l+1][N]; out(z) at out + z csz.  grid: (N/BS, l+1, Z)
+__global__ void __launch_bounds__(BS) k_moddown_final(const u64* __restrict__ y, const u64* __restrict__ conv,
+                                                      u64* __restrict__ out, const PrimeConst* __restrict__ pc,
+                                                      const u64* __restrict__ md, u32 N, u32 l, u32 np, u32 nq) {
+  const u32 k = blockIdx.x * BS + threadIdx.x;
+  const u32 i = blockIdx.y, z = blockIdx.z;
+  const u32 ne = l + 1 + np;
+  const u64 q = pc[i].q;
+  const u64* pinv = md + 2 * np + 2 * (size_t)np * nq;   // [nq][2]
+  const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
+  const size_t yi = ((size_t)z * 2 * ne + i) * N + k;
+  const size_t ci = ((size_t)z * 2 * (l + 1) + i) * N + k;
+  u64* o = out + (size_t)z * 2 * (l + 1) * N;
+  o[(size_t)i * N + k] = shoup(y[yi] + q - conv[ci], w, wsh, q);
+  o[(size_t)(l + 1 + i) * N + k] = shoup(y[yi + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q);
+}
+
 // grid: (N/BS, l+1, B).  One thread: coefficient k of limb i of item b, all
 // J giant steps summed in registers (modular sums are exact, so the order of
 // the terms does not change the result).
@@ -398,18 +491,18 @@ __global__ void __launch_bounds__(BS) k_ks_final(const u64* __restrict__ u, cons
 // plaintext words (xcd_decode).  One product per giant sum: s_j = pts[j] (.) in.
 template <int JC>
 __global__ void __launch_bounds__(BS) k_multplain(Items in, const u64* __restrict__ pts, u64* __restrict__ s,
-                                                  const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n2) {
+                                                  const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n2, u32 pl) {
   const u32 nkb = N / BS;
   u32 b, tile;
   xcd_decode(blockIdx.x, in.n, nkb * (l + 1) * (n2 / JC), b, tile);
   const u32 k = (tile % nkb) * BS + threadIdx.x;
   const u32 li = (tile / nkb) % (l + 1), jc = tile / (nkb * (l + 1));
   const PrimeConst pk = pc[li];
-  const size_t csz = (size_t)2 * (l + 1) * N, comp = (size_t)n2 * (l + 1) * N;
+  const size_t csz = (size_t)2 * (l + 1) * N, comp = (size_t)n2 * pl * N;
   const u64 r0 = in.p[b][(size_t)li * N + k], r1 = in.p[b][(size_t)(l + 1 + li) * N + k];
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
-    const size_t o = ((size_t)(jc * JC + jj) * (l + 1) + li) * N + k;
+    const size_t o = ((size_t)(jc * JC + jj) * pl + li) * N + k;
     const u64 pt = pts[o], ps = pts[comp + o];
     u64* out = s + ((size_t)(jc * JC + jj) * in.n + b) * csz;
     out[(size_t)li * N + k] = mp_final<false>(shoup_lazy4(r0, pt, ps, pk.q), pk);
@@ -478,10 +571,11 @@ __global__ void __launch_bounds__(BS) k_add_plain(Items ct, const u64* __restric
 // comp = floor(w 2^64 / q) by restoring long division of w 2^64 (w < q < 2^61:
 // the running remainder stays below 2q < 2^62).  grid (N/BS, level+1, m).
 __global__ void __launch_bounds__(BS) k_shoup_companion(const u64* __restrict__ pts, u64* __restrict__ comp,
-                                                        const PrimeConst* __restrict__ pc, u32 N, u32 level) {
+                                                        const PrimeConst* __restrict__ pc, u32 N, u32 nlimbs,
+                                                        u32 l, u32 nq) {
   const u32 k = blockIdx.x * BS + threadIdx.x, r = blockIdx.y, i = blockIdx.z;
-  const size_t o = ((size_t)i * (level + 1) + r) * N + k;
-  const u64 q = pc[r].q;
+  const size_t o = ((size_t)i * nlimbs + r) * N + k;
+  const u64 q = pc[r <= l ? r : nq + (r - l - 1)].q;
   u64 rem = pts[o], quo = 0;
   for (int bit = 63; bit >= 0; --bit) {
     rem <<= 1;
@@ -629,17 +723,52 @@ int launch_ks_final(he_ctx* c, u32 l, u32 nitems, const u64* u, const u64* conv,
   return ok();
 }
 
-int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u64* s) {
+int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u32 pl, u64* s) {
   TraceScope ts(c, TK_MULTPLAIN, ((double)in.n * (1 + n2) * 2.0 * (l + 1) + 2.0 * n2 * (l + 1)) * (8.0 * (double)c->N));
   const u32 jc = n2 >= 8 ? 8 : (n2 >= 4 ? 4 : (n2 >= 2 ? 2 : 1));
-  if (n2 % jc) return HE_EINVAL;
+  if (n2 % jc || pl < l + 1) return HE_EINVAL;
   dim3 grid(in.n * (n2 / jc) * (c->N / BS) * (l + 1));
+#define HE_LAUNCH_M1(J) \
+  HE_LAUNCH(ts, (k_multplain<J>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2, pl)
   switch (jc) {
-    case 8: HE_LAUNCH(ts, (k_multplain<8>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
-    case 4: HE_LAUNCH(ts, (k_multplain<4>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
-    case 2: HE_LAUNCH(ts, (k_multplain<2>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
-    default: HE_LAUNCH(ts, (k_multplain<1>), grid, dim3(BS), c->stream, in, pts, s, c->d_pc, c->N, l, n2); break;
+    case 8: HE_LAUNCH_M1(8); break;
+    case 4: HE_LAUNCH_M1(4); break;
+    case 2: HE_LAUNCH_M1(2); break;
+    default: HE_LAUNCH_M1(1); break;
   }
+#undef HE_LAUNCH_M1
+  return ok();
+}
+
+int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const StepKeys& keys,
+                         const Items& in, const u64* pts, u64* sqp) {
+  const u32 jc = n2 >= 8 ? 8 : (n2 >= 4 ? 4 : (n2 >= 2 ? 2 : 1));
+  if (n2 % jc) return HE_EINVAL;
+  const double ne = l + 1 + c->np;
+  // per item: c0 and c1 (plus c0 again, permuted, per baby step), u of every
+  // baby step (2 polys over Q_l u P), the n2 sums written over Q_l u P;
+  // plaintexts (value + companion) once
+  TraceScope ts(c, TK_EXT_MP,
+                ((double)B * (2.0 * (l + 1) + (n1 - 1) * (2.0 * ne + (l + 1)) + 2.0 * n2 * ne) + 2.0 * n1 * n2 * ne) *
+                    (8.0 * (double)c->N));
+  dim3 grid(B * (n2 / jc) * (c->N / BS) * (u32)ne);
+#define HE_LAUNCH_XM(J)                                                                                           \
+  HE_LAUNCH(ts, (k_ext_mp<J>), grid, dim3(BS), c->stream, u, keys, in, pts, sqp, c->d_pc, c->d_moddown, c->N,  \
+            c->log_n, l, c->np, c->nq, n1, n2)
+  switch (jc) {
+    case 8: HE_LAUNCH_XM(8); break;
+    case 4: HE_LAUNCH_XM(4); break;
+    case 2: HE_LAUNCH_XM(2); break;
+    default: HE_LAUNCH_XM(1); break;
+  }
+#undef HE_LAUNCH_XM
+  return ok();
+}
+
+int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, u64* out) {
+  TraceScope ts(c, TK_MODDOWN_FINAL, (double)Z * 6.0 * (l + 1) * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_moddown_final, dim3(c->N / BS, l + 1, Z), dim3(BS), c->stream, y, conv, out, c->d_pc,
+            c->d_moddown, c->N, l, c->np, c->nq);
   return ok();
 }
 
@@ -674,9 +803,10 @@ int launch_add_plain(he_ctx* c, u32 l, const Items& ct, const u64* poly) {
   return ok();
 }
 
-int launch_shoup_companion(he_ctx* c, u32 m, u32 level, const u64* pts, u64* comp) {
-  TraceScope ts(c, TK_SHOUP_COMPANION, 2.0 * m * (level + 1) * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_shoup_companion, dim3(c->N / BS, level + 1, m), dim3(BS), c->stream, pts, comp, c->d_pc, c->N, level);
+int launch_shoup_companion(he_ctx* c, u32 m, u32 nlimbs, u32 l, const u64* pts, u64* comp) {
+  TraceScope ts(c, TK_SHOUP_COMPANION, 2.0 * m * nlimbs * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_shoup_companion, dim3(c->N / BS, nlimbs, m), dim3(BS), c->stream, pts, comp, c->d_pc, c->N, nlimbs,
+            l, c->nq);
   return ok();
 }
 

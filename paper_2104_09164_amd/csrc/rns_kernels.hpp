@@ -87,12 +87,27 @@ int launch_ks_final_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64
 
 // Inner sums with one baby step (n1 = 1), item b, j < n2:
 //   s[j][b] = pts[j] (.) in.p[b]   (both polynomials), s = [n2][B][2][l+1][N];
-// pts in NTT form followed by their Shoup companions (he_dense layout).
-int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u64* s);
+// pts in NTT form followed by their Shoup companions (he_dense layout), pl
+// limbs per diagonal (l+1, or l+1+K for diagonals over Q_l u P: the first
+// l+1 are used).
+int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, u32 pl, u64* s);
 
-// comp[i][r][k] = floor(pts[i][r][k] 2^64 / q_r) for m diagonals of limbs r <= level
-// (the Shoup companions of the plaintext words; exact long division).
-int launch_shoup_companion(he_ctx* c, u32 m, u32 level, const u64* pts, u64* comp);
+// Lazy-ModDown inner sums: with u holding the extended key-switch inner
+// products of baby steps i = 1 .. n1-1 (step s = i - 1) of items b < B,
+//   sqp[j][b] = sum_{i < n1} pts[n1 j + i] (.) r_i(b) over Q_l u P,
+//   r_0 = (P c0, P c1), r_i = (P sigma_i(c0) + u_b, u_a),
+// pts = [m][l+1+K][N] then companions; sqp = [n2][B][2][l+1+K][N], every limb in [0, q).
+int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const StepKeys& keys,
+                         const Items& in, const u64* pts, u64* sqp);
+// ModDown output of Z extended ciphertexts y = [Z][2][l+1+K][N] whose
+// conversions (NTT form) are in conv = [Z][2][l+1][N]: out + z 2 (l+1) N =
+// (y_Q - conv) P^{-1}.
+int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, u64* out);
+
+// comp[i][r][k] = floor(pts[i][r][k] 2^64 / q) for m arrays of nlimbs limbs,
+// limb r over prime r for r <= l, else p_{r-l-1} (the Shoup companions of
+// plaintext and key words; exact long division).
+int launch_shoup_companion(he_ctx* c, u32 m, u32 nlimbs, u32 l, const u64* pts, u64* comp);
 
 // Tensor for squaring: d01 = [B][2][l+1] (c0^2, 2 c0 c1), d2 = [B][l+1] (c1^2).
 int launch_tensor(he_ctx* c, u32 l, const Items& in, u64* d01, u64* d2);

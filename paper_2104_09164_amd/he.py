@@ -68,9 +68,11 @@ def lib() -> C.CDLL:
             "he_key_bytes": (sz, [vp, u32]),
             "he_workspace_bytes": (sz, [vp, u32, u32, u32]),
             "he_dense_bytes": (sz, [vp, u32, u32, C.c_int]),
+            "he_dense_bytes_ex": (sz, [vp, u32, u32, C.c_int, u32]),
             "he_ctx_bind": (C.c_int, [vp, vp, sz, u32, u32, u32]),
             "he_load_keys": (C.c_int, [vp, vp, u32, C.POINTER(i32), C.POINTER(vp), vp, sz]),
             "he_dense_load": (C.c_int, [vp, u32, u32, u32, u32, vp, vp, dbl, dbl, vp, sz, C.POINTER(vp)]),
+            "he_dense_load_ex": (C.c_int, [vp, u32, u32, u32, u32, vp, vp, dbl, dbl, u32, vp, sz, C.POINTER(vp)]),
             "he_dense_free": (C.c_int, [vp]),
             "he_ct_import": (C.c_int, [vp, vp, u32, dbl, ctp]),
             "he_ct_export": (C.c_int, [vp, ctp, vp]),
@@ -105,7 +107,10 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_dense_free", "he_ct_import", "he_ct_export", "he_ct_from_coeff_dev", "he_ct_to_coeff_dev",
             "he_eval_dense", "he_square", "he_rotate", "he_rotate_hoisted", "he_rescale", "he_add",
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
-            "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read")
+            "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
+            "he_dense_load_ex")
+
+HE_DENSE_QP = 1
 
 
 def _check(rc: int, where: str) -> None:
@@ -144,10 +149,10 @@ class Ct:
 
 
 class Dense:
-    def __init__(self, ctx: "Context", handle, buf, level, m, n, n1, pt_scale, bias_scale):
+    def __init__(self, ctx: "Context", handle, buf, level, m, n, n1, pt_scale, bias_scale, qp=False):
         self.ctx, self.h, self.buf = ctx, handle, buf
         self.level, self.m, self.n, self.n1 = level, m, n, n1
-        self.pt_scale, self.bias_scale = pt_scale, bias_scale
+        self.pt_scale, self.bias_scale, self.qp = pt_scale, bias_scale, qp
 
     def __del__(self):
         try:
@@ -224,16 +229,20 @@ class Context:
         self.key_steps = steps
 
     def dense_load(self, level: int, m: int, n: int, n1: int, pts: np.ndarray, bias: np.ndarray | None,
-                   pt_scale: float, bias_scale: float) -> Dense:
+                   pt_scale: float, bias_scale: float, qp: bool = False) -> Dense:
+        """qp: diagonals over q_0..q_level, p_0..p_{K-1} (lazy-ModDown form, HE_DENSE_QP)."""
         pts = np.ascontiguousarray(pts, dtype=np.uint64)
         b = np.ascontiguousarray(bias, dtype=np.uint64) if bias is not None else None
-        nbytes = int(lib().he_dense_bytes(self.h, level, m, b is not None))
+        flags = HE_DENSE_QP if qp else 0
+        if pts.shape != (m, level + 1 + (len(self.p) if qp else 0), self.N):
+            raise ValueError(f"diagonals of shape {pts.shape} for m={m}, level={level}, qp={qp}")
+        nbytes = int(lib().he_dense_bytes_ex(self.h, level, m, b is not None, flags))
         buf = self._alloc(nbytes)
         h = C.c_void_p()
-        _check(lib().he_dense_load(self.h, level, m, n, n1, C.c_void_p(pts.ctypes.data),
-                                   C.c_void_p(b.ctypes.data) if b is not None else None, pt_scale, bias_scale,
-                                   C.c_void_p(buf.data_ptr()), nbytes, C.byref(h)), "he_dense_load")
-        return Dense(self, h, buf, level, m, n, n1, pt_scale, bias_scale)
+        _check(lib().he_dense_load_ex(self.h, level, m, n, n1, C.c_void_p(pts.ctypes.data),
+                                      C.c_void_p(b.ctypes.data) if b is not None else None, pt_scale, bias_scale,
+                                      flags, C.c_void_p(buf.data_ptr()), nbytes, C.byref(h)), "he_dense_load_ex")
+        return Dense(self, h, buf, level, m, n, n1, pt_scale, bias_scale, qp)
 
     # ------------------------------------------------------ import/export
     def import_ct(self, coeff: np.ndarray, level: int, scale: float) -> Ct:

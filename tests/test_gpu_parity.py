@@ -198,6 +198,42 @@ def test_dense_parity(setup10, m, n, n1, bias):
     assert np.array_equal(ctx.export_ct(got), want.data)
 
 
+@pytest.mark.parametrize("m,n,n1,bias", DENSE_CASES)
+def test_dense_qp_parity(setup10, m, n, n1, bias):
+    """Lazy-ModDown form (HE_DENSE_QP): diagonals over Q_l u P, inner sums over
+    Q_l u P, one ModDown per inner sum, against the oracle's orc_dense_qp."""
+    pr, o, keys, ctx = setup10
+    rng = np.random.default_rng(m * 1000 + n * 10 + n1 + 1)
+    W = rng.normal(0, 0.05, (m, n))
+    b = rng.normal(0, 0.05, m) if bias else None
+    x, ct = encrypt(o, keys, pr, 9, width=n)
+    lay = o.prepare_dense(W, b, n1, ct.level, ct.scale, qp=True)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True)
+    g = ctx.import_ct(ct.data, ct.level, ct.scale)
+    got = ctx.eval_dense(g, d)
+    want = o.dense(ct, lay, keys)
+    assert got.scale == want.scale and got.level == want.level
+    assert np.array_equal(ctx.export_ct(got), want.data)
+
+
+def test_dense_qp_lower_level_batched(setup10):
+    """Lazy-ModDown form one level down (the last digit holds one limb),
+    three ciphertexts batched: each equals its single call and the oracle."""
+    pr, o, keys, ctx = setup10
+    m, n, n1 = 8, 64, 8
+    W = np.random.default_rng(29).normal(0, 0.05, (m, n))
+    b = np.random.default_rng(30).normal(0, 0.05, m)
+    cts = [o.rescale(encrypt(o, keys, pr, 50 + i, width=n)[1]) for i in range(3)]
+    lay = o.prepare_dense(W, b, n1, cts[0].level, cts[0].scale, qp=True)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True)
+    gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+    batch = ctx.eval_dense_batch(gs, d)
+    for i, c in enumerate(cts):
+        got = ctx.export_ct(batch[i])
+        assert np.array_equal(got, ctx.export_ct(ctx.eval_dense(gs[i], d)))
+        assert np.array_equal(got, o.dense(c, lay, keys).data)
+
+
 def test_batched_equals_single(setup10):
     pr, o, keys, ctx = setup10
     m, n, n1 = 8, 64, 4
@@ -256,6 +292,12 @@ def test_full_batch_of_64():
     for i in (0, 63):
         want = o.rescale(o.square(o.dense(cts[i], lay, keys), keys))
         assert np.array_equal(ctx.export_ct(out[i]), want.data)
+    # lazy-ModDown form: n2 B = 128 extended inner sums brought down in one set of launches
+    lq = o.prepare_dense(W, b, n1, cts[0].level, cts[0].scale, qp=True)
+    dq = ctx.dense_load(lq.level, m, n, n1, lq.pts, lq.bias, lq.pt_scale, lq.bias_scale, qp=True)
+    outq = ctx.eval_dense_batch(gs, dq)
+    for i in (0, 17, 63):
+        assert np.array_equal(ctx.export_ct(outq[i]), o.dense(cts[i], lq, keys).data), i
 
 
 def test_error_codes(setup10):
