@@ -70,9 +70,11 @@ def setup(plan, batch, seed=7):
     del relin, rot
     layers = []
     for li, lay in enumerate(plan.layers):
-        pts = residues(plan.q[: lay.level + 1], N, (lay.m,), seed + 100 + li)
+        # lazy-ModDown layers hold their diagonals over Q_l u P
+        pts = residues(plan.q[: lay.level + 1] + (plan.p if lay.qp else []), N, (lay.m,), seed + 100 + li)
         bias = residues(plan.q[: lay.level + 1], N, (), seed + 200 + li)
-        layers.append(ctx.dense_load(lay.level, lay.m, lay.n, lay.n1, pts, bias, lay.pt_scale, lay.bias_scale))
+        layers.append(ctx.dense_load(lay.level, lay.m, lay.n, lay.n1, pts, bias, lay.pt_scale, lay.bias_scale,
+                                     qp=lay.qp))
     runner = NetworkRunner(ctx, plan, layers, batch)
     for b in range(batch):
         x = residues(plan.q, N, (2,), seed + 1000 + b)
@@ -320,12 +322,10 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     import torch
     from paper_2104_09164_amd import netplan, tune
     tuned = tune.load(name) if use_tuning else None
-    shapes = None
-    if tuned and tuned.get("n1") and tuned_n1:
-        shapes = [(m, n, n1) for (m, n, _), n1 in zip(netplan.PRESETS[name]["shapes"], tuned["n1"])]
-    plan = netplan.preset_plan(name, shapes)
+    plan = netplan.preset_plan(name, netplan.tuned_shapes(name, tuned, tuned_n1))
     log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}, "
-        f"n1={[l.n1 for l in plan.layers]}, knobs={tuned.get('knobs') if tuned else None}")
+        f"n1={[l.n1 for l in plan.layers]}, lazy ModDown={[l.qp for l in plan.layers]}, "
+        f"knobs={tuned.get('knobs') if tuned else None}")
     ctx, runner = setup(plan, batch)
     tune.apply_knobs(ctx, tuned)
     torch.cuda.synchronize()
@@ -363,9 +363,11 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
            "plain_eager_p50_ms": float(np.percentile(lat_eager, 50)),
            "workload": (f"{name}: N=2^{plan.log_n}, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
                         f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
-                        + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers) + ", x^2 between"),
+                        + ", ".join(f"{l.n}->{l.m} (n1={l.n1}{', lazy ModDown' if l.qp else ''})"
+                                    for l in plan.layers) + ", x^2 between"),
            "ops_per_inference": plan.op_counts(),
-           "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1") if tuned_n1 else None} if tuned else None}
+           "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1") if tuned_n1 else None,
+                      "lazy_moddown": [l.qp for l in plan.layers]} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
     if trace:
         log(f"{name}: traced eager pass")
@@ -459,7 +461,7 @@ def main():
         from paper_2104_09164_amd import netplan, tune
         calibration_copy()
         tuned = tune.load("cfg3")
-        plan = netplan.preset_plan("cfg3")
+        plan = netplan.preset_plan("cfg3", netplan.tuned_shapes("cfg3", tuned, tuned_n1=False))
         ctx, runner = setup(plan, args.batch)
         tune.apply_knobs(ctx, tuned)
         tab = trace_steps(ctx, runner, args.batch, args.steps)

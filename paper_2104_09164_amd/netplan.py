@@ -9,7 +9,9 @@ dense -> rescale -> square -> rescale -> ... -> dense -> rescale.
 This module only does bookkeeping: levels, scales (IEEE doubles updated by
 *Delta_w, by squaring and by /q_l, in that order), the rotation steps each
 layer needs (baby steps 1..n1-1, giant steps n1*j, rotate-and-sum n/2..m),
-and the per-inference operation counts.
+and the per-inference operation counts.  A layer with qp set runs in the
+lazy-ModDown form (diagonals over Q_l u P, one ModDown per inner sum instead of
+one per baby step); like n1 it changes the rounding, so it is part of the plan.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ class LayerPlan:
     level: int            # level the layer is evaluated at
     in_scale: float
     pt_scale: float
+    qp: bool = False      # lazy-ModDown form (HE_DENSE_QP)
 
     @property
     def n2(self) -> int:
@@ -47,6 +50,12 @@ class LayerPlan:
             c += 1
             t //= 2
         return c
+
+    def moddowns(self) -> int:
+        """ModDowns of one evaluation: one per baby step, or one per inner sum
+        in the lazy form, plus one per giant step and rotate-and-sum step."""
+        return ((self.n2 if self.qp else 0) if self.n1 > 1 else 0) + (0 if self.qp else self.n1 - 1) \
+            + (self.n2 - 1) + self.rs_count()
 
 
 @dataclass
@@ -88,15 +97,18 @@ class NetPlan:
         ks = sum((l.n1 - 1) + (l.n2 - 1) + l.rs_count() for l in self.layers) + (len(self.layers) - 1)
         return {"key_switches": ks, "multplain": sum(l.m for l in self.layers),
                 "rescales": 2 * len(self.layers) - 1, "squares": len(self.layers) - 1,
-                "hoisted_modups": sum(1 for l in self.layers if l.n1 > 1)}
+                "hoisted_modups": sum(1 for l in self.layers if l.n1 > 1),
+                "moddowns": sum(l.moddowns() for l in self.layers) + (len(self.layers) - 1),
+                "lazy_moddown_layers": [li for li, l in enumerate(self.layers) if l.qp]}
 
 
 def plan_network(log_n: int, q, p, alpha: int, scale_bits: int, shapes) -> NetPlan:
-    """shapes: [(m, n, n1), ...] from the first layer to the last."""
+    """shapes: [(m, n, n1) or (m, n, n1, qp), ...] from the first layer to the last."""
     pl = NetPlan(log_n, list(q), list(p), alpha, float(2 ** scale_bits))
     level, s = pl.L, pl.scale
-    for li, (m, n, n1) in enumerate(shapes):
-        lay = LayerPlan(m, n, n1, level, s, pl.scale)
+    for li, shp in enumerate(shapes):
+        m, n, n1 = shp[:3]
+        lay = LayerPlan(m, n, n1, level, s, pl.scale, bool(shp[3]) if len(shp) > 3 else False)
         pl.layers.append(lay)
         s = s * lay.pt_scale
         s = s / pl.q[level]
@@ -120,6 +132,20 @@ PRESETS = {
     "cfg4": dict(log_n=16, q_bits=[60] + [45] * 10, p_bits=[60] * 3, alpha=3, scale_bits=45,
                  shapes=[(256, 4096, 16), (64, 256, 8), (2, 64, 2)], sigma=0.02),
 }
+
+
+def tuned_shapes(name: str, tuned: dict | None, tuned_n1: bool = True) -> list:
+    """Layer shapes of a preset with the autotuner's plan choices: its n1 and
+    lazy-ModDown flags (tuned_n1), or the preset's n1 with the flags the
+    tuner found best for it."""
+    shapes = [tuple(s) for s in PRESETS[name]["shapes"]]
+    if not tuned:
+        return shapes
+    if tuned_n1 and tuned.get("n1"):
+        qp = tuned.get("qp") or [False] * len(shapes)
+        return [(m, n, n1, bool(f)) for (m, n, _), n1, f in zip(shapes, tuned["n1"], qp)]
+    qp = tuned.get("qp_preset") or [False] * len(shapes)
+    return [(m, n, n1, bool(f)) for (m, n, n1), f in zip(shapes, qp)]
 
 
 def preset_plan(name: str, shapes=None) -> NetPlan:

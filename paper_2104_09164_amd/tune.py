@@ -8,9 +8,11 @@ Two kinds of choices:
 * Plan choices that the oracle replays: the baby-step count n1 of each dense
   layer (the paper notes that the baby-step/giant-step trade-off depends on
   the ciphertext counts; Methods, "Algorithmic and cryptographic
-  optimizations") changes which key switches run and hence the output bits,
-  so it is recorded in the plan; and the batch size (requests per launch),
-  chosen for throughput under a latency cap.
+  optimizations") and whether the layer runs in the lazy-ModDown form (one
+  ModDown per inner sum instead of one per baby step) change which key
+  switches run or where they round, hence the output bits, so both are
+  recorded in the plan; and the batch size (requests per launch), chosen for
+  throughput under a latency cap.
 
 Every measurement times the real batched entry points on the device with
 HIP events, on synthetic residues of the workload's shape.
@@ -23,6 +25,7 @@ import argparse
 import itertools
 import json
 import os
+import sys
 
 import numpy as np
 
@@ -30,6 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
 KNOB_SPACE = {"ntt_cols": [16, 32], "ntt_cols_b": [8, 16, 32], "ntt_chunk_mb": [0, 64, 128, 256]}
+# The lazy-ModDown form is chosen only when it is at least this much faster.
+LAZY_MARGIN = 1.02
 
 
 def n1_candidates(m: int, max_n1: int = 64) -> list[int]:
@@ -120,6 +125,7 @@ def tune_ntt(ctx, items: int, reps: int = 5) -> tuple[dict, dict]:
         for k, v in knobs.items():
             ctx.set_knob(k, v)
         table[json.dumps(knobs, sort_keys=True)] = _time(run, reps)
+        print(f"[tune] ntt {knobs}: {table[json.dumps(knobs, sort_keys=True)]:.3f} ms", file=sys.stderr, flush=True)
     best = json.loads(pick_min(table))
     for k, v in best.items():
         ctx.set_knob(k, v)
@@ -145,24 +151,39 @@ def build_context(plan, batch: int, n1_sets: list[list[int]], seed: int = 7):
     return ctx
 
 
-def tune_n1(ctx, plan, batch: int, n1_sets: list[list[int]], reps: int = 3) -> tuple[list[int], list[dict]]:
-    """Per layer: time he_eval_dense_batch at every candidate n1."""
+def tune_n1(ctx, plan, batch: int, n1_sets: list[list[int]], reps: int = 3, preset_n1=None):
+    """Per layer: time he_eval_dense_batch at every candidate (n1, lazy
+    ModDown).  Returns the best n1 and flag per layer, the best flag at the
+    preset's n1 (when it is a candidate) and the timing tables."""
     N = 1 << plan.log_n
-    best, tables = [], []
+    best_n1, best_qp, preset_qp, tables = [], [], [], []
     for li, (lay, cands) in enumerate(zip(plan.layers, n1_sets)):
         cts = [ctx.import_ct(_residues(plan.q[: lay.level + 1], N, (2,), 900 + b), lay.level, lay.in_scale)
                for b in range(batch)]
         outs = [ctx.new_ct(lay.level) for _ in range(batch)]
-        pts = _residues(plan.q[: lay.level + 1], N, (lay.m,), 300 + li)
         bias = _residues(plan.q[: lay.level + 1], N, (), 400 + li)
         table = {}
-        for n1 in cands:
-            d = ctx.dense_load(lay.level, lay.m, lay.n, n1, pts, bias, lay.pt_scale, lay.bias_scale)
-            table[n1] = _time(lambda: ctx.eval_dense_batch(cts, d, outs), reps, 1)
-            del d
+        for qp in (False, True):
+            primes = plan.q[: lay.level + 1] + (plan.p if qp else [])
+            pts = _residues(primes, N, (lay.m,), 300 + li)
+            for n1 in cands:
+                if qp and n1 == 1:
+                    continue                    # same launches as the plain form
+                d = ctx.dense_load(lay.level, lay.m, lay.n, n1, pts, bias, lay.pt_scale, lay.bias_scale, qp=qp)
+                table[(n1, qp)] = _time(lambda: ctx.eval_dense_batch(cts, d, outs), reps, 1)
+                print(f"[tune] layer {li}: n1={n1} lazy_moddown={qp}: {table[(n1, qp)]:.3f} ms", file=sys.stderr,
+                      flush=True)
+                del d
         tables.append(table)
-        best.append(pick_min(table))
-    return best, tables
+        n1, qp = pick_min(table)
+        if qp and (n1, False) in table and table[(n1, False)] <= LAZY_MARGIN * table[(n1, True)]:
+            qp = False                          # keep the ordinary form unless the lazy one clearly wins
+        best_n1.append(n1)
+        best_qp.append(qp)
+        p = preset_n1[li] if preset_n1 else None
+        preset_qp.append(p in {c for c, _ in table} and (p, True) in table
+                         and table[(p, True)] * LAZY_MARGIN < table[(p, False)])
+    return best_n1, best_qp, preset_qp, tables
 
 
 def tune_batch(ctx, plan, layers, batches: list[int], cap_ms: float | None, reps: int = 3):
@@ -177,6 +198,7 @@ def tune_batch(ctx, plan, layers, batches: list[int], cap_ms: float | None, reps
         g = runner.capture(b)
         ms = _time(g.replay, reps, 1)
         rates[b], lat[b] = 1000.0 * b / ms, ms
+        print(f"[tune] batch {b}: {rates[b]:.1f} inferences/s", file=sys.stderr, flush=True)
     return pick_batch(rates, lat, cap_ms), rates, lat
 
 
@@ -184,21 +206,25 @@ def tune_workload(name: str, batch: int, cap_ms: float | None = None, out_dir: s
                   batches=(1, 4, 8, 16, 32)) -> dict:
     from . import netplan
     plan = netplan.preset_plan(name)
-    # n1 <= 32 and n2 = m / n1 <= 32 bound the baby and inner-sum workspaces
-    n1_sets = [[n for n in n1_candidates(lay.m, 32) if lay.m // n <= 32] for lay in plan.layers]
+    # n1 <= 64 and n2 = m / n1 <= 32 bound the baby and inner-sum workspaces
+    n1_sets = [[n for n in n1_candidates(lay.m, 64) if lay.m // n <= 32] for lay in plan.layers]
     ctx = build_context(plan, max(max(batches), batch), n1_sets)
     knobs, ntt_table = tune_ntt(ctx, items=min(batch, 64))
-    n1s, n1_tables = tune_n1(ctx, plan, batch, n1_sets)
-    shapes = [(l.m, l.n, n1) for l, n1 in zip(plan.layers, n1s)]
+    n1s, qps, qp_preset, n1_tables = tune_n1(ctx, plan, batch, n1_sets,
+                                             preset_n1=[l.n1 for l in plan.layers])
+    shapes = [(l.m, l.n, n1, qp) for l, n1, qp in zip(plan.layers, n1s, qps)]
     plan2 = netplan.plan_network(plan.log_n, plan.q, plan.p, plan.alpha, int(np.log2(plan.scale)), shapes)
     N = 1 << plan.log_n
-    layers = [ctx.dense_load(l.level, l.m, l.n, l.n1, _residues(plan.q[: l.level + 1], N, (l.m,), 300 + i),
-                             _residues(plan.q[: l.level + 1], N, (), 400 + i), l.pt_scale, l.bias_scale)
+    layers = [ctx.dense_load(l.level, l.m, l.n, l.n1,
+                             _residues(plan.q[: l.level + 1] + (plan.p if l.qp else []), N, (l.m,), 300 + i),
+                             _residues(plan.q[: l.level + 1], N, (), 400 + i), l.pt_scale, l.bias_scale, qp=l.qp)
               for i, l in enumerate(plan2.layers)]
     bbest, rates, lat = tune_batch(ctx, plan2, layers, list(batches), cap_ms)
-    res = {"device": device_tag(), "workload": name, "knobs": knobs, "n1": n1s, "batch": bbest,
-           "latency_cap_ms": cap_ms,
-           "measurements": {"ntt_ms": ntt_table, "dense_ms": [{str(k): v for k, v in t.items()} for t in n1_tables],
+    res = {"device": device_tag(), "workload": name, "knobs": knobs, "n1": n1s, "qp": qps, "qp_preset": qp_preset,
+           "batch": bbest, "latency_cap_ms": cap_ms,
+           "measurements": {"ntt_ms": ntt_table,
+                            "dense_ms": [{f"{k[0]}{'q' if k[1] else ''}": v for k, v in t.items()}
+                                         for t in n1_tables],
                             "batch_inferences_per_s": {str(k): v for k, v in rates.items()},
                             "batch_latency_ms": {str(k): v for k, v in lat.items()}}}
     os.makedirs(out_dir, exist_ok=True)
@@ -215,7 +241,8 @@ def main():
     ap.add_argument("--out", default=TUNING_DIR)
     args = ap.parse_args()
     res = tune_workload(args.workload, args.batch, args.cap_ms, args.out)
-    print(json.dumps({k: res[k] for k in ("device", "workload", "knobs", "n1", "batch")}), flush=True)
+    print(json.dumps({k: res[k] for k in ("device", "workload", "knobs", "n1", "qp", "qp_preset", "batch")}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -27,21 +27,21 @@ def run_network(name, requests, check_bits, tuned_split=True):
     from paper_2104_09164_amd.batch import NetworkRunner
     c = netplan.PRESETS[name]
     tuned = tune.load(name, "gfx950")
-    n1s = tuned["n1"] if tuned and tuned_split else [s[2] for s in c["shapes"]]
-    shapes = [(m, n, n1) for (m, n, _), n1 in zip(c["shapes"], n1s)]
+    shapes = netplan.tuned_shapes(name, tuned, tuned_split)     # (m, n, n1, lazy ModDown)
     pr = params.preset(name)
     o = ckks.Oracle(pr)
-    print(f"[fullsize] {name}: keygen for {len(ckks.network_steps(shapes))} rotation keys", flush=True)
-    keys = o.keygen(synth.SEED_KEYS, ckks.network_steps(shapes))
-    Ws, bs = synth.network_weights(shapes, c["sigma"])
-    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes])
+    steps = ckks.network_steps([s[:3] for s in shapes])
+    print(f"[fullsize] {name}: keygen for {len(steps)} rotation keys, plan {shapes}", flush=True)
+    keys = o.keygen(synth.SEED_KEYS, steps)
+    Ws, bs = synth.network_weights([s[:3] for s in shapes], c["sigma"])
+    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes], qps=[len(s) > 3 and s[3] for s in shapes])
     npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, c["scale_bits"], shapes)
     ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
     tune.apply_knobs(ctx, tuned)
     B = len(requests)
     ctx.bind(B, npl.max_n1(), npl.max_n2())
     ctx.load_keys(keys.rlk, keys.rot)
-    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale) for l in lays]
+    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale, qp=l.qp) for l in lays]
     runner = NetworkRunner(ctx, npl, dls, B)
     cts, xs = [], []
     for i, r in enumerate(requests):

@@ -234,6 +234,23 @@ def test_dense_qp_lower_level_batched(setup10):
         assert np.array_equal(got, o.dense(c, lay, keys).data)
 
 
+@pytest.mark.parametrize("qp", [False, True])
+def test_dense_64_baby_steps(qp):
+    """The widest baby-step count the workspace takes (n1 = 64: 63 rotations
+    in one step-batched key switch), both forms, two ciphertexts batched."""
+    pr = small(10)
+    m = n = n1 = 64
+    o, keys, ctx = make_setup(pr, plan.rotation_steps(m, n, n1), max_batch=2, max_n1=n1, max_n2=1, relin=False)
+    W = np.random.default_rng(31).normal(0, 0.05, (m, n))
+    b = np.random.default_rng(32).normal(0, 0.05, m)
+    cts = [encrypt(o, keys, pr, 60 + i, width=n)[1] for i in range(2)]
+    lay = o.prepare_dense(W, b, n1, cts[0].level, cts[0].scale, qp=qp)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=qp)
+    out = ctx.eval_dense_batch([ctx.import_ct(c.data, c.level, c.scale) for c in cts], d)
+    for i, c in enumerate(cts):
+        assert np.array_equal(ctx.export_ct(out[i]), o.dense(c, lay, keys).data), i
+
+
 def test_batched_equals_single(setup10):
     pr, o, keys, ctx = setup10
     m, n, n1 = 8, 64, 4
