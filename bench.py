@@ -259,6 +259,9 @@ KERNEL_LABEL = {
     "ks_final_steps": "key-switch epilogue, all hoisted steps of a batch in one launch",
     "multplain": "MultPlain inner sums (one baby step)",
     "ks_final_multplain": "baby-step key-switch epilogue folded into the MultPlain inner sums",
+    "ks_inner_ext_multplain": "lazy-ModDown baby steps: key inner products of every baby step fused into the "
+                              "plaintext inner sums over Q u P (automorphism gathered), one launch per layer",
+    "ext_multplain": "lazy-ModDown inner sums over Q u P from stored key-switch products",
 }
 
 
@@ -296,16 +299,61 @@ def traffic_record(kernel, launches_per_step):
     return None
 
 
-def step_roofline(tab, steps):
+# Integer VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one 32-bit lane
+# operation per lane per clock; v_mad_u64_u32 and v_mul_lo/hi_u32 issue at that
+# rate on gfx950).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Minimal VALU lane operations per modular product in the gfx950 code of this
+# library (instruction sequences read from its own disassembly): a key product
+# folded into a running sum (add_shoup4: 2 v_mul_hi_u32, 3 v_mad_u64_u32,
+# 4 v_mul_lo_u32, 2 v_add3_u32) 11; a plaintext product and its 64-bit
+# accumulation (shoup_lazy4 + add) 14; the lift of c0 by P (Shoup product) 8.
+OPS_KEY, OPS_PT, OPS_LIFT = 11, 14, 8
+# Kernel classes bound by VALU issue rather than HBM (rocprofv3 SQ counters:
+# VALU instructions issued in about two thirds of the kernel's cycles, HBM
+# traffic a fraction of the copy rate): their roofline is the integer VALU peak.
+ALU_CLASSES = ("ks_inner_ext_multplain",)
+
+
+def fused_ops(plan, batch) -> int:
+    """Algorithmic VALU lane operations of the fused lazy-ModDown baby-step
+    kernels of one inference step: per item, baby step and coefficient, 2 beta
+    key products and 2 n2 plaintext products on every limb of Q_l u P plus the
+    lift of c0 on the Q-limbs; the unrotated term adds 2 lifts and 2 n2
+    plaintext products per Q-limb."""
+    N, K = 1 << plan.log_n, len(plan.p)
+    total = 0
+    for lay in plan.layers:
+        if not (lay.qp and lay.n1 > 1 and lay.n2 <= 8):
+            continue
+        l1 = lay.level + 1
+        ne, beta = l1 + K, -(-l1 // plan.alpha)
+        per_step = ne * (2 * beta * OPS_KEY + 2 * lay.n2 * OPS_PT) + l1 * OPS_LIFT
+        total += batch * N * ((lay.n1 - 1) * per_step + l1 * (2 * OPS_LIFT + 2 * lay.n2 * OPS_PT))
+    return total
+
+
+def step_roofline(tab, steps, alu_ops_per_step=0):
     """Roofline of the dominant kernel class of one step (largest summed time):
-    achieved = its algorithmic bytes per launch / its mean launch duration."""
+    achieved = its algorithmic bytes per launch / its mean launch duration
+    (HBM), or, for a VALU-bound class, its algorithmic VALU lane operations
+    (fused_ops) / its duration."""
     kern = max(tab, key=lambda k: tab[k][1])
     n, ms, by = tab[kern]
-    achieved = by / (ms * 1e-3) / 1e9
+    gbs = by / (ms * 1e-3) / 1e9
     per_step = n // steps
     total_ms = sum(v[1] for v in tab.values())
-    return {"bound": "hbm", "kernel": KERNEL_LABEL.get(kern, kern), "kernel_class": kern,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+    if kern in ALU_CLASSES and alu_ops_per_step:
+        ops = alu_ops_per_step * steps
+        achieved = ops / (ms * 1e-3) / 1e12
+        head = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "TOP/s (32-bit integer VALU lane ops)", "frac": achieved / VALU_PEAK_TOPS,
+                "alg_ops_per_launch": ops / n,
+                "ops_per_product": {"key": OPS_KEY, "plaintext": OPS_PT, "lift": OPS_LIFT},
+                "hbm_view": {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}}
+    else:
+        head = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    return {**head, "kernel": KERNEL_LABEL.get(kern, kern), "kernel_class": kern,
             "traffic": traffic_record(kern, per_step), "alg_bytes_per_launch": by / n,
             "us_per_launch": ms * 1e3 / n, "launches_per_step": per_step,
             "share_of_kernel_time": ms / total_ms,
@@ -465,7 +513,7 @@ def main():
         ctx, runner = setup(plan, args.batch)
         tune.apply_knobs(ctx, tuned)
         tab = trace_steps(ctx, runner, args.batch, args.steps)
-        print(json.dumps({"roofline": step_roofline(tab, args.steps)}), flush=True)
+        print(json.dumps({"roofline": step_roofline(tab, args.steps, fused_ops(plan, args.batch))}), flush=True)
         return 0
     # headline: the preset's BSGS split (32 baby steps in the first layer), tuned execution knobs
     plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
@@ -481,7 +529,7 @@ def main():
                       "tuning": small["tuning"]},
            "latency_ms": {"batched_p50": small["batched_p50_ms"], "batched_p99": small["batched_p99_ms"],
                           "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
-           "roofline": step_roofline(small.pop("trace"), args.steps),
+           "roofline": step_roofline(small.pop("trace"), args.steps, fused_ops(plan3, args.batch)),
            "plain_inferences_per_s": small["plain_inferences_per_s"],
            "batched_over_plain": small["batched_over_plain"]}
     nets = {"small": (plan3, ctx3, args.batch)}
@@ -498,7 +546,7 @@ def main():
                                                 max(3, args.plain // 2), graph=not args.no_graph,
                                                 use_tuning=not args.no_tuning)
         runner_layers["large"] = run4.layers
-        large["roofline"] = step_roofline(large.pop("trace"), large_steps)
+        large["roofline"] = step_roofline(large.pop("trace"), large_steps, fused_ops(plan4, args.large_batch))
         out["large_net"] = large
         nets["large"] = (plan4, ctx4, args.large_batch)
     if not args.no_serve and not args.no_large:

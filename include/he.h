@@ -242,6 +242,9 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   0 (default) = as "ntt_cols"
  *   "ntt_single_pass"  N = 2^15: 1 = one register-resident launch per
  *                   transform (one HBM pass), 0 (default) = two phases
+ *   "ks_fuse"       lazy-ModDown dense layers with n2 <= 8: 1 (default) = the
+ *                   baby steps' key inner products computed inside the
+ *                   inner-sum kernel (never stored), 0 = two launches
  *   "trace"         1 = bracket every kernel launch with HIP events on the
  *                   context stream (not while the stream is being captured
  *                   into a graph); read with he_trace_read.  0 = off.

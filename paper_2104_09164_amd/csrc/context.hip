@@ -213,7 +213,7 @@ thread_local char g_last_error[256] = "";
 static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
     "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner_steps", "moddown_conv", "ks_final", "ks_final_steps",
-    "ks_final_multplain", "ks_final_sum", "ext_multplain", "moddown_final", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
+    "ks_final_multplain", "ks_final_sum", "ext_multplain", "ks_inner_ext_multplain", "moddown_final", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
     "add_plain", "copy_polys", "shoup_companion"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
@@ -525,6 +525,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ntt_single_pass = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse")) {
+    if (value > 1) return HE_EINVAL;
+    c->ks_fuse = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "trace")) {
     if (value > 1) return HE_EINVAL;
     return trace_enable(c, value == 1);
@@ -562,6 +567,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ntt_cols")) { *value = c->ntt_cols; return HE_OK; }
   if (!std::strcmp(key, "ntt_cols_b")) { *value = c->ntt_cols_b; return HE_OK; }
   if (!std::strcmp(key, "ntt_single_pass")) { *value = c->ntt_single_pass; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse")) { *value = c->ks_fuse; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

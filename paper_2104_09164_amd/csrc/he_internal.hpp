@@ -49,7 +49,7 @@ struct PolyBatch {
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
   TK_MODUP_CONV, TK_KS_INNER_STEPS, TK_MODDOWN_CONV, TK_KS_FINAL, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM,
-  TK_EXT_MP, TK_MODDOWN_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
+  TK_EXT_MP, TK_KS_EXT_FUSED, TK_MODDOWN_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
   TK_COUNT
 };
 const char* trace_name(int kind);
@@ -100,7 +100,8 @@ struct he_ctx {
   int64_t ntt_chunk_mb = 0;
   int64_t ntt_cols = 16;      // sub-transforms per NTT workgroup tile: 8, 16 or 32
   int64_t ntt_cols_b = 0;     // the same for the row phase (0 = ntt_cols)
-  int64_t ntt_single_pass = 0;  // N = 2^15: register-resident single-pass transform (off: VALU-bound either way)
+  int64_t ntt_single_pass = 0;
+  int64_t ks_fuse = 1;          // lazy-ModDown baby steps: inner product fused into the inner sums  // N = 2^15: register-resident single-pass transform (off: VALU-bound either way)
 
   Tracer tr;
 

@@ -30,14 +30,15 @@ size_t ws_words(const he_ctx* c, u32 B, u32 n1, u32 n2, WS* w) {
   WS dummy;
   WS& x = w ? *w : dummy;
   // coef and ext hold the ModUp of every giant step (GJ steps of B items);
-  // u and conv every step of one step-batched key switch.  ext also holds the
-  // n2 B lazy-ModDown inner sums over Q u P (the digits are dead by then), and
-  // conv their conversions.
+  // u and conv every step of one step-batched key switch.  The n2 B
+  // lazy-ModDown inner sums over Q u P go to ext (the digits are dead by then)
+  // or, from the fused kernel that still reads the digits, to u; conv holds
+  // their conversions.
   const size_t GJ = giant_group(n2), G = std::max<size_t>(ks_group(n1), GJ), J2 = n2 ? n2 : 1;
   take(&x.rtmp, B * csz);
   take(&x.coef, GJ * B * L1 * N);
   take(&x.ext, std::max(GJ * c->dnum, 2 * J2) * B * E * N);
-  take(&x.u, G * B * 2 * E * N);
+  take(&x.u, std::max(G, J2) * B * 2 * E * N);
   take(&x.conv, std::max(G, J2) * B * csz);
   take(&x.d01, B * csz);
   take(&x.d2, B * L1 * N);
@@ -484,9 +485,17 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       // lazy ModDown: the inner products stay over Q_l u P; the inner sums
       // are formed there (the extended rotations only in registers) into
       // the dead digit region, then each sum is brought down once
-      if ((rc = launch_ks_inner_steps(c, l, n, S, w.ext, 0, own_of(n, c1in), sk, w.u))) return rc;
-      if ((rc = launch_ext_multplain(c, l, n, n1, n2, w.u, sk, inI, d->pts, w.ext))) return rc;
-      if ((rc = moddown_items(c, l, n2 * n, w.ext, w.conv, w.giant))) return rc;
+      // (fused: the inner products stay in registers; the sums go to w.u,
+      // free in this form, since the digits in w.ext are read throughout)
+      u64* sqp = w.ext;
+      if (c->ks_fuse && n2 <= 8) {
+        sqp = w.u;
+        if ((rc = launch_ks_ext_fused(c, l, n, n1, n2, w.ext, own_of(n, c1in), sk, inI, d->pts, sqp))) return rc;
+      } else {
+        if ((rc = launch_ks_inner_steps(c, l, n, S, w.ext, 0, own_of(n, c1in), sk, w.u))) return rc;
+        if ((rc = launch_ext_multplain(c, l, n, n1, n2, w.u, sk, inI, d->pts, w.ext))) return rc;
+      }
+      if ((rc = moddown_items(c, l, n2 * n, sqp, w.conv, w.giant))) return rc;
     } else {
       if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
       if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;

@@ -99,6 +99,12 @@ int launch_multplain(he_ctx* c, u32 l, u32 n2, const Items& in, const u64* pts, 
 // pts = [m][l+1+K][N] then companions; sqp = [n2][B][2][l+1+K][N], every limb in [0, q).
 int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, const StepKeys& keys,
                          const Items& in, const u64* pts, u64* sqp);
+// The same inner sums fused with the baby steps' key inner products (digits
+// of item b in ext as for launch_ks_inner_steps with ext_items = 0, own limbs
+// from own.ptr[b]): one launch, no per-step products in memory.  n1 >= 2,
+// n2 in {1, 2, 4, 8}, keys = the n1 - 1 baby steps.
+int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
+                        const StepKeys& keys, const Items& in, const u64* pts, u64* sqp);
 // ModDown output of Z extended ciphertexts y = [Z][2][l+1+K][N] whose
 // conversions (NTT form) are in conv = [Z][2][l+1][N]: out + z 2 (l+1) N =
 // (y_Q - conv) P^{-1}.

@@ -216,10 +216,14 @@ def test_dense_qp_parity(setup10, m, n, n1, bias):
     assert np.array_equal(ctx.export_ct(got), want.data)
 
 
-def test_dense_qp_lower_level_batched(setup10):
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_dense_qp_lower_level_batched(setup10, fuse):
     """Lazy-ModDown form one level down (the last digit holds one limb),
-    three ciphertexts batched: each equals its single call and the oracle."""
+    three ciphertexts batched: each equals its single call and the oracle;
+    with the baby steps' inner product fused into the inner sums (knob
+    ks_fuse = 1, the default) and as two launches (0)."""
     pr, o, keys, ctx = setup10
+    ctx.set_knob("ks_fuse", fuse)
     m, n, n1 = 8, 64, 8
     W = np.random.default_rng(29).normal(0, 0.05, (m, n))
     b = np.random.default_rng(30).normal(0, 0.05, m)
@@ -232,6 +236,7 @@ def test_dense_qp_lower_level_batched(setup10):
         got = ctx.export_ct(batch[i])
         assert np.array_equal(got, ctx.export_ct(ctx.eval_dense(gs[i], d)))
         assert np.array_equal(got, o.dense(c, lay, keys).data)
+    ctx.set_knob("ks_fuse", 1)
 
 
 @pytest.mark.parametrize("qp", [False, True])

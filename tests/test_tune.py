@@ -58,7 +58,7 @@ def test_knobs_preserve_bits():
 
 def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
-    assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass"}
+    assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse"}
     assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
     assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
     assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
@@ -69,10 +69,11 @@ def test_knob_api_validation():
     from paper_2104_09164_amd import he
     q, p = he.prime_chain(12, [50, 40], [50])
     ctx = he.Context(12, q, p, 1)
-    defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "trace": 0}
+    defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1, "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
-    for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("trace", 3), ("ntt_chunk_mb", -1),
+    for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
+                   ("ntt_chunk_mb", -1),
                    ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
             ctx.set_knob(k, bad)
