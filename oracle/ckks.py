@@ -82,6 +82,9 @@ def lib():
         L.orc_rotate.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int64, U64P, U64P]
         L.orc_square.argtypes = [C.c_void_p, U64P, C.c_int, U64P, U64P]
         L.orc_rotate_ext.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int64, U64P, U64P]
+        L.orc_dense_ex.restype = C.c_int
+        L.orc_dense_ex.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int, C.c_int, C.c_int, U64P, U64P,
+                                   C.c_int, I64P, C.POINTER(U64P), C.c_int, C.c_int, U64P]
         for f in (L.orc_dense, L.orc_dense_qp):
             f.restype = C.c_int
             f.argtypes = [C.c_void_p, U64P, C.c_int, C.c_int, C.c_int, C.c_int, U64P, U64P,
@@ -293,16 +296,15 @@ class Oracle:
         key_ptrs = (U64P * max(1, len(steps)))(*[_p(keys.rot[s]) for s in steps])
         out = np.empty_like(a.data)
         bias = _p(layer.bias) if layer.bias is not None else None
-        fn = self.L.orc_dense_qp if layer.qp else self.L.orc_dense
-        rc = fn(self._h, _p(a.data), a.level, layer.m, layer.n, layer.n1, _p(layer.pts), bias,
-                len(steps), _p(step_arr, I64P), key_ptrs, _p(out))
+        rc = self.L.orc_dense_ex(self._h, _p(a.data), a.level, layer.m, layer.n, layer.n1, _p(layer.pts), bias,
+                                 len(steps), _p(step_arr, I64P), key_ptrs, int(layer.qp), int(layer.rs_bits), _p(out))
         if rc != 0:
             raise RuntimeError(f"orc_dense failed ({rc})")
         return Ciphertext(out, a.level, a.scale * layer.pt_scale)
 
     # ----------------------------------------------------------- network
     def prepare_dense(self, W: np.ndarray, b: np.ndarray | None, n1: int, level: int, in_scale: float,
-                      pt_scale: float | None = None, qp: bool = False) -> "DenseLayer":
+                      pt_scale: float | None = None, qp: bool = False, rs_bits: int = 0) -> "DenseLayer":
         """Encode the pre-rotated diagonals (scale Delta_w, limbs q_0..q_l only:
         level-aware encoding; with qp, also p_0..p_{K-1} for the lazy-ModDown
         form) and the bias (scale in_scale * Delta_w, period m, limbs q_0..q_l)."""
@@ -315,16 +317,17 @@ class Oracle:
         bias = None
         if b is not None:
             bias = self.encode(planmod.bias_slots(b, pr.slots), in_scale * pt_scale, level)
-        return DenseLayer(m, n, n1, level, pts, bias, pt_scale, in_scale * pt_scale, qp)
+        return DenseLayer(m, n, n1, level, pts, bias, pt_scale, in_scale * pt_scale, qp, rs_bits)
 
-    def prepare_network(self, weights, biases, n1s, level=None, in_scale=None, qps=None) -> list:
+    def prepare_network(self, weights, biases, n1s, level=None, in_scale=None, qps=None, rs_bits=None) -> list:
         """Walk levels and scales: dense -> rescale -> (square -> rescale) ..."""
         pr = self.pr
         level = pr.L if level is None else level
         scale = pr.scale if in_scale is None else in_scale
         layers = []
         for li, (W, b, n1) in enumerate(zip(weights, biases, n1s)):
-            lay = self.prepare_dense(W, b, n1, level, scale, qp=bool(qps[li]) if qps else False)
+            lay = self.prepare_dense(W, b, n1, level, scale, qp=bool(qps[li]) if qps else False,
+                                     rs_bits=int(rs_bits[li]) if rs_bits else 0)
             layers.append(lay)
             scale = scale * lay.pt_scale
             scale = scale / pr.q[level]
@@ -354,11 +357,13 @@ class DenseLayer:
     pt_scale: float
     bias_scale: float
     qp: bool = False           # diagonals over Q_l u P: lazy-ModDown evaluation (orc_dense_qp)
+    rs_bits: int = 0           # rotate-and-sum: sequential (0) or hoisted groups of this many bits
 
 
-def network_steps(layers_shape) -> list[int]:
-    """Union of rotation steps of all dense layers [(m, n, n1), ...]."""
+def network_steps(layers_shape, rs_bits=None) -> list[int]:
+    """Union of rotation steps of all dense layers [(m, n, n1), ...] (rs_bits:
+    the rotate-and-sum form of each layer, default sequential)."""
     steps = set()
-    for m, n, n1 in layers_shape:
-        steps.update(planmod.rotation_steps(m, n, n1))
+    for li, (m, n, n1) in enumerate(layers_shape):
+        steps.update(planmod.rotation_steps(m, n, n1, rs_bits[li] if rs_bits else 0))
     return sorted(steps)

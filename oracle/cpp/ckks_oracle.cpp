@@ -493,26 +493,62 @@ static const u64* find_key(int nrot, const i64* steps, const u64* const* keys, i
 static bool dense_shape_ok(const Ctx& c, int m, int n, int n1) {
   return m > 0 && n > 0 && n1 > 0 && n % m == 0 && m % n1 == 0 && (c.N / 2) % n == 0;
 }
-// Giant steps, rotate-and-sum and bias from the inner sums s[0..n2-1].
+// Rotate-and-sum with hoisted groups (not in the paper: its hoisting applied
+// to the rotate-and-sum).  The R = n/m shifted copies are summed over the
+// log2(R) bits of the shift index, taken in groups of `bits` bits from the
+// most significant: a group of b bits with base shift t replaces z by
+// ModDown(sum_{k < 2^b} rho_ext^{k t}(z)), all its rotations hoisted from the
+// same z and kept over Q_l u P (orc_rotate_ext), brought down once.  Groups of
+// one bit are exactly the sequential steps z + rho^t(z), t = n/2, ..., m.
+static void rotate_sum_hoisted(void* h, std::vector<u64>& z, int level, int m, int n, int bits, int nrot,
+                               const i64* steps, const u64* const* keys) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, ne = nl + c.np, esz = 2 * ne * N;
+  std::vector<int> eidx(ne); for (size_t t = 0; t < ne; ++t) eidx[t] = ext_prime(c, level, (int)t);
+  int left = 0; while ((m << left) < n) ++left;          // log2(n / m) bits still to sum
+  std::vector<u64> acc(esz), r(esz);
+  while (left > 0) {
+    const int b = std::min(bits, left);
+    left -= b;
+    const i64 t = (i64)m << left;
+    std::fill(acc.begin(), acc.end(), 0);
+    for (int k = 0; k < (1 << b); ++k) {
+      orc_rotate_ext(h, z.data(), level, k * t, k ? find_key(nrot, steps, keys, k * t) : nullptr, r.data());
+      for (int p = 0; p < 2; ++p)
+        for (size_t i = 0; i < ne; ++i) for (size_t x = 0; x < N; ++x) {
+          const size_t o = (p * ne + i) * N + x;
+          acc[o] = addmod(acc[o], r[o], c.primes[eidx[i]]);
+        }
+    }
+    orc_moddown(h, acc.data(), level, z.data());
+    orc_moddown(h, acc.data() + ne * N, level, z.data() + nl * N);
+  }
+}
+
+// Giant steps, rotate-and-sum (sequential for rs_bits = 0, else hoisted in
+// groups of rs_bits bits) and bias from the inner sums s[0..n2-1].
 static void dense_tail(void* h, const std::vector<std::vector<u64>>& s, int level, int m, int n, int n1,
-                       const u64* bias, int nrot, const i64* steps, const u64* const* keys, u64* out) {
+                       const u64* bias, int nrot, const i64* steps, const u64* const* keys, int rs_bits, u64* out) {
   const size_t csz = s[0].size();
   std::vector<u64> z = s[0], rot(csz);
   for (size_t j = 1; j < s.size(); ++j) {
     orc_rotate(h, s[j].data(), level, (i64)n1 * j, find_key(nrot, steps, keys, (i64)n1 * j), rot.data());
     orc_add(h, z.data(), rot.data(), level, z.data());
   }
-  for (int t = n / 2; t >= m; t /= 2) {
-    orc_rotate(h, z.data(), level, t, find_key(nrot, steps, keys, t), rot.data());
-    orc_add(h, z.data(), rot.data(), level, z.data());
+  if (rs_bits > 0) {
+    rotate_sum_hoisted(h, z, level, m, n, rs_bits, nrot, steps, keys);
+  } else {
+    for (int t = n / 2; t >= m; t /= 2) {
+      orc_rotate(h, z.data(), level, t, find_key(nrot, steps, keys, t), rot.data());
+      orc_add(h, z.data(), rot.data(), level, z.data());
+    }
   }
   if (bias) orc_add_plain(h, z.data(), bias, level, z.data());
   std::memcpy(out, z.data(), csz * sizeof(u64));
 }
 
-// pts: [m][l+1][N].
-int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
-              int nrot, const i64* steps, const u64* const* keys, u64* out) {
+// pts: [m][l+1][N]; rs_bits: rotate-and-sum form (0 sequential, else hoisted groups of that many bits).
+static int dense_std(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+                     int nrot, const i64* steps, const u64* const* keys, int rs_bits, u64* out) {
   Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, csz = 2 * nl * N;
   if (!dense_shape_ok(c, m, n, n1)) return -1;
   const int n2 = m / n1;
@@ -527,7 +563,7 @@ int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64
         orc_mult_plain(h, baby[i].data(), pts + (size_t)(n1 * j + i) * nl * N, level, prod.data());
         orc_add(h, s[j].data(), prod.data(), level, s[j].data());
       }
-    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, out);
+    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, rs_bits, out);
   } catch (const std::exception&) { return -3; }
   return 0;
 }
@@ -540,8 +576,8 @@ int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64
 // then giant steps, rotate-and-sum and bias as in orc_dense.  Not in the paper:
 // a reordering of its baby-step/giant-step evaluation that moves the ModDown
 // behind the plaintext products (one per inner sum instead of one per baby step).
-int orc_dense_qp(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
-                 int nrot, const i64* steps, const u64* const* keys, u64* out) {
+static int dense_qp(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+                    int nrot, const i64* steps, const u64* const* keys, int rs_bits, u64* out) {
   Ctx& c = *(Ctx*)h; const size_t N = c.N, nl = level + 1, ne = nl + c.np, csz = 2 * nl * N, esz = 2 * ne * N;
   if (!dense_shape_ok(c, m, n, n1)) return -1;
   const int n2 = m / n1;
@@ -566,9 +602,25 @@ int orc_dense_qp(void* h, const u64* ct, int level, int m, int n, int n1, const 
       orc_moddown(h, acc.data(), level, s[j].data());
       orc_moddown(h, acc.data() + ne * N, level, s[j].data() + nl * N);
     }
-    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, out);
+    dense_tail(h, s, level, m, n, n1, bias, nrot, steps, keys, rs_bits, out);
   } catch (const std::exception&) { return -3; }
   return 0;
+}
+
+int orc_dense(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+              int nrot, const i64* steps, const u64* const* keys, u64* out) {
+  return dense_std(h, ct, level, m, n, n1, pts, bias, nrot, steps, keys, 0, out);
+}
+int orc_dense_qp(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+                 int nrot, const i64* steps, const u64* const* keys, u64* out) {
+  return dense_qp(h, ct, level, m, n, n1, pts, bias, nrot, steps, keys, 0, out);
+}
+// Either form (qp != 0: lazy ModDown) with the rotate-and-sum form rs_bits.
+int orc_dense_ex(void* h, const u64* ct, int level, int m, int n, int n1, const u64* pts, const u64* bias,
+                 int nrot, const i64* steps, const u64* const* keys, int qp, int rs_bits, u64* out) {
+  if (rs_bits < 0 || rs_bits > 16) return -1;
+  return qp ? dense_qp(h, ct, level, m, n, n1, pts, bias, nrot, steps, keys, rs_bits, out)
+            : dense_std(h, ct, level, m, n, n1, pts, bias, nrot, steps, keys, rs_bits, out);
 }
 
 }  // extern "C"

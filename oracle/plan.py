@@ -62,14 +62,32 @@ def input_slots(x: np.ndarray, slots: int) -> np.ndarray:
     return np.asarray(x, dtype=np.float64)[np.arange(slots) % n]
 
 
-def rotation_steps(m: int, n: int, n1: int) -> list[int]:
-    """Baby steps 1..n1-1, giant steps n1*j (j < m/n1), rotate-and-sum n/2..m."""
-    steps = list(range(1, n1)) + [n1 * j for j in range(1, m // n1)]
-    t = n // 2
-    while t >= m:
-        steps.append(t)
-        t //= 2
+def rotate_sum_steps(m: int, n: int, rs_bits: int = 0) -> list[int]:
+    """Rotation amounts of the rotate-and-sum that leaves period m from period
+    n.  rs_bits = 0: sequential n/2, n/4, .., m.  rs_bits = b > 0: hoisted
+    groups over the log2(n/m) bits of the shift index, b bits at a time from
+    the most significant; a group of b' bits with base shift t uses k t for
+    0 < k < 2^b'.  (b = 1 gives the sequential amounts.)"""
+    if rs_bits <= 0:
+        steps, t = [], n // 2
+        while t >= m:
+            steps.append(t)
+            t //= 2
+        return steps
+    left = (n // m).bit_length() - 1
+    steps = []
+    while left > 0:
+        b = min(rs_bits, left)
+        left -= b
+        t = m << left
+        steps += [k * t for k in range(1, 1 << b)]
     return steps
+
+
+def rotation_steps(m: int, n: int, n1: int, rs_bits: int = 0) -> list[int]:
+    """Baby steps 1..n1-1, giant steps n1*j (j < m/n1), rotate-and-sum steps."""
+    steps = list(range(1, n1)) + [n1 * j for j in range(1, m // n1)]
+    return steps + rotate_sum_steps(m, n, rs_bits)
 
 
 def op_counts(m: int, n: int, n1: int) -> dict:

@@ -309,19 +309,40 @@ class Tiny:
         b = [[(x + v * P) % q for x, v in zip(ub[i], c0[i])] for i, q in enumerate(mods)] + ub[level + 1:]
         return [b, ua]
 
-    def _dense_tail(self, sums, level, m, n, n1, bias, rot):
+    def _rotate_sum_hoisted(self, z, level, m, n, bits, rot):
+        """Hoisted rotate-and-sum: per group of b bits (most significant first)
+        with base shift t, z <- ModDown(sum_{k < 2^b} rho_ext^{k t}(z))."""
+        mods = self._ext(level)
+        left = (n // m).bit_length() - 1
+        while left > 0:
+            b = min(bits, left)
+            left -= b
+            t = m << left
+            acc = [[[0] * self.n for _ in mods] for _ in range(2)]
+            for k in range(1 << b):
+                r = self.rotate_ext(z, level, k * t, rot)
+                for p in range(2):
+                    for i, q in enumerate(mods):
+                        acc[p][i] = [(x + y) % q for x, y in zip(acc[p][i], r[p][i])]
+            z = [self.moddown(acc[0], level), self.moddown(acc[1], level)]
+        return z
+
+    def _dense_tail(self, sums, level, m, n, n1, bias, rot, rs_bits=0):
         z = sums[0]
         for j in range(1, len(sums)):
             z = self.add(z, self.rotate(sums[j], level, n1 * j, rot), level)
-        t = n // 2
-        while t >= m:
-            z = self.add(z, self.rotate(z, level, t, rot), level)
-            t //= 2
+        if rs_bits > 0:
+            z = self._rotate_sum_hoisted(z, level, m, n, rs_bits, rot)
+        else:
+            t = n // 2
+            while t >= m:
+                z = self.add(z, self.rotate(z, level, t, rot), level)
+                t //= 2
         if bias is not None:
             z = self.add_plain(z, bias, level)
         return z
 
-    def dense(self, ct, level, m, n, n1, pts, bias, rot):
+    def dense(self, ct, level, m, n, n1, pts, bias, rot, rs_bits=0):
         n2 = m // n1
         baby = [ct] + [self.rotate(ct, level, i, rot) for i in range(1, n1)]
         sums = []
@@ -331,9 +352,9 @@ class Tiny:
                 prod = self.mult_plain(baby[i], pts[n1 * j + i], level)
                 s = prod if s is None else self.add(s, prod, level)
             sums.append(s)
-        return self._dense_tail(sums, level, m, n, n1, bias, rot)
+        return self._dense_tail(sums, level, m, n, n1, bias, rot, rs_bits)
 
-    def dense_qp(self, ct, level, m, n, n1, pts, bias, rot):
+    def dense_qp(self, ct, level, m, n, n1, pts, bias, rot, rs_bits=0):
         """Lazy-ModDown dense: inner sums over Q_l u P (pts over Q_l u P), one
         ModDown per inner sum, then the same giant steps / rotate-and-sum / bias."""
         n2 = m // n1
@@ -349,4 +370,4 @@ class Tiny:
                         pr = negacyclic_mul(baby[i][k][t], pt[t], q)
                         acc[k][t] = [(x + y) % q for x, y in zip(acc[k][t], pr)]
             sums.append([self.moddown(acc[0], level), self.moddown(acc[1], level)])
-        return self._dense_tail(sums, level, m, n, n1, bias, rot)
+        return self._dense_tail(sums, level, m, n, n1, bias, rot, rs_bits)

@@ -404,6 +404,49 @@ def test_dense_qp_slots(o10, keys10, m, n, n1):
         assert not np.array_equal(out.data, std.data)   # a different rounding point
 
 
+# ------------------------------------------------- hoisted rotate-and-sum
+def _dense_case(o, keys0, m, n, n1, seed, qp=False, rs_bits=0, extra_rs=()):
+    pr = o.pr
+    rng = np.random.default_rng(seed)
+    W, b, x = rng.normal(0, 0.1, (m, n)), rng.normal(0, 0.1, m), rng.uniform(-1, 1, n)
+    steps = set(plan.rotation_steps(m, n, n1, rs_bits))
+    for r in extra_rs:
+        steps |= set(plan.rotation_steps(m, n, n1, r))
+    keys = keys0 if steps <= set(keys0.rot) else o.keygen(11, steps=sorted(steps | set(keys0.rot)))
+    ct = o.encrypt(plan.input_slots(x, pr.slots), keys.pk, seed + 7)
+    return W, b, x, keys, ct
+
+
+@pytest.mark.parametrize("m,n,n1,qp", [(4, 64, 2, False), (4, 64, 2, True), (2, 16, 1, False), (8, 256, 4, True)])
+def test_rotate_sum_one_bit_groups_are_sequential(o10, keys10, m, n, n1, qp):
+    # A hoisted group of one bit is ModDown(P z + rho_ext^t(z)) = z + rho^t(z)
+    # exactly, and the groups run from the largest shift down, so rs_bits = 1
+    # reproduces the sequential rotate-and-sum bit for bit.
+    W, b, x, keys, ct = _dense_case(o10, keys10, m, n, n1, 50 + m + n, qp, 0, (1,))
+    seq = o10.dense(ct, o10.prepare_dense(W, b, n1, ct.level, ct.scale, qp=qp), keys)
+    one = o10.dense(ct, o10.prepare_dense(W, b, n1, ct.level, ct.scale, qp=qp, rs_bits=1), keys)
+    assert np.array_equal(seq.data, one.data)
+
+
+@pytest.mark.parametrize("m,n,n1,qp,rs_bits", [(4, 64, 2, False, 2), (4, 64, 2, True, 4), (2, 128, 2, False, 3),
+                                               (8, 256, 4, True, 3), (16, 16, 4, False, 2)])
+def test_rotate_sum_hoisted_slots(o10, keys10, m, n, n1, qp, rs_bits):
+    # Groups of several bits: decrypts to W x + b and to the sequential form's
+    # value within the rounding of the extra ModDowns (n = m: no rotate-and-sum,
+    # identical to the sequential form).
+    pr = o10.pr
+    W, b, x, keys, ct = _dense_case(o10, keys10, m, n, n1, 60 + m + n, qp, rs_bits)
+    hz = o10.dense(ct, o10.prepare_dense(W, b, n1, ct.level, ct.scale, qp=qp, rs_bits=rs_bits), keys)
+    got = o10.decrypt_decode(o10.rescale(hz), keys.sk).real
+    assert np.max(np.abs(got - plan.bias_slots(W @ x + b, pr.slots))) < 2.0 ** -14
+    keys_s = keys if set(plan.rotation_steps(m, n, n1)) <= set(keys.rot) else \
+        o10.keygen(11, steps=sorted(set(keys.rot) | set(plan.rotation_steps(m, n, n1))))
+    seq = o10.dense(ct, o10.prepare_dense(W, b, n1, ct.level, ct.scale, qp=qp), keys_s)
+    ref = o10.decrypt_decode(o10.rescale(seq), keys.sk).real
+    assert np.max(np.abs(got - ref)) < 2.0 ** -18
+    assert np.array_equal(hz.data, seq.data) == (n == m)
+
+
 def test_dense_plan_slot_algebra():
     # The plan's diagonals and pre-rotation reproduce W x in plain slot arithmetic.
     rng = np.random.default_rng(16)
@@ -494,6 +537,17 @@ def test_tiny_bit_exact(oracle_lib, log_n):
     got = o.dense(ct, lay_qp, K)
     want = T.dense_qp(c, L, m, n, n1, lay_qp.pts.tolist(), lay_qp.bias.tolist(), rot)
     assert np.array_equal(got.data, A(want))
+    # hoisted rotate-and-sum (2 -> period 2 from 8: shifts 2, 4, 6 in one group), both forms
+    m3, n3, n13 = 2, 8, 2
+    st3 = sorted(set(steps) | set(plan.rotation_steps(m3, n3, n13, 2)))
+    K3 = o.keygen(7, st3)
+    _, _, _, rot3 = T.keygen(7, st3)
+    W3, b3 = rng.normal(0, 0.1, (m3, n3)), rng.normal(0, 0.1, m3)
+    for qp in (False, True):
+        lay3 = o.prepare_dense(W3, b3, n13, L, ct.scale, qp=qp, rs_bits=2)
+        fn = T.dense_qp if qp else T.dense
+        want = fn(c, L, m3, n3, n13, lay3.pts.tolist(), lay3.bias.tolist(), rot3, rs_bits=2)
+        assert np.array_equal(o.dense(ct, lay3, K3).data, A(want)), qp
     # Two-layer network: dense -> rescale -> square -> rescale -> dense.
     W2 = rng.normal(0, 0.1, (2, m))
     b2 = rng.normal(0, 0.1, 2)
