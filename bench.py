@@ -74,7 +74,7 @@ def setup(plan, batch, seed=7):
         pts = residues(plan.q[: lay.level + 1] + (plan.p if lay.qp else []), N, (lay.m,), seed + 100 + li)
         bias = residues(plan.q[: lay.level + 1], N, (), seed + 200 + li)
         layers.append(ctx.dense_load(lay.level, lay.m, lay.n, lay.n1, pts, bias, lay.pt_scale, lay.bias_scale,
-                                     qp=lay.qp))
+                                     qp=lay.qp, rs_bits=lay.rs_bits))
     runner = NetworkRunner(ctx, plan, layers, batch)
     for b in range(batch):
         x = residues(plan.q, N, (2,), seed + 1000 + b)
@@ -259,8 +259,9 @@ KERNEL_LABEL = {
     "ks_final_steps": "key-switch epilogue, all hoisted steps of a batch in one launch",
     "multplain": "MultPlain inner sums (one baby step)",
     "ks_final_multplain": "baby-step key-switch epilogue folded into the MultPlain inner sums",
-    "ks_inner_ext_multplain": "lazy-ModDown baby steps: key inner products of every baby step fused into the "
-                              "plaintext inner sums over Q u P (automorphism gathered), one launch per layer",
+    "ks_inner_ext_multplain": "fused extended sums: the key inner products of every hoisted step (lazy-ModDown "
+                              "baby steps, hoisted rotate-and-sum groups) summed over Q u P in registers, with "
+                              "the plaintext diagonals for the baby steps",
     "ext_multplain": "lazy-ModDown inner sums over Q u P from stored key-switch products",
 }
 
@@ -316,20 +317,30 @@ ALU_CLASSES = ("ks_inner_ext_multplain",)
 
 
 def fused_ops(plan, batch) -> int:
-    """Algorithmic VALU lane operations of the fused lazy-ModDown baby-step
-    kernels of one inference step: per item, baby step and coefficient, 2 beta
-    key products and 2 n2 plaintext products on every limb of Q_l u P plus the
-    lift of c0 on the Q-limbs; the unrotated term adds 2 lifts and 2 n2
-    plaintext products per Q-limb."""
+    """Algorithmic VALU lane operations of the fused extended-sum kernels of
+    one inference step.  Lazy-ModDown baby steps: per item, baby step and
+    coefficient, 2 beta key products and 2 n2 plaintext products on every limb
+    of Q_l u P plus the lift of c0 on the Q-limbs; the unrotated term adds 2
+    lifts and 2 n2 plaintext products per Q-limb.  Hoisted rotate-and-sum
+    groups of b bits: the same with 2^b - 1 steps, n2 = 1 and the plaintext
+    product replaced by the reduction of each term (a Shoup product by 1)."""
     N, K = 1 << plan.log_n, len(plan.p)
     total = 0
     for lay in plan.layers:
-        if not (lay.qp and lay.n1 > 1 and lay.n2 <= 8):
-            continue
         l1 = lay.level + 1
         ne, beta = l1 + K, -(-l1 // plan.alpha)
-        per_step = ne * (2 * beta * OPS_KEY + 2 * lay.n2 * OPS_PT) + l1 * OPS_LIFT
-        total += batch * N * ((lay.n1 - 1) * per_step + l1 * (2 * OPS_LIFT + 2 * lay.n2 * OPS_PT))
+
+        def per_item(steps, n2):
+            per_step = ne * (2 * beta * OPS_KEY + 2 * n2 * OPS_PT) + l1 * OPS_LIFT
+            return steps * per_step + l1 * (2 * OPS_LIFT + 2 * n2 * OPS_PT)
+        if lay.qp and lay.n1 > 1 and lay.n2 <= 8:
+            total += batch * N * per_item(lay.n1 - 1, lay.n2)
+        if lay.rs_bits > 0:
+            left = (lay.n // lay.m).bit_length() - 1
+            while left > 0:
+                b = min(lay.rs_bits, left)
+                left -= b
+                total += batch * N * per_item((1 << b) - 1, 1)
     return total
 
 
@@ -373,6 +384,7 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     plan = netplan.preset_plan(name, netplan.tuned_shapes(name, tuned, tuned_n1))
     log(f"{name}: N=2^{plan.log_n}, L={plan.L}, K={len(plan.p)}, alpha={plan.alpha}, batch={batch}, "
         f"n1={[l.n1 for l in plan.layers]}, lazy ModDown={[l.qp for l in plan.layers]}, "
+        f"rotate-and-sum bits={[l.rs_bits for l in plan.layers]}, "
         f"knobs={tuned.get('knobs') if tuned else None}")
     ctx, runner = setup(plan, batch)
     tune.apply_knobs(ctx, tuned)
@@ -411,11 +423,13 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
            "plain_eager_p50_ms": float(np.percentile(lat_eager, 50)),
            "workload": (f"{name}: N=2^{plan.log_n}, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, "
                         f"P {len(c['p_bits'])}x{c['p_bits'][0]}b, alpha={plan.alpha}, layers "
-                        + ", ".join(f"{l.n}->{l.m} (n1={l.n1}{', lazy ModDown' if l.qp else ''})"
+                        + ", ".join(f"{l.n}->{l.m} (n1={l.n1}{', lazy ModDown' if l.qp else ''}"
+                                    f"{f', rotate-and-sum hoisted {l.rs_bits} bits' if l.rs_bits else ''})"
                                     for l in plan.layers) + ", x^2 between"),
            "ops_per_inference": plan.op_counts(),
            "tuning": {"knobs": tuned.get("knobs"), "n1": tuned.get("n1") if tuned_n1 else None,
-                      "lazy_moddown": [l.qp for l in plan.layers]} if tuned else None}
+                      "lazy_moddown": [l.qp for l in plan.layers],
+                      "rotate_sum_bits": [l.rs_bits for l in plan.layers]} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
     if trace:
         log(f"{name}: traced eager pass")

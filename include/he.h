@@ -170,10 +170,21 @@ int he_dense_free(he_dense* d);
  * forms s_j = ModDown(sum_i MultPlain(r_i, pt_{n1 j + i})) (both
  * polynomials; one ModDown per inner sum instead of one per baby step), and
  * continues with the giant steps, rotate-and-sum and bias as above.  The
- * bias stays uint64[level+1][N].  flags = 0 is he_dense_load /
+ * bias stays uint64[level+1][N].
+ * flags |= HE_DENSE_RS(b), 1 <= b <= HE_DENSE_RS_MAX: the rotate-and-sum is
+ * hoisted (the paper's hoisting applied to it; also a plan parameter, as it
+ * changes the rounding): the n/m shifted copies are summed over the log2(n/m)
+ * bits of the shift index in groups of b bits, most significant first; a group
+ * of b' bits with base shift t sets z <- ModDown(sum_{k < 2^b'} rho^{k t}(z)),
+ * every rotation of the group from one ModUp of z and kept over Q_level u P
+ * until that single ModDown (so keys for the amounts k t are needed).  b = 1
+ * gives exactly the sequential steps.  flags = 0 is he_dense_load /
  * he_dense_bytes; other bits: HE_EINVAL.  dev: the diagonals (NTT form), their
  * Shoup companions, then the bias, as above. */
 #define HE_DENSE_QP 1u
+#define HE_DENSE_RS_SHIFT 8
+#define HE_DENSE_RS_MAX 6
+#define HE_DENSE_RS(b) ((uint32_t)(b) << HE_DENSE_RS_SHIFT)
 size_t he_dense_bytes_ex(const he_ctx* ctx, uint32_t level, uint32_t m, int has_bias, uint32_t flags);
 int he_dense_load_ex(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
                      const uint64_t* bias, double pt_scale, double bias_scale, uint32_t flags, void* dev,

@@ -400,7 +400,10 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
 int he_dense_load_ex(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
                      const uint64_t* bias, double pt_scale, double bias_scale, uint32_t flags, void* dev, size_t bytes,
                      he_dense** out) {
-  if (!c || !pt_diag || !dev || !out || (flags & ~(uint32_t)HE_DENSE_QP)) return HE_EINVAL;
+  const u32 rs_bits = (flags >> HE_DENSE_RS_SHIFT) & 0xFF;
+  if (!c || !pt_diag || !dev || !out || (flags & ~(uint32_t)(HE_DENSE_QP | (0xFFu << HE_DENSE_RS_SHIFT))) ||
+      rs_bits > HE_DENSE_RS_MAX)
+    return HE_EINVAL;
   auto pow2 = [](u32 v) { return v && !(v & (v - 1)); };
   if (level >= c->nq) return HE_ELEVEL;
   if (!pow2(m) || !pow2(n) || !pow2(n1) || n % m || m % n1 || (c->N / 2) % n) return HE_EINVAL;
@@ -434,7 +437,7 @@ int he_dense_load_ex(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t
   if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
   he_dense* h = new (std::nothrow) he_dense;
   if (!h) return HE_ENOMEM;
-  *h = he_dense{c, level, m, n, n1, m / n1, pt_scale, bias_scale, pl, d, db};
+  *h = he_dense{c, level, m, n, n1, m / n1, pt_scale, bias_scale, pl, rs_bits, d, db};
   *out = h;
   return HE_OK;
 }

@@ -121,6 +121,7 @@ struct he_dense {
   u32 level, m, n, n1, n2;
   double pt_scale, bias_scale;
   u32 pl;      // limbs per diagonal: level+1, or level+1+K over Q_l u P (lazy-ModDown evaluation)
+  u32 rs_bits; // rotate-and-sum: 0 sequential, else hoisted groups of this many bits
   u64* pts;    // [m][pl][N], NTT form, then their Shoup companions floor(w 2^64 / q), same shape
   u64* bias;   // [level+1][N], NTT form, or null
 };

@@ -202,9 +202,9 @@ int ks_steps_inner(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, const OwnMap& ow
 }
 
 // ModDown of Z ciphertexts over Q_l u P (y = [Z][2][l+1+K][N], NTT form, limbs
-// in [0, q)) into out + z 2 (l+1) N: inverse NTT of the P-limbs in place,
+// in [0, q)) into om (+ bias on c0): inverse NTT of the P-limbs in place,
 // conversion to Q_l (conv, coefficient form), its NTT, and the combine.
-int moddown_items(he_ctx* c, u32 l, u32 Z, u64* y, u64* conv, u64* out) {
+int moddown_items(he_ctx* c, u32 l, u32 Z, u64* y, u64* conv, const OutMap& om, const u64* bias) {
   const size_t N = c->N;
   const u32 ne = l + 1 + c->np;
   PolyBatch pi = batch_of(Z);
@@ -221,7 +221,7 @@ int moddown_items(he_ctx* c, u32 l, u32 Z, u64* y, u64* conv, u64* out) {
   pf.stride = (size_t)2 * (l + 1) * N;
   for (u32 r = 0; r < 2 * (l + 1); ++r) pf.prime[r] = (uint8_t)(r % (l + 1));
   if ((rc = launch_ntt(c, pf, false))) return rc;
-  return launch_moddown_final(c, l, Z, y, conv, out);
+  return launch_moddown_final(c, l, Z, y, conv, om, bias);
 }
 
 int ks_steps(he_ctx* c, u32 l, u32 B, u32 S, const WS& w, u64* const* c1, const StepKeys& keys, const Items& add0,
@@ -455,8 +455,35 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     if (!(baby[i] = find_rot(c, galois_of(c, i)))) return HE_ENOKEY;   // i < n1 <= 64 < N/2: never the identity
   for (u32 j = 1; j < n2; ++j)
     if (galois_of(c, (int64_t)n1 * j) != 1 && !(giant[j] = find_rot(c, galois_of(c, (int64_t)n1 * j)))) return HE_ENOKEY;
-  for (size_t u = 0; u < rs_steps.size(); ++u)
-    if (galois_of(c, rs_steps[u]) != 1 && !(rsk[u] = find_rot(c, galois_of(c, rs_steps[u])))) return HE_ENOKEY;
+  // Hoisted rotate-and-sum (rs_bits > 0): groups of rs_bits bits of the shift
+  // index from the most significant; group g sums rho^{k t_g}, 0 < k < 2^b_g.
+  const bool rs_hoisted = d->rs_bits > 0 && !rs_steps.empty();
+  std::vector<u32> grp_bits, grp_shift;
+  std::vector<StepKeys> grp_keys;
+  if (rs_hoisted) {
+    u32 left = 0;
+    while ((d->m << left) < d->n) ++left;
+    while (left > 0) {
+      const u32 b = std::min<u32>(d->rs_bits, left);
+      left -= b;
+      const u32 t = d->m << left;
+      StepKeys sk;
+      std::memset(&sk, 0, sizeof(sk));
+      for (u32 k = 1; k < (1u << b); ++k) {       // k t < n <= N/2: never the identity
+        const KeySlot* ks = find_rot(c, galois_of(c, (int64_t)k * t));
+        if (!ks) return HE_ENOKEY;
+        sk.key[k - 1] = ks->dev;
+        sk.galois[k - 1] = ks->galois;
+        sk.galois_inv[k - 1] = galois_inverse(c, ks->galois);
+      }
+      grp_bits.push_back(b);
+      grp_shift.push_back(t);
+      grp_keys.push_back(sk);
+    }
+  } else {
+    for (size_t u = 0; u < rs_steps.size(); ++u)
+      if (galois_of(c, rs_steps[u]) != 1 && !(rsk[u] = find_rot(c, galois_of(c, rs_steps[u])))) return HE_ENOKEY;
+  }
 
   const size_t N = c->N, csz = (size_t)2 * (l + 1) * N;
   const WS w = carve(c);
@@ -495,7 +522,11 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
         if ((rc = launch_ks_inner_steps(c, l, n, S, w.ext, 0, own_of(n, c1in), sk, w.u))) return rc;
         if ((rc = launch_ext_multplain(c, l, n, n1, n2, w.u, sk, inI, d->pts, w.ext))) return rc;
       }
-      if ((rc = moddown_items(c, l, n2 * n, sqp, w.conv, w.giant))) return rc;
+      OutMap om;
+      std::memset(&om, 0, sizeof(om));
+      om.base = w.giant;
+      om.ob = csz;
+      if ((rc = moddown_items(c, l, n2 * n, sqp, w.conv, om, nullptr))) return rc;
     } else {
       if ((rc = ks_steps_inner(c, l, n, S, w, own_of(n, c1in), 0, sk))) return rc;
       if ((rc = launch_ks_final_multplain(c, l, n, n1, n2, w.u, w.conv, sk, inI, d->pts, w.giant))) return rc;
@@ -507,7 +538,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
   // Giant steps then rotate-and-sum, each a full key switch; the last one
   // writes the caller's output and adds the bias.
   // giant region [n2][B][csz]: s_j of item b at giant + (j n + b) csz
-  u32 total = (n2 - 1) + (u32)rs_steps.size();
+  u32 total = (n2 - 1) + (rs_hoisted ? 0u : (u32)rs_steps.size());
   u64* cur[HE_MAXB];
   for (u32 b = 0; b < n; ++b) cur[b] = w.giant + (size_t)b * csz;
   bool giants_batched = n2 > 1 && n2 - 1 <= giant_group(c->ws_n2);
@@ -543,12 +574,12 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       return HE_OK;
     }
     for (u32 b = 0; b < n; ++b) cur[b] = w.z0 + (size_t)b * csz;
-    total = (u32)rs_steps.size();
+    total = rs_hoisted ? 0u : (u32)rs_steps.size();
   }
   u32 done = 0;
   auto step = [&](const KeySlot* key, u64* const* src, bool accumulate_in_place) -> int {
     ++done;
-    const bool last = done == total;
+    const bool last = done == total && !rs_hoisted;
     u64* dst[HE_MAXB];
     for (u32 b = 0; b < n; ++b) {
       if (last) dst[b] = out[b].dev;
@@ -584,12 +615,35 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     for (u32 b = 0; b < n; ++b) src[b] = w.giant + ((size_t)j * n + b) * csz;
     if ((rc = step(giant[j], src, true))) return rc;
   }
-  for (size_t u = 0; u < rs_steps.size(); ++u) {
+  for (size_t u = 0; u < rs_steps.size() && !rs_hoisted; ++u) {
     u64* src[HE_MAXB];
     for (u32 b = 0; b < n; ++b) src[b] = cur[b];
     if ((rc = step(rsk[u], src, false))) return rc;
   }
-  if (total == 0) {
+  for (size_t g = 0; g < grp_bits.size(); ++g) {
+    // one hoisted group: ModUp of cur's c1, the 2^b - 1 rotations' inner
+    // products summed with P cur in registers (extended basis), one ModDown
+    const bool last = g + 1 == grp_bits.size();
+    u64* c1[HE_MAXB];
+    Items ci;
+    ci.n = n;
+    for (u32 b = 0; b < n; ++b) {
+      c1[b] = cur[b] + (size_t)(l + 1) * N;
+      ci.p[b] = cur[b];
+    }
+    if ((rc = modup(c, l, n, c1, w))) return rc;
+    if ((rc = launch_ks_ext_fused(c, l, n, 1u << grp_bits[g], 1, w.ext, own_of(n, c1), grp_keys[g], ci, nullptr,
+                                  w.u)))
+      return rc;
+    OutMap om;
+    std::memset(&om, 0, sizeof(om));
+    for (u32 b = 0; b < n; ++b)
+      om.ptr[b] = last ? out[b].dev
+                       : ((cur[b] == w.z0 + (size_t)b * csz) ? w.z1 + (size_t)b * csz : w.z0 + (size_t)b * csz);
+    if ((rc = moddown_items(c, l, n, w.u, w.conv, om, last ? d->bias : nullptr))) return rc;
+    for (u32 b = 0; b < n; ++b) cur[b] = om.ptr[b];
+  }
+  if (total == 0 && !rs_hoisted) {
     Items o;
     o.n = n;
     for (u32 b = 0; b < n; ++b) {

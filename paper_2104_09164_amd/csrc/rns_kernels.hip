@@ -408,8 +408,8 @@ __device__ __forceinline__ void ks_ext_fused_body(const u64* __restrict__ ext, c
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) {
       const size_t o = ((size_t)n1 * jj * ne + t) * N + x;
-      pt[jj] = pts[o];
-      ps[jj] = pts[comp + o];
+      pt[jj] = pts ? pts[o] : 1;                   // no plaintexts: a plain sum (x 1, companion mu)
+      ps[jj] = pts ? pts[comp + o] : P.mu;
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -439,8 +439,8 @@ __device__ __forceinline__ void ks_ext_fused_body(const u64* __restrict__ ext, c
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) {
       const size_t o = (((size_t)n1 * jj + i) * ne + t) * N + x;
-      pt[jj] = pts[o];
-      ps[jj] = pts[comp + o];
+      pt[jj] = pts ? pts[o] : 1;
+      ps[jj] = pts ? pts[comp + o] : P.mu;
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -503,10 +503,12 @@ __global__ void __launch_bounds__(BS) k_ks_ext_fused(const u64* __restrict__ ext
 
 // ModDown output of Z extended ciphertexts: out(z) = (y_Q - conv) P^{-1} over
 // limbs i <= l (NTT domain), y = [Z][2][ne][N] (Q-limbs in [0, q)), conv =
-// [Z][2][l+1][N]; out(z) at out + z csz.  grid: (N/BS, l+1, Z)
+// [Z][2][l+1][N]; out(z) at om (base + z ob, or ptr[z]); + bias on c0 when
+// non-null.  grid: (N/BS, l+1, Z)
 __global__ void __launch_bounds__(BS) k_moddown_final(const u64* __restrict__ y, const u64* __restrict__ conv,
-                                                      u64* __restrict__ out, const PrimeConst* __restrict__ pc,
-                                                      const u64* __restrict__ md, u32 N, u32 l, u32 np, u32 nq) {
+                                                      OutMap om, const u64* __restrict__ bias,
+                                                      const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                      u32 N, u32 l, u32 np, u32 nq) {
   const u32 k = blockIdx.x * BS + threadIdx.x;
   const u32 i = blockIdx.y, z = blockIdx.z;
   const u32 ne = l + 1 + np;
@@ -515,8 +517,10 @@ __global__ void __launch_bounds__(BS) k_moddown_final(const u64* __restrict__ y,
   const u64 w = pinv[2 * i], wsh = pinv[2 * i + 1];
   const size_t yi = ((size_t)z * 2 * ne + i) * N + k;
   const size_t ci = ((size_t)z * 2 * (l + 1) + i) * N + k;
-  u64* o = out + (size_t)z * 2 * (l + 1) * N;
-  o[(size_t)i * N + k] = shoup(y[yi] + q - conv[ci], w, wsh, q);
+  u64* o = om.base ? om.base + z * om.ob : om.ptr[z];
+  u64 r0 = shoup(y[yi] + q - conv[ci], w, wsh, q);
+  if (bias) r0 = add_mod(r0, bias[(size_t)i * N + k], q);
+  o[(size_t)i * N + k] = r0;
   o[(size_t)(l + 1 + i) * N + k] = shoup(y[yi + (size_t)ne * N] + q - conv[ci + (size_t)(l + 1) * N], w, wsh, q);
 }
 
@@ -897,11 +901,12 @@ int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, 
 int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
                         const StepKeys& keys, const Items& in, const u64* pts, u64* sqp) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np, S = n1 - 1;
-  if (n1 < 2 || S > HE_MAX_STEPS || !(n2 == 1 || n2 == 2 || n2 == 4 || n2 == 8) || B != in.n) return HE_EINVAL;
+  if (n1 < 2 || S > HE_MAX_STEPS || !(n2 == 1 || n2 == 2 || n2 == 4 || n2 == 8) || B != in.n || (!pts && n2 != 1))
+    return HE_EINVAL;
   // keys once per step, each item's digits and input once, plaintexts once, the sums written
   TraceScope ts(c, TK_KS_EXT_FUSED,
                 ((double)S * 4.0 * beta * ne + (double)B * (beta * ne + 2.0 * (l + 1) + 2.0 * n2 * ne) +
-                 2.0 * n1 * n2 * ne) * (8.0 * (double)c->N));
+                 (pts ? 2.0 * n1 * n2 * ne : 0.0)) * (8.0 * (double)c->N));
   // items per thread: G n2 <= 16 accumulator pairs (more items per thread
   // measured faster than more waves: each key and plaintext word loaded is
   // used G times)
@@ -933,9 +938,11 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
   return ok();
 }
 
-int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, u64* out) {
-  TraceScope ts(c, TK_MODDOWN_FINAL, (double)Z * 6.0 * (l + 1) * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_moddown_final, dim3(c->N / BS, l + 1, Z), dim3(BS), c->stream, y, conv, out, c->d_pc,
+int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, const OutMap& om,
+                         const u64* bias) {
+  if (!om.base && Z > HE_MAXB) return HE_EINVAL;
+  TraceScope ts(c, TK_MODDOWN_FINAL, ((double)Z * 6.0 + (bias ? 1.0 : 0.0)) * (l + 1) * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_moddown_final, dim3(c->N / BS, l + 1, Z), dim3(BS), c->stream, y, conv, om, bias, c->d_pc,
             c->d_moddown, c->N, l, c->np, c->nq);
   return ok();
 }

@@ -67,6 +67,13 @@ struct OutMap {
   u64* base;
   size_t os, ob;
 };
+// ModDown output of Z extended ciphertexts y = [Z][2][l+1+K][N] whose
+// conversions (NTT form) are in conv = [Z][2][l+1][N]: out(z) = (y_Q - conv)
+// P^{-1} (+ bias on c0 when non-null), out(z) = om.base + z om.ob, or
+// om.ptr[z] (Z <= HE_MAXB).
+int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, const OutMap& om,
+                         const u64* bias);
+
 // Rotation outputs: out(s, b).c0 = add0.p[b].c0[perm_{g_s}(.)] + (u_b - conv_b) P^{-1},
 //                   out(s, b).c1 =                               (u_a - conv_a) P^{-1}.
 int launch_ks_final_steps(he_ctx* c, u32 l, u32 B, u32 S, const u64* u, const u64* conv, const StepKeys& keys,
@@ -102,13 +109,11 @@ int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, 
 // The same inner sums fused with the baby steps' key inner products (digits
 // of item b in ext as for launch_ks_inner_steps with ext_items = 0, own limbs
 // from own.ptr[b]): one launch, no per-step products in memory.  n1 >= 2,
-// n2 in {1, 2, 4, 8}, keys = the n1 - 1 baby steps.
+// n2 in {1, 2, 4, 8}, keys = the n1 - 1 baby steps.  pts = null (n2 = 1): the
+// plain sum sqp[b] = sum_{i < n1} r_i(b) (a hoisted rotate-and-sum group).
 int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
                         const StepKeys& keys, const Items& in, const u64* pts, u64* sqp);
-// ModDown output of Z extended ciphertexts y = [Z][2][l+1+K][N] whose
-// conversions (NTT form) are in conv = [Z][2][l+1][N]: out + z 2 (l+1) N =
-// (y_Q - conv) P^{-1}.
-int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv, u64* out);
+
 
 // comp[i][r][k] = floor(pts[i][r][k] 2^64 / q) for m arrays of nlimbs limbs,
 // limb r over prime r for r <= l, else p_{r-l-1} (the Shoup companions of

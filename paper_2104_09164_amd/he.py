@@ -111,6 +111,7 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_dense_load_ex")
 
 HE_DENSE_QP = 1
+HE_DENSE_RS_SHIFT = 8
 
 
 def _check(rc: int, where: str) -> None:
@@ -149,10 +150,10 @@ class Ct:
 
 
 class Dense:
-    def __init__(self, ctx: "Context", handle, buf, level, m, n, n1, pt_scale, bias_scale, qp=False):
+    def __init__(self, ctx: "Context", handle, buf, level, m, n, n1, pt_scale, bias_scale, qp=False, rs_bits=0):
         self.ctx, self.h, self.buf = ctx, handle, buf
         self.level, self.m, self.n, self.n1 = level, m, n, n1
-        self.pt_scale, self.bias_scale, self.qp = pt_scale, bias_scale, qp
+        self.pt_scale, self.bias_scale, self.qp, self.rs_bits = pt_scale, bias_scale, qp, rs_bits
 
     def __del__(self):
         try:
@@ -229,11 +230,12 @@ class Context:
         self.key_steps = steps
 
     def dense_load(self, level: int, m: int, n: int, n1: int, pts: np.ndarray, bias: np.ndarray | None,
-                   pt_scale: float, bias_scale: float, qp: bool = False) -> Dense:
-        """qp: diagonals over q_0..q_level, p_0..p_{K-1} (lazy-ModDown form, HE_DENSE_QP)."""
+                   pt_scale: float, bias_scale: float, qp: bool = False, rs_bits: int = 0) -> Dense:
+        """qp: diagonals over q_0..q_level, p_0..p_{K-1} (lazy-ModDown form, HE_DENSE_QP);
+        rs_bits: hoisted rotate-and-sum groups (HE_DENSE_RS), 0 = sequential."""
         pts = np.ascontiguousarray(pts, dtype=np.uint64)
         b = np.ascontiguousarray(bias, dtype=np.uint64) if bias is not None else None
-        flags = HE_DENSE_QP if qp else 0
+        flags = (HE_DENSE_QP if qp else 0) | (int(rs_bits) << HE_DENSE_RS_SHIFT)
         if pts.shape != (m, level + 1 + (len(self.p) if qp else 0), self.N):
             raise ValueError(f"diagonals of shape {pts.shape} for m={m}, level={level}, qp={qp}")
         nbytes = int(lib().he_dense_bytes_ex(self.h, level, m, b is not None, flags))
@@ -242,7 +244,7 @@ class Context:
         _check(lib().he_dense_load_ex(self.h, level, m, n, n1, C.c_void_p(pts.ctypes.data),
                                       C.c_void_p(b.ctypes.data) if b is not None else None, pt_scale, bias_scale,
                                       flags, C.c_void_p(buf.data_ptr()), nbytes, C.byref(h)), "he_dense_load_ex")
-        return Dense(self, h, buf, level, m, n, n1, pt_scale, bias_scale, qp)
+        return Dense(self, h, buf, level, m, n, n1, pt_scale, bias_scale, qp, rs_bits)
 
     # ------------------------------------------------------ import/export
     def import_ct(self, coeff: np.ndarray, level: int, scale: float) -> Ct:

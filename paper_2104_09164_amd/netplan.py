@@ -12,6 +12,8 @@ layer needs (baby steps 1..n1-1, giant steps n1*j, rotate-and-sum n/2..m),
 and the per-inference operation counts.  A layer with qp set runs in the
 lazy-ModDown form (diagonals over Q_l u P, one ModDown per inner sum instead of
 one per baby step); like n1 it changes the rounding, so it is part of the plan.
+So is rs_bits: the rotate-and-sum as hoisted groups of that many bits of the
+shift index (0 = the sequential log2(n/m) key switches).
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ class LayerPlan:
     in_scale: float
     pt_scale: float
     qp: bool = False      # lazy-ModDown form (HE_DENSE_QP)
+    rs_bits: int = 0      # rotate-and-sum: 0 sequential, b > 0 hoisted groups of b bits (HE_DENSE_RS)
 
     @property
     def n2(self) -> int:
@@ -36,13 +39,29 @@ class LayerPlan:
     def bias_scale(self) -> float:
         return self.in_scale * self.pt_scale
 
-    def steps(self) -> list[int]:
-        s = list(range(1, self.n1)) + [self.n1 * j for j in range(1, self.n2)]
-        t = self.n // 2
-        while t >= self.m:
-            s.append(t)
-            t //= 2
+    def rs_amounts(self) -> list[int]:
+        """Rotation amounts of the rotate-and-sum (sequential n/2 .. m, or the
+        k t of each hoisted group, most significant group first)."""
+        if self.rs_bits <= 0:
+            s, t = [], self.n // 2
+            while t >= self.m:
+                s.append(t)
+                t //= 2
+            return s
+        left, s = (self.n // self.m).bit_length() - 1, []
+        while left > 0:
+            b = min(self.rs_bits, left)
+            left -= b
+            s += [k * (self.m << left) for k in range(1, 1 << b)]
         return s
+
+    def rs_groups(self) -> int:
+        """Key switches (sequential) or hoisted groups of the rotate-and-sum."""
+        total = (self.n // self.m).bit_length() - 1
+        return total if self.rs_bits <= 0 else -(-total // self.rs_bits)
+
+    def steps(self) -> list[int]:
+        return list(range(1, self.n1)) + [self.n1 * j for j in range(1, self.n2)] + self.rs_amounts()
 
     def rs_count(self) -> int:
         c, t = 0, self.n // 2
@@ -55,7 +74,7 @@ class LayerPlan:
         """ModDowns of one evaluation: one per baby step, or one per inner sum
         in the lazy form, plus one per giant step and rotate-and-sum step."""
         return ((self.n2 if self.qp else 0) if self.n1 > 1 else 0) + (0 if self.qp else self.n1 - 1) \
-            + (self.n2 - 1) + self.rs_count()
+            + (self.n2 - 1) + self.rs_groups()
 
 
 @dataclass
@@ -94,21 +113,23 @@ class NetPlan:
         return max(l.n2 for l in self.layers)
 
     def op_counts(self) -> dict:
-        ks = sum((l.n1 - 1) + (l.n2 - 1) + l.rs_count() for l in self.layers) + (len(self.layers) - 1)
+        ks = sum((l.n1 - 1) + (l.n2 - 1) + len(l.rs_amounts()) for l in self.layers) + (len(self.layers) - 1)
         return {"key_switches": ks, "multplain": sum(l.m for l in self.layers),
                 "rescales": 2 * len(self.layers) - 1, "squares": len(self.layers) - 1,
                 "hoisted_modups": sum(1 for l in self.layers if l.n1 > 1),
                 "moddowns": sum(l.moddowns() for l in self.layers) + (len(self.layers) - 1),
-                "lazy_moddown_layers": [li for li, l in enumerate(self.layers) if l.qp]}
+                "lazy_moddown_layers": [li for li, l in enumerate(self.layers) if l.qp],
+                "hoisted_rotate_and_sum_bits": [l.rs_bits for l in self.layers]}
 
 
 def plan_network(log_n: int, q, p, alpha: int, scale_bits: int, shapes) -> NetPlan:
-    """shapes: [(m, n, n1) or (m, n, n1, qp), ...] from the first layer to the last."""
+    """shapes: [(m, n, n1[, qp[, rs_bits]]), ...] from the first layer to the last."""
     pl = NetPlan(log_n, list(q), list(p), alpha, float(2 ** scale_bits))
     level, s = pl.L, pl.scale
     for li, shp in enumerate(shapes):
         m, n, n1 = shp[:3]
-        lay = LayerPlan(m, n, n1, level, s, pl.scale, bool(shp[3]) if len(shp) > 3 else False)
+        lay = LayerPlan(m, n, n1, level, s, pl.scale, bool(shp[3]) if len(shp) > 3 else False,
+                        int(shp[4]) if len(shp) > 4 else 0)
         pl.layers.append(lay)
         s = s * lay.pt_scale
         s = s / pl.q[level]
@@ -141,11 +162,12 @@ def tuned_shapes(name: str, tuned: dict | None, tuned_n1: bool = True) -> list:
     shapes = [tuple(s) for s in PRESETS[name]["shapes"]]
     if not tuned:
         return shapes
+    rs = tuned.get("rs_bits") or [0] * len(shapes)
     if tuned_n1 and tuned.get("n1"):
         qp = tuned.get("qp") or [False] * len(shapes)
-        return [(m, n, n1, bool(f)) for (m, n, _), n1, f in zip(shapes, tuned["n1"], qp)]
+        return [(m, n, n1, bool(f), int(r)) for (m, n, _), n1, f, r in zip(shapes, tuned["n1"], qp, rs)]
     qp = tuned.get("qp_preset") or [False] * len(shapes)
-    return [(m, n, n1, bool(f)) for (m, n, n1), f in zip(shapes, qp)]
+    return [(m, n, n1, bool(f), int(r)) for (m, n, n1), f, r in zip(shapes, qp, rs)]
 
 
 def preset_plan(name: str, shapes=None) -> NetPlan:

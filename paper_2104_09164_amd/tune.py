@@ -8,9 +8,10 @@ Two kinds of choices:
 * Plan choices that the oracle replays: the baby-step count n1 of each dense
   layer (the paper notes that the baby-step/giant-step trade-off depends on
   the ciphertext counts; Methods, "Algorithmic and cryptographic
-  optimizations") and whether the layer runs in the lazy-ModDown form (one
-  ModDown per inner sum instead of one per baby step) change which key
-  switches run or where they round, hence the output bits, so both are
+  optimizations"), whether the layer runs in the lazy-ModDown form (one
+  ModDown per inner sum instead of one per baby step) and the rotate-and-sum
+  form (sequential, or hoisted groups of rs_bits bits) change which key
+  switches run or where they round, hence the output bits, so all three are
   recorded in the plan; and the batch size (requests per launch), chosen for
   throughput under a latency cap.
 
@@ -132,6 +133,13 @@ def tune_ntt(ctx, items: int, reps: int = 5) -> tuple[dict, dict]:
     return best, table
 
 
+def rs_candidates(m: int, n: int) -> list[int]:
+    """Rotate-and-sum forms worth timing: sequential (0) and hoisted groups of
+    2 .. min(6, log2(n/m)) bits (1 bit is the sequential form)."""
+    total = (n // m).bit_length() - 1
+    return [0] + list(range(2, min(6, total) + 1))
+
+
 def build_context(plan, batch: int, n1_sets: list[list[int]], seed: int = 7):
     """Context with synthetic keys for every rotation step any candidate plan needs."""
     from . import he
@@ -142,8 +150,9 @@ def build_context(plan, batch: int, n1_sets: list[list[int]], seed: int = 7):
     steps = set()
     for lay, cands in zip(plan.layers, n1_sets):
         for n1 in cands:
-            lay2 = type(lay)(lay.m, lay.n, n1, lay.level, lay.in_scale, lay.pt_scale)
-            steps.update(lay2.steps())
+            for rs in rs_candidates(lay.m, lay.n):
+                lay2 = type(lay)(lay.m, lay.n, n1, lay.level, lay.in_scale, lay.pt_scale, False, rs)
+                steps.update(lay2.steps())
     N = 1 << plan.log_n
     allp = plan.q + plan.p
     rot = {s: _residues(allp, N, (plan.dnum, 2), seed + i) for i, s in enumerate(sorted(steps))}
@@ -186,6 +195,32 @@ def tune_n1(ctx, plan, batch: int, n1_sets: list[list[int]], reps: int = 3, pres
     return best_n1, best_qp, preset_qp, tables
 
 
+def tune_rs(ctx, plan, batch: int, n1s: list[int], qps: list[bool], reps: int = 3):
+    """Per layer, at its chosen n1 and form: time every rotate-and-sum form."""
+    N = 1 << plan.log_n
+    best, tables = [], []
+    for li, (lay, n1, qp) in enumerate(zip(plan.layers, n1s, qps)):
+        cts = [ctx.import_ct(_residues(plan.q[: lay.level + 1], N, (2,), 900 + b), lay.level, lay.in_scale)
+               for b in range(batch)]
+        outs = [ctx.new_ct(lay.level) for _ in range(batch)]
+        bias = _residues(plan.q[: lay.level + 1], N, (), 400 + li)
+        pts = _residues(plan.q[: lay.level + 1] + (plan.p if qp else []), N, (lay.m,), 300 + li)
+        table = {}
+        for rs in rs_candidates(lay.m, lay.n):
+            d = ctx.dense_load(lay.level, lay.m, lay.n, n1, pts, bias, lay.pt_scale, lay.bias_scale, qp=qp,
+                               rs_bits=rs)
+            table[rs] = _time(lambda: ctx.eval_dense_batch(cts, d, outs), reps, 1)
+            print(f"[tune] layer {li}: n1={n1} lazy_moddown={qp} rs_bits={rs}: {table[rs]:.3f} ms", file=sys.stderr,
+                  flush=True)
+            del d
+        b = pick_min(table)
+        if b and table[0] <= LAZY_MARGIN * table[b]:
+            b = 0                               # keep the sequential form unless the hoisted one clearly wins
+        best.append(b)
+        tables.append(table)
+    return best, tables
+
+
 def tune_batch(ctx, plan, layers, batches: list[int], cap_ms: float | None, reps: int = 3):
     """Whole-network throughput (graph replay) at each batch size."""
     from .batch import NetworkRunner
@@ -212,19 +247,23 @@ def tune_workload(name: str, batch: int, cap_ms: float | None = None, out_dir: s
     knobs, ntt_table = tune_ntt(ctx, items=min(batch, 64))
     n1s, qps, qp_preset, n1_tables = tune_n1(ctx, plan, batch, n1_sets,
                                              preset_n1=[l.n1 for l in plan.layers])
-    shapes = [(l.m, l.n, n1, qp) for l, n1, qp in zip(plan.layers, n1s, qps)]
+    # the rotate-and-sum form, timed at the preset split (it follows the layer's m and n, not n1)
+    rs_bits, rs_tables = tune_rs(ctx, plan, batch, [l.n1 for l in plan.layers], qp_preset)
+    shapes = [(l.m, l.n, n1, qp, rs) for l, n1, qp, rs in zip(plan.layers, n1s, qps, rs_bits)]
     plan2 = netplan.plan_network(plan.log_n, plan.q, plan.p, plan.alpha, int(np.log2(plan.scale)), shapes)
     N = 1 << plan.log_n
     layers = [ctx.dense_load(l.level, l.m, l.n, l.n1,
                              _residues(plan.q[: l.level + 1] + (plan.p if l.qp else []), N, (l.m,), 300 + i),
-                             _residues(plan.q[: l.level + 1], N, (), 400 + i), l.pt_scale, l.bias_scale, qp=l.qp)
+                             _residues(plan.q[: l.level + 1], N, (), 400 + i), l.pt_scale, l.bias_scale, qp=l.qp,
+                             rs_bits=l.rs_bits)
               for i, l in enumerate(plan2.layers)]
     bbest, rates, lat = tune_batch(ctx, plan2, layers, list(batches), cap_ms)
     res = {"device": device_tag(), "workload": name, "knobs": knobs, "n1": n1s, "qp": qps, "qp_preset": qp_preset,
-           "batch": bbest, "latency_cap_ms": cap_ms,
+           "rs_bits": rs_bits, "batch": bbest, "latency_cap_ms": cap_ms,
            "measurements": {"ntt_ms": ntt_table,
                             "dense_ms": [{f"{k[0]}{'q' if k[1] else ''}": v for k, v in t.items()}
                                          for t in n1_tables],
+                            "rotate_sum_ms": [{str(k): v for k, v in t.items()} for t in rs_tables],
                             "batch_inferences_per_s": {str(k): v for k, v in rates.items()},
                             "batch_latency_ms": {str(k): v for k, v in lat.items()}}}
     os.makedirs(out_dir, exist_ok=True)
@@ -241,7 +280,7 @@ def main():
     ap.add_argument("--out", default=TUNING_DIR)
     args = ap.parse_args()
     res = tune_workload(args.workload, args.batch, args.cap_ms, args.out)
-    print(json.dumps({k: res[k] for k in ("device", "workload", "knobs", "n1", "qp", "qp_preset", "batch")}),
+    print(json.dumps({k: res[k] for k in ("device", "workload", "knobs", "n1", "qp", "qp_preset", "rs_bits", "batch")}),
           flush=True)
 
 

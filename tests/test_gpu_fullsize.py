@@ -30,18 +30,20 @@ def run_network(name, requests, check_bits, tuned_split=True):
     shapes = netplan.tuned_shapes(name, tuned, tuned_split)     # (m, n, n1, lazy ModDown)
     pr = params.preset(name)
     o = ckks.Oracle(pr)
-    steps = ckks.network_steps([s[:3] for s in shapes])
+    rs = [s[4] if len(s) > 4 else 0 for s in shapes]
+    steps = ckks.network_steps([s[:3] for s in shapes], rs)
     print(f"[fullsize] {name}: keygen for {len(steps)} rotation keys, plan {shapes}", flush=True)
     keys = o.keygen(synth.SEED_KEYS, steps)
     Ws, bs = synth.network_weights([s[:3] for s in shapes], c["sigma"])
-    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes], qps=[len(s) > 3 and s[3] for s in shapes])
+    lays = o.prepare_network(Ws, bs, [s[2] for s in shapes], qps=[len(s) > 3 and s[3] for s in shapes], rs_bits=rs)
     npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, c["scale_bits"], shapes)
     ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
     tune.apply_knobs(ctx, tuned)
     B = len(requests)
     ctx.bind(B, npl.max_n1(), npl.max_n2())
     ctx.load_keys(keys.rlk, keys.rot)
-    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale, qp=l.qp) for l in lays]
+    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale, qp=l.qp, rs_bits=l.rs_bits)
+           for l in lays]
     runner = NetworkRunner(ctx, npl, dls, B)
     cts, xs = [], []
     for i, r in enumerate(requests):

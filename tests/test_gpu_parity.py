@@ -256,6 +256,41 @@ def test_dense_64_baby_steps(qp):
         assert np.array_equal(ctx.export_ct(out[i]), o.dense(c, lay, keys).data), i
 
 
+RS_CASES = [(4, 64, 2, False, 2), (4, 64, 2, True, 4), (2, 128, 2, False, 3), (8, 256, 4, True, 3),
+            (4, 64, 2, False, 1), (8, 256, 4, True, 1)]
+
+
+@pytest.fixture(scope="module")
+def setup_rs():
+    pr = small(10)
+    steps = set()
+    for m, n, n1, _, rs in RS_CASES:
+        steps |= set(plan.rotation_steps(m, n, n1, rs)) | set(plan.rotation_steps(m, n, n1))
+    return (pr,) + make_setup(pr, sorted(steps), max_batch=3)
+
+
+@pytest.mark.parametrize("m,n,n1,qp,rs_bits", RS_CASES)
+def test_dense_rotate_sum_hoisted_parity(setup_rs, m, n, n1, qp, rs_bits):
+    """Hoisted rotate-and-sum (HE_DENSE_RS): groups of rs_bits bits, each one
+    ModUp, the group's rotations fused into one extended sum, one ModDown;
+    three ciphertexts batched, against the oracle; rs_bits = 1 also equals
+    the sequential form bit for bit."""
+    pr, o, keys, ctx = setup_rs
+    rng = np.random.default_rng(m + n + n1 + rs_bits)
+    W, b = rng.normal(0, 0.05, (m, n)), rng.normal(0, 0.05, m)
+    cts = [encrypt(o, keys, pr, 70 + i, width=n)[1] for i in range(3)]
+    lay = o.prepare_dense(W, b, n1, cts[0].level, cts[0].scale, qp=qp, rs_bits=rs_bits)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=qp, rs_bits=rs_bits)
+    gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+    out = ctx.eval_dense_batch(gs, d)
+    for i, c in enumerate(cts):
+        got = ctx.export_ct(out[i])
+        assert np.array_equal(got, o.dense(c, lay, keys).data), i
+    if rs_bits == 1:
+        d0 = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=qp)
+        assert np.array_equal(ctx.export_ct(ctx.eval_dense(gs[0], d0)), ctx.export_ct(out[0]))
+
+
 def test_batched_equals_single(setup10):
     pr, o, keys, ctx = setup10
     m, n, n1 = 8, 64, 4
