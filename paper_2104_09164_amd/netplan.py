@@ -19,6 +19,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+import numpy as np
+
 
 @dataclass
 class LayerPlan:
@@ -142,6 +144,30 @@ def plan_network(log_n: int, q, p, alpha: int, scale_bits: int, shapes) -> NetPl
             raise ValueError("modulus chain too short for this network")
     pl.out_level, pl.out_scale = level, s
     return pl
+
+
+def fold_quadratic_activations(weights, biases, acts):
+    """Collapse per-feature quadratic activations a x^2 + b x + c (paper,
+    "Non-convolutional layers": bias, batch normalisation and the polynomial
+    activation become one polynomial per feature) into the adjacent dense
+    layers, so that the encrypted network only squares:
+        a x^2 + b x + c = a (x + d)^2 + e,   d = b / (2a),  e = c - a d^2,
+    d moves into the bias of the layer before, a scales the columns of the
+    next layer's weights and W_next e moves into its bias.  Needs a != 0 in
+    every feature.  Returns new (weights, biases) lists (FP64); the network
+    W_L(... (W_1 x + b_1)^2 ...) + b_L with them equals the original one."""
+    Ws = [np.array(W, dtype=np.float64) for W in weights]
+    bs = [np.array(b, dtype=np.float64) for b in biases]
+    for i, (a, b, c) in enumerate(acts):
+        a, b, c = (np.asarray(v, dtype=np.float64) for v in (a, b, c))
+        if np.any(a == 0):
+            raise ValueError("a quadratic activation with a = 0 cannot be folded into a square")
+        d = b / (2.0 * a)
+        e = c - a * d * d
+        bs[i] = bs[i] + d
+        bs[i + 1] = bs[i + 1] + Ws[i + 1] @ e
+        Ws[i + 1] = Ws[i + 1] * a[None, :]
+    return Ws, bs
 
 
 # Workload presets (ring, primes by bit size, digit size, scale, layer shapes).

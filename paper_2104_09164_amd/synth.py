@@ -32,6 +32,15 @@ def network_weights(layers, sigma: float, seed: int = SEED_WEIGHTS):
     return Ws, bs
 
 
+def activation_coeffs(layers, seed: int = SEED_WEIGHTS + 10):
+    """Per-feature quadratic activations (a, b, c) after every layer but the
+    last, shaped like a trained quadratic stand-in for ReLU on [-1, 1]:
+    a ~ U[0.2, 0.6], b ~ U[0.3, 0.7], c ~ U[0, 0.2] (a bounded away from 0)."""
+    rng = np.random.default_rng(seed)
+    return [(rng.uniform(0.2, 0.6, m), rng.uniform(0.3, 0.7, m), rng.uniform(0.0, 0.2, m))
+            for m, _, _ in layers[:-1]]
+
+
 def uniform_residues(primes, n: int, shape_prefix=(), seed: int = 0) -> np.ndarray:
     """uint64 array shape_prefix + [len(primes)][n], each row uniform in [0, q)."""
     rng = np.random.default_rng(seed)
