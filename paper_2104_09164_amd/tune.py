@@ -33,7 +33,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
-KNOB_SPACE = {"ntt_cols": [16, 32], "ntt_cols_b": [8, 16, 32], "ntt_chunk_mb": [0, 64, 128, 256]}
+KNOB_SPACE = {"ntt_cols": [16, 32], "ntt_cols_b": [8, 16, 32], "ntt_chunk_mb": [0, 32, 64, 128, 256]}
 # The lazy-ModDown form is chosen only when it is at least this much faster.
 LAZY_MARGIN = 1.02
 
@@ -237,6 +237,20 @@ def tune_batch(ctx, plan, layers, batches: list[int], cap_ms: float | None, reps
     return pick_batch(rates, lat, cap_ms), rates, lat
 
 
+def tune_kernel_bench(out_dir: str = TUNING_DIR) -> dict:
+    """The kernel micro-benchmark's ring (N = 2^16, 24 + 8 limbs of 50 bits,
+    64 ciphertexts): NTT launch knobs only (no plan choices)."""
+    from . import he
+    q, p = he.prime_chain(16, [50] * 24, [50] * 8)
+    ctx = he.Context(16, q, p, 8)
+    knobs, ntt_table = tune_ntt(ctx, items=64)
+    res = {"device": device_tag(), "workload": "cfg2", "knobs": knobs, "measurements": {"ntt_ms": ntt_table}}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"{res['device']}_cfg2.json"), "w") as f:
+        json.dump(res, f, indent=1, sort_keys=True)
+    return res
+
+
 def tune_workload(name: str, batch: int, cap_ms: float | None = None, out_dir: str = TUNING_DIR,
                   batches=(1, 4, 8, 16, 32)) -> dict:
     from . import netplan
@@ -274,11 +288,15 @@ def tune_workload(name: str, batch: int, cap_ms: float | None = None, out_dir: s
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["cfg1", "cfg3", "cfg4"])
+    ap.add_argument("workload", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--cap-ms", type=float, default=None)
     ap.add_argument("--out", default=TUNING_DIR)
     args = ap.parse_args()
+    if args.workload == "cfg2":
+        res = tune_kernel_bench(args.out)
+        print(json.dumps({k: res[k] for k in ("device", "workload", "knobs")}), flush=True)
+        return
     res = tune_workload(args.workload, args.batch, args.cap_ms, args.out)
     print(json.dumps({k: res[k] for k in ("device", "workload", "knobs", "n1", "qp", "qp_preset", "rs_bits", "batch")}),
           flush=True)
