@@ -190,6 +190,41 @@ int he_dense_load_ex(he_ctx* ctx, uint32_t level, uint32_t m, uint32_t n, uint32
                      const uint64_t* bias, double pt_scale, double bias_scale, uint32_t flags, void* dev,
                      size_t bytes, he_dense** out);
 
+/* Multi-input linear transform in baby-step/giant-step form: the paper's
+ * multi-channel homomorphic convolution (Methods, "Single-channel homomorphic
+ * convolutions" and the multi-channel equation after it, in the baby-step
+ * strategy of "Algorithmic and cryptographic optimizations": rotate each
+ * input by the kernel offsets, multiply by plaintexts pre-rotated by the
+ * channel offsets, sum, rotate by the channel offsets, sum):
+ *   out[j] = sum_{g < n_giant} rho^{giant[g]}( sum_{i < n_in} sum_{b < n_baby}
+ *                                pt[g][j][i][b] (.) rho^{baby[b]}(in[i]) ),   j < n_out.
+ * baby: rotation amounts (0 = the input itself); giant[0] must be 0, the other
+ * giant amounts non-trivial rotations.  n_in n_baby <= 64, n_giant <= 64.
+ * pts: host uint64[n_giant][n_out][n_in][n_baby][level+1][N], coefficient
+ * form, encoded at pt_scale over q_0..q_level.  dev: caller-owned device
+ * storage >= he_linear_bytes(...): the plaintexts in NTT form, then their
+ * Shoup companions.  *out: host handle (free with he_linear_free).
+ * Synchronous. */
+typedef struct he_linear he_linear;
+size_t he_linear_bytes(const he_ctx* ctx, uint32_t level, uint32_t n_out, uint32_t n_giant, uint32_t n_in,
+                       uint32_t n_baby);
+int he_linear_load(he_ctx* ctx, uint32_t level, uint32_t n_out, uint32_t n_giant, uint32_t n_in, uint32_t n_baby,
+                   const int32_t* baby, const int32_t* giant, const uint64_t* pts, double pt_scale, void* dev,
+                   size_t bytes, he_linear** out);
+int he_linear_free(he_linear* t);
+/* Caller-owned scratch for he_eval_linear: the baby rotations of every input
+ * (he_linear_scratch_bytes(ctx, level, n_in, n_baby) bytes, device). */
+size_t he_linear_scratch_bytes(const he_ctx* ctx, uint32_t level, uint32_t n_in, uint32_t n_baby);
+/* Evaluates the transform on in[0..n_in) (equal level = the plaintexts' level,
+ * equal scale) into out[0..n_out) (scale in.scale * pt_scale; outputs must
+ * not alias inputs).  The workspace bound with he_ctx_bind must have
+ * max_batch >= n_in, n_out and max_n2 >= n_giant (HE_ENOMEM otherwise); keys
+ * for every nonzero rotation amount (HE_ENOKEY).  The baby rotations of all
+ * inputs share one ModUp per input; all giant steps of all outputs form one
+ * step-batched key switch. */
+int he_eval_linear(he_ctx* ctx, const he_ct* in, const he_linear* t, void* scratch, size_t scratch_bytes,
+                   he_ct* out);
+
 /* Ciphertext import/export.  *_import: host coefficient form -> inout->dev
  * (caller sets inout->dev; level and scale are written).  *_export: blocking
  * (synchronises the stream), writes host coefficient form [2][level+1][N].

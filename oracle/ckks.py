@@ -302,6 +302,30 @@ class Oracle:
             raise RuntimeError(f"orc_dense failed ({rc})")
         return Ciphertext(out, a.level, a.scale * layer.pt_scale)
 
+    def linear(self, cts: list, pts: np.ndarray, baby, giant, pt_scale: float, keys: Keys, only=None) -> list:
+        """Multi-input linear transform in baby-step/giant-step form (the
+        multi-channel convolution of oracle/conv.py):
+            out[j] = sum_g rho^{giant[g]}( sum_{i,b} MultPlain(rho^{baby[b]}(cts[i]), pts[g][j][i][b]) ),
+        giant[0] = 0; the sums over g accumulate in increasing g.  only: the
+        output indices to compute (default all)."""
+        n_giant, n_out, n_in, n_baby = pts.shape[:4]
+        rot = [[self.rotate(ct, r, keys) for r in baby] for ct in cts]
+        outs = []
+        for j in (range(n_out) if only is None else only):
+            z = None
+            for g in range(n_giant):
+                s = None
+                for i in range(n_in):
+                    for b in range(n_baby):
+                        p = self.mult_plain(rot[i][b], pts[g, j, i, b], pt_scale)
+                        s = p if s is None else self.add(s, p)
+                if g == 0:
+                    z = s
+                else:
+                    z = self.add(z, self.rotate(s, giant[g], keys))
+            outs.append(z)
+        return outs
+
     # ----------------------------------------------------------- network
     def prepare_dense(self, W: np.ndarray, b: np.ndarray | None, n1: int, level: int, in_scale: float,
                       pt_scale: float | None = None, qp: bool = False, rs_bits: int = 0) -> "DenseLayer":

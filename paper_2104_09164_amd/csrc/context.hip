@@ -213,7 +213,7 @@ thread_local char g_last_error[256] = "";
 static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
     "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner_steps", "moddown_conv", "ks_final", "ks_final_steps",
-    "ks_final_multplain", "ks_final_sum", "ext_multplain", "ks_inner_ext_multplain", "moddown_final", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
+    "ks_final_multplain", "ks_final_sum", "ext_multplain", "ks_inner_ext_multplain", "moddown_final", "multplain_accumulate", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
     "add_plain", "copy_polys", "shoup_companion"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
@@ -445,6 +445,58 @@ int he_dense_load_ex(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t
 int he_dense_load(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
                   const uint64_t* bias, double pt_scale, double bias_scale, void* dev, size_t bytes, he_dense** out) {
   return he_dense_load_ex(c, level, m, n, n1, pt_diag, bias, pt_scale, bias_scale, 0, dev, bytes, out);
+}
+
+size_t he_linear_bytes(const he_ctx* c, uint32_t level, uint32_t n_out, uint32_t n_giant, uint32_t n_in,
+                       uint32_t n_baby) {
+  return c ? 2 * (size_t)n_out * n_giant * n_in * n_baby * (level + 1) * c->N * sizeof(u64) : 0;
+}
+
+int he_linear_load(he_ctx* c, uint32_t level, uint32_t n_out, uint32_t n_giant, uint32_t n_in, uint32_t n_baby,
+                   const int32_t* baby, const int32_t* giant, const uint64_t* pts, double pt_scale, void* dev,
+                   size_t bytes, he_linear** out) {
+  if (!c || !baby || !giant || !pts || !dev || !out) return HE_EINVAL;
+  if (level >= c->nq) return HE_ELEVEL;
+  if (!n_out || !n_giant || !n_in || !n_baby || n_giant > 64 || n_baby > 64 || n_in * n_baby > HE_MAXB ||
+      giant[0] != 0)
+    return HE_EINVAL;
+  if (bytes < he_linear_bytes(c, level, n_out, n_giant, n_in, n_baby)) return HE_ENOMEM;
+  const size_t m = (size_t)n_out * n_giant * n_in * n_baby, per = (size_t)(level + 1) * c->N;
+  u64* d = (u64*)dev;
+  if (hipMemcpyAsync(d, pts, m * per * sizeof(u64), hipMemcpyHostToDevice, c->stream) != hipSuccess) return HE_EDEVICE;
+  for (size_t k0 = 0; k0 < m; k0 += HE_MAXB) {
+    PolyBatch pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.nitems = (u32)std::min<size_t>(HE_MAXB, m - k0);
+    pb.npoly = level + 1;
+    for (u32 b = 0; b < pb.nitems; ++b) pb.src[b] = pb.dst[b] = d + (k0 + b) * per;
+    for (u32 r = 0; r <= level; ++r) pb.prime[r] = (uint8_t)r;
+    int rc = launch_ntt(c, pb, false);
+    if (rc) return rc;
+  }
+  int rc = launch_shoup_companion(c, (u32)m, level + 1, level, d, d + m * per);
+  if (rc) return rc;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
+  he_linear* h = new (std::nothrow) he_linear;
+  if (!h) return HE_ENOMEM;
+  h->ctx = c;
+  h->level = level;
+  h->n_out = n_out;
+  h->n_giant = n_giant;
+  h->n_in = n_in;
+  h->n_baby = n_baby;
+  h->pt_scale = pt_scale;
+  for (u32 b = 0; b < n_baby; ++b) h->baby[b] = baby[b];
+  for (u32 g = 0; g < n_giant; ++g) h->giant[g] = giant[g];
+  h->pts = d;
+  *out = h;
+  return HE_OK;
+}
+
+int he_linear_free(he_linear* t) {
+  if (!t) return HE_EINVAL;
+  delete t;
+  return HE_OK;
 }
 
 int he_dense_free(he_dense* d) {

@@ -49,7 +49,7 @@ struct PolyBatch {
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
   TK_MODUP_CONV, TK_KS_INNER_STEPS, TK_MODDOWN_CONV, TK_KS_FINAL, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM,
-  TK_EXT_MP, TK_KS_EXT_FUSED, TK_MODDOWN_FINAL, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
+  TK_EXT_MP, TK_KS_EXT_FUSED, TK_MODDOWN_FINAL, TK_MP_ACC, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
   TK_COUNT
 };
 const char* trace_name(int kind);
@@ -124,6 +124,14 @@ struct he_dense {
   u32 rs_bits; // rotate-and-sum: 0 sequential, else hoisted groups of this many bits
   u64* pts;    // [m][pl][N], NTT form, then their Shoup companions floor(w 2^64 / q), same shape
   u64* bias;   // [level+1][N], NTT form, or null
+};
+
+struct he_linear {
+  he_ctx* ctx;
+  u32 level, n_out, n_giant, n_in, n_baby;
+  double pt_scale;
+  int32_t baby[64], giant[64];   // rotation amounts (giant[0] = 0)
+  u64* pts;    // [n_giant][n_out][n_in][n_baby][level+1][N], NTT form, then their Shoup companions
 };
 
 // ---------------------------------------------------------------- helpers

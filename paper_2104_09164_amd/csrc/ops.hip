@@ -663,4 +663,86 @@ int he_eval_dense(he_ctx* c, const he_ct* in, const he_dense* d, he_ct* out) {
   return he_eval_dense_batch(c, 1, in, d, out);
 }
 
+size_t he_linear_scratch_bytes(const he_ctx* c, uint32_t level, uint32_t n_in, uint32_t n_baby) {
+  return c ? (size_t)n_in * n_baby * 2 * (level + 1) * c->N * sizeof(u64) : 0;
+}
+
+int he_eval_linear(he_ctx* c, const he_ct* in, const he_linear* t, void* scratch, size_t scratch_bytes,
+                   he_ct* out) {
+  if (!t || t->ctx != c) return HE_EINVAL;
+  const u32 n_in = t->n_in, n_out = t->n_out, NB = t->n_baby, NG = t->n_giant, l = t->level;
+  int rc = check_batch(c, n_in, in, out, n_out);
+  if (rc) return rc;
+  if (in[0].level != l) return HE_ELEVEL;
+  if (n_out > c->ws_batch) return HE_ENOMEM;
+  if (NG > std::max<u32>(c->ws_n2, 1) || (NG > 1 && NG - 1 > giant_group(c->ws_n2))) return HE_ENOMEM;
+  for (u32 j = 0; j < n_out; ++j)
+    for (u32 i = 0; i < n_in; ++i)
+      if (out[j].dev == in[i].dev) return HE_EINVAL;
+  // keys and the rotated copies' storage, checked before anything is enqueued
+  std::vector<int32_t> bsteps;
+  std::vector<u32> bslot(NB, 0xFFFFFFFFu);
+  for (u32 b = 0; b < NB; ++b)
+    if (galois_of(c, t->baby[b]) != 1) {
+      bslot[b] = (u32)bsteps.size();
+      bsteps.push_back(t->baby[b]);
+    }
+  const size_t N = c->N, csz = (size_t)2 * (l + 1) * N;
+  if (!bsteps.empty() && (!scratch || scratch_bytes < (size_t)n_in * bsteps.size() * csz * sizeof(u64)))
+    return HE_ENOMEM;
+  StepKeys sk;
+  std::memset(&sk, 0, sizeof(sk));
+  for (u32 g = 1; g < NG; ++g) {
+    const KeySlot* k = find_rot(c, galois_of(c, t->giant[g]));
+    if (galois_of(c, t->giant[g]) == 1 || !k) return HE_ENOKEY;   // giant[g] must be a real rotation
+    sk.key[g - 1] = k->dev;
+    sk.galois[g - 1] = k->galois;
+    sk.galois_inv[g - 1] = galois_inverse(c, k->galois);
+  }
+  for (int32_t st : bsteps)
+    if (!find_rot(c, galois_of(c, st))) return HE_ENOKEY;
+  const WS w = carve(c);
+  // 1. baby rotations of every input: one hoisted ModUp per input, step-batched key switches
+  std::vector<he_ct> rot(n_in * bsteps.size());
+  for (u32 i = 0; i < n_in; ++i)
+    for (size_t u = 0; u < bsteps.size(); ++u)
+      rot[i * bsteps.size() + u].dev = (u64*)scratch + (i * bsteps.size() + u) * csz;
+  if (!bsteps.empty() &&
+      (rc = he_rotate_hoisted_batch(c, n_in, in, (u32)bsteps.size(), bsteps.data(), rot.data())))
+    return rc;
+  // 2. inner sums s[g][j] = sum_{i, b} pt[g][j][i][b] (.) rho^{baby b}(in i): output o = g n_out + j
+  //    at giant + o csz (the layout of the dense layer's giant region)
+  Items terms;
+  terms.n = n_in * NB;
+  for (u32 i = 0; i < n_in; ++i)
+    for (u32 b = 0; b < NB; ++b)
+      terms.p[i * NB + b] = bslot[b] == 0xFFFFFFFFu ? in[i].dev : rot[i * bsteps.size() + bslot[b]].dev;
+  if ((rc = launch_mp_acc(c, l, terms, NG * n_out, t->pts, w.giant))) return rc;
+  // 3. out[j] = s[0][j] + sum_{g >= 1} rho^{giant g}(s[g][j]): every giant step of every output in
+  //    one step-batched key switch (one ModUp per (g, j)), summed in one epilogue
+  if (NG == 1) {
+    for (u32 j = 0; j < n_out; ++j)
+      if ((rc = copy_ct(c, l, w.giant + (size_t)j * csz, out[j].dev))) return rc;
+  } else {
+    const u32 J = NG - 1;
+    u64* c1base = w.giant + (size_t)n_out * csz + (size_t)(l + 1) * N;
+    if ((rc = modup_strided(c, l, J * n_out, c1base, csz, w))) return rc;
+    OwnMap own;
+    std::memset(&own, 0, sizeof(own));
+    own.base = c1base;
+    own.os = (size_t)n_out * csz;
+    own.ob = csz;
+    if ((rc = ks_steps_inner(c, l, n_out, J, w, own, n_out, sk))) return rc;
+    OutMap om;
+    std::memset(&om, 0, sizeof(om));
+    for (u32 j = 0; j < n_out; ++j) om.ptr[j] = out[j].dev;
+    if ((rc = launch_ks_final_sum(c, l, n_out, J, w.u, w.conv, sk, w.giant, nullptr, om))) return rc;
+  }
+  for (u32 j = 0; j < n_out; ++j) {
+    out[j].level = l;
+    out[j].scale = in[0].scale * t->pt_scale;
+  }
+  return HE_OK;
+}
+
 }  // extern "C"

@@ -643,6 +643,40 @@ __global__ void __launch_bounds__(BS) k_multplain(Items in, const u64* __restric
   }
 }
 
+// Plaintext multiply-accumulate over a list of T ciphertexts (the inner sums
+// of a multi-input linear transform): for output o < n_o,
+//   s[o] = sum_{t < T} pts[o][t] (.) terms.p[t]   (both polynomials),
+// pts = [n_o][T][l+1][N] then companions, s[o] at s + o 2 (l+1) N.  1-D grid
+// over n_o x (N/BS, l+1) tiles: the outputs of a tile share its ciphertext words.
+template <bool LAZY>
+__device__ __forceinline__ void mp_acc_body(const Items& terms, const u64* __restrict__ pts, u64* __restrict__ s,
+                                            const PrimeConst& pk, u32 N, u32 l, u32 n_o, u32 o, u32 k, u32 li) {
+  const u32 T = terms.n;
+  const size_t comp = (size_t)n_o * T * (l + 1) * N;
+  u64 a0 = 0, a1 = 0;
+  for (u32 t = 0; t < T; ++t) {
+    const u64* x = terms.p[t];
+    const size_t po = (((size_t)o * T + t) * (l + 1) + li) * N + k;
+    const u64 pt = pts[po], ps = pts[comp + po];
+    a0 = mp_add<LAZY>(a0, x[(size_t)li * N + k], pt, ps, pk);
+    a1 = mp_add<LAZY>(a1, x[(size_t)(l + 1 + li) * N + k], pt, ps, pk);
+  }
+  u64* out = s + (size_t)o * 2 * (l + 1) * N;
+  out[(size_t)li * N + k] = mp_final<LAZY>(a0, pk);
+  out[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(a1, pk);
+}
+
+__global__ void __launch_bounds__(BS) k_mp_acc(Items terms, const u64* __restrict__ pts, u64* __restrict__ s,
+                                               const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n_o) {
+  const u32 nkb = N / BS;
+  u32 o, tile;
+  xcd_decode(blockIdx.x, n_o, nkb * (l + 1), o, tile);
+  const u32 k = (tile % nkb) * BS + threadIdx.x, li = tile / nkb;
+  const PrimeConst pk = pc[li];
+  if (pk.q < kLazyMP) mp_acc_body<true>(terms, pts, s, pk, N, l, n_o, o, k, li);
+  else mp_acc_body<false>(terms, pts, s, pk, N, l, n_o, o, k, li);
+}
+
 // grid: (N/BS, l+1, B)
 __global__ void __launch_bounds__(BS) k_tensor(Items in, u64* __restrict__ d01, u64* __restrict__ d2,
                                                const PrimeConst* __restrict__ pc, u32 N, u32 l) {
@@ -944,6 +978,16 @@ int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv,
   TraceScope ts(c, TK_MODDOWN_FINAL, ((double)Z * 6.0 + (bias ? 1.0 : 0.0)) * (l + 1) * (8.0 * (double)c->N));
   HE_LAUNCH(ts, k_moddown_final, dim3(c->N / BS, l + 1, Z), dim3(BS), c->stream, y, conv, om, bias, c->d_pc,
             c->d_moddown, c->N, l, c->np, c->nq);
+  return ok();
+}
+
+int launch_mp_acc(he_ctx* c, u32 l, const Items& terms, u32 n_o, const u64* pts, u64* s) {
+  if (!terms.n || terms.n > HE_MAXB || !n_o) return HE_EINVAL;
+  // the T terms (2 polys each) once, plaintexts (value + companion), the outputs
+  TraceScope ts(c, TK_MP_ACC,
+                ((double)terms.n * 2.0 + (double)n_o * terms.n * 2.0 + n_o * 2.0) * (l + 1) * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_mp_acc, dim3(n_o * (c->N / BS) * (l + 1)), dim3(BS), c->stream, terms, pts, s, c->d_pc, c->N, l,
+            n_o);
   return ok();
 }
 

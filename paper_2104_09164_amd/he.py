@@ -74,6 +74,12 @@ def lib() -> C.CDLL:
             "he_dense_load": (C.c_int, [vp, u32, u32, u32, u32, vp, vp, dbl, dbl, vp, sz, C.POINTER(vp)]),
             "he_dense_load_ex": (C.c_int, [vp, u32, u32, u32, u32, vp, vp, dbl, dbl, u32, vp, sz, C.POINTER(vp)]),
             "he_dense_free": (C.c_int, [vp]),
+            "he_linear_bytes": (sz, [vp, u32, u32, u32, u32, u32]),
+            "he_linear_load": (C.c_int, [vp, u32, u32, u32, u32, u32, C.POINTER(i32), C.POINTER(i32), vp, dbl, vp, sz,
+                                         C.POINTER(vp)]),
+            "he_linear_free": (C.c_int, [vp]),
+            "he_linear_scratch_bytes": (sz, [vp, u32, u32, u32]),
+            "he_eval_linear": (C.c_int, [vp, ctp, vp, vp, sz, ctp]),
             "he_ct_import": (C.c_int, [vp, vp, u32, dbl, ctp]),
             "he_ct_export": (C.c_int, [vp, ctp, vp]),
             "he_ct_from_coeff_dev": (C.c_int, [vp, vp, u32, dbl, ctp]),
@@ -108,7 +114,8 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_eval_dense", "he_square", "he_rotate", "he_rotate_hoisted", "he_rescale", "he_add",
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
             "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
-            "he_dense_load_ex")
+            "he_dense_load_ex", "he_linear_bytes", "he_linear_load", "he_linear_free", "he_linear_scratch_bytes",
+            "he_eval_linear")
 
 HE_DENSE_QP = 1
 HE_DENSE_RS_SHIFT = 8
@@ -158,6 +165,20 @@ class Dense:
     def __del__(self):
         try:
             lib().he_dense_free(self.h)
+        except Exception:
+            pass
+
+
+class Linear:
+    def __init__(self, ctx: "Context", handle, buf, level, n_out, n_giant, n_in, n_baby, baby, giant, pt_scale):
+        self.ctx, self.h, self.buf = ctx, handle, buf
+        self.level, self.n_out, self.n_giant, self.n_in, self.n_baby = level, n_out, n_giant, n_in, n_baby
+        self.baby, self.giant, self.pt_scale = list(baby), list(giant), pt_scale
+        self.scratch = None
+
+    def __del__(self):
+        try:
+            lib().he_linear_free(self.h)
         except Exception:
             pass
 
@@ -245,6 +266,34 @@ class Context:
                                       C.c_void_p(b.ctypes.data) if b is not None else None, pt_scale, bias_scale,
                                       flags, C.c_void_p(buf.data_ptr()), nbytes, C.byref(h)), "he_dense_load_ex")
         return Dense(self, h, buf, level, m, n, n1, pt_scale, bias_scale, qp, rs_bits)
+
+    def linear_load(self, level: int, baby, giant, pts: np.ndarray, pt_scale: float) -> Linear:
+        """pts: uint64 [n_giant][n_out][n_in][n_baby][level+1][N] (coefficient form)."""
+        pts = np.ascontiguousarray(pts, dtype=np.uint64)
+        n_giant, n_out, n_in, n_baby = pts.shape[:4]
+        if pts.shape[4:] != (level + 1, self.N) or len(baby) != n_baby or len(giant) != n_giant:
+            raise ValueError(f"plaintexts of shape {pts.shape} for baby {baby}, giant {giant}, level {level}")
+        nbytes = int(lib().he_linear_bytes(self.h, level, n_out, n_giant, n_in, n_baby))
+        buf = self._alloc(nbytes)
+        b = (C.c_int32 * n_baby)(*baby)
+        g = (C.c_int32 * n_giant)(*giant)
+        h = C.c_void_p()
+        _check(lib().he_linear_load(self.h, level, n_out, n_giant, n_in, n_baby, b, g, C.c_void_p(pts.ctypes.data),
+                                    pt_scale, C.c_void_p(buf.data_ptr()), nbytes, C.byref(h)), "he_linear_load")
+        return Linear(self, h, buf, level, n_out, n_giant, n_in, n_baby, baby, giant, pt_scale)
+
+    def eval_linear(self, cts, lt: Linear, outs=None):
+        if len(cts) != lt.n_in:
+            raise ValueError(f"{len(cts)} inputs for a transform of {lt.n_in}")
+        outs = outs or [self.new_ct(lt.level) for _ in range(lt.n_out)]
+        if lt.scratch is None:
+            nb = int(lib().he_linear_scratch_bytes(self.h, lt.level, lt.n_in, lt.n_baby))
+            lt.scratch = self._alloc(max(nb, 256))
+        ia, oa = self._arr(cts), self._arr(outs)
+        _check(lib().he_eval_linear(self.h, ia, lt.h, C.c_void_p(lt.scratch.data_ptr()),
+                                    lt.scratch.numel() * lt.scratch.element_size(), oa), "he_eval_linear")
+        self._sync_meta(outs, oa)
+        return outs
 
     # ------------------------------------------------------ import/export
     def import_ct(self, coeff: np.ndarray, level: int, scale: float) -> Ct:
