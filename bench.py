@@ -1,7 +1,7 @@
 """Benchmark: encrypted inferences/s of the small dense net, batched vs plain.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--large-batch B]
-                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-cpu]
+                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-conv] [--no-cpu]
 
 One step = one batched encrypted inference of B requests through the whole
 small network (N=2^15; dense 1024->128 with 32 baby steps -> rescale ->
@@ -135,6 +135,53 @@ def ntt_leg(reps=10):
             "fwd_ms": f, "inv_ms": i,
             "fwd_gbs": alg_bytes / f / 1e6, "inv_gbs": alg_bytes / i / 1e6,
             "fwd_inv_gbs": 2 * alg_bytes / (f + i) / 1e6, "alg_bytes_per_transform": alg_bytes}
+
+
+def conv_leg(reps=5):
+    """The paper's multi-channel homomorphic convolution at the shape of Table
+    1's 1D-CNN-64 conv2 (output map 240, 64 -> 128 channels, 16 per ciphertext
+    so n_in = 4, n_out = 8, kernel width 3) on the small net's ring (N = 2^15,
+    top level), one request: 8 baby rotations (hoisted per input), 4 x 8 x 16
+    inner sums of 12 products, 8 x 15 giant rotations.  Random residues as
+    keys, plaintexts and ciphertexts (the call sequence is tested bit for bit
+    against the oracle at this shape)."""
+    import torch
+    from paper_2104_09164_amd import he, netplan, tune
+    plan = netplan.preset_plan("cfg3")
+    N, L1 = 1 << plan.log_n, len(plan.q)
+    c, f, L, n_in, n_out = 16, 3, 240, 4, 8
+    dist = 1 << (L - 1).bit_length()
+    baby = [k - f // 2 for k in range(f)]
+    giant = [dist * l for l in range(c)]
+    ctx = he.Context(plan.log_n, plan.q, plan.p, plan.alpha)
+    tune.apply_knobs(ctx, tune.load("cfg3"))
+    ctx.bind(max(n_in, n_out), 1, c)
+    allp = plan.q + plan.p
+    steps = sorted(set(baby + giant) - {0})
+    ctx.load_keys(None, {s: residues(allp, N, (plan.dnum, 2), 700 + i) for i, s in enumerate(steps)})
+    pts = residues(plan.q, N, (c, n_out, n_in, f), 900)
+    lt = ctx.linear_load(plan.L, baby, giant, pts, plan.scale)
+    del pts
+    cts = [ctx.import_ct(residues(plan.q, N, (2,), 950 + i), plan.L, plan.scale) for i in range(n_in)]
+    outs = [ctx.new_ct(plan.L) for _ in range(n_out)]
+    for _ in range(2):
+        ctx.eval_linear(cts, lt, outs)
+    torch.cuda.synchronize()
+    t = time_events(lambda: ctx.eval_linear(cts, lt, outs), reps)
+    ctx.trace_read()
+    ctx.set_knob("trace", 1)
+    ctx.eval_linear(cts, lt, outs)
+    tab = ctx.trace_read()
+    ctx.set_knob("trace", 0)
+    ms = float(np.median(t))
+    return {"workload": (f"1D-CNN-64 conv2 shape: map {L} (slot distance {dist}), 64 -> 128 channels, {c} per "
+                         f"ciphertext (n_in {n_in}, n_out {n_out}), kernel width {f}; N=2^{plan.log_n}, "
+                         f"{L1} limbs, one request"),
+            "ms_per_layer": ms, "rotations": n_in * (f - 1) + n_out * (c - 1), "multplain": c * n_out * n_in * f,
+            "classes": {k: {"launches": v[0], "ms": v[1], "gbs": v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None}
+                        for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])},
+            "paper_context_ms": {"ordinary_conv": 409, "fast_conv_total": 390,
+                                 "note": "Table 1, 1D-CNN-64 conv2, 16-thread Xeon with SEAL; context only"}}
 
 
 def ks_leg(reps=3, items=64, n_steps=32):
@@ -507,6 +554,7 @@ def main():
     ap.add_argument("--no-ntt", action="store_true")
     ap.add_argument("--no-ks", action="store_true")
     ap.add_argument("--no-tuned-split", action="store_true", help="skip the small-net leg with tuned baby steps")
+    ap.add_argument("--no-conv", action="store_true", help="skip the multi-channel convolution leg")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--roofline-only", action="store_true",
@@ -582,6 +630,9 @@ def main():
     if not args.no_ks:
         log("key-switch leg")
         out["key_switch"] = ks_leg()
+    if not args.no_conv:
+        log("convolution leg")
+        out["conv"] = conv_leg()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         # weighted by the operation counts of the paper's evaluation order (one
