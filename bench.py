@@ -137,6 +137,41 @@ def ntt_leg(reps=10):
             "fwd_inv_gbs": 2 * alg_bytes / (f + i) / 1e6, "alg_bytes_per_transform": alg_bytes}
 
 
+def fast_conv_leg(ctx, plan, reps):
+    """The fast convolution (merge-and-conquer) at Table 1's 1D-CNN-64 conv3
+    shape: 8 punctured inputs (pooled maps of 120 at stride 4, slot distance
+    512, 16 channels each), load number 4: two merges of 4 ciphertexts, the
+    multi-channel convolution of the 2 merged ciphertexts into 16 outputs,
+    rotate-and-sum by 2 and 1, rescales; one request, random residues."""
+    import torch
+    from paper_2104_09164_amd.conv import FastConv
+    N = 1 << plan.log_n
+    c, f, dist, nP, n_in, n_out = 16, 3, 512, 4, 8, 16
+    pre_g = [-p for p in range(nP)]
+    baby = [nP * (k - f // 2) for k in range(f)]
+    giant = [dist * l for l in range(c)]
+    post = [2, 1]
+    allp = plan.q + plan.p
+    steps = sorted(set(pre_g + baby + giant + post) - {0})
+    ctx.bind(n_out, 1, c)
+    ctx.load_keys(None, {s: residues(allp, N, (plan.dnum, 2), 800 + i) for i, s in enumerate(steps)})
+    pre = residues(plan.q, N, (nP, 1, nP, 1), 1900)
+    pts = residues(plan.q[:-1], N, (c, n_out, n_in // nP, f), 1901)
+    fc = FastConv(ctx, plan.L, nP, pre_g, pre, baby, giant, pts, post, plan.scale)
+    del pre, pts
+    cts = [ctx.import_ct(residues(plan.q, N, (2,), 1950 + i), plan.L, plan.scale) for i in range(n_in)]
+    for _ in range(2):
+        fc.run(cts)
+    torch.cuda.synchronize()
+    t = time_events(lambda: fc.run(cts), reps)
+    return {"workload": (f"1D-CNN-64 conv3 shape, fast convolution: 8 punctured inputs (map 120 at stride {nP}, "
+                         f"slot distance {dist}, {c} channels each), load number {nP}, 2 merged -> {n_out} outputs, "
+                         f"kernel width {f}; N=2^{plan.log_n}, one request"),
+            "ms_per_layer": float(np.median(t)),
+            "paper_context_ms": {"ordinary_conv": 422, "fast_conv_total": 242,
+                                 "note": "Table 1, 1D-CNN-64 conv3, 16-thread Xeon with SEAL; context only"}}
+
+
 def conv_leg(reps=5):
     """The paper's multi-channel homomorphic convolution at the shape of Table
     1's 1D-CNN-64 conv2 (output map 240, 64 -> 128 channels, 16 per ciphertext
@@ -174,7 +209,11 @@ def conv_leg(reps=5):
     tab = ctx.trace_read()
     ctx.set_knob("trace", 0)
     ms = float(np.median(t))
-    return {"workload": (f"1D-CNN-64 conv2 shape: map {L} (slot distance {dist}), 64 -> 128 channels, {c} per "
+    del lt, cts, outs
+    torch.cuda.synchronize()
+    fast = fast_conv_leg(ctx, plan, reps)
+    return {"fast_conv": fast,
+            "workload": (f"1D-CNN-64 conv2 shape: map {L} (slot distance {dist}), 64 -> 128 channels, {c} per "
                          f"ciphertext (n_in {n_in}, n_out {n_out}), kernel width {f}; N=2^{plan.log_n}, "
                          f"{L1} limbs, one request"),
             "ms_per_layer": ms, "rotations": n_in * (f - 1) + n_out * (c - 1), "multplain": c * n_out * n_in * f,
