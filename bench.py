@@ -153,7 +153,8 @@ def fast_conv_leg(ctx, plan, reps):
     post = [2, 1]
     allp = plan.q + plan.p
     steps = sorted(set(pre_g + baby + giant + post) - {0})
-    ctx.bind(n_out, 1, c)
+    R = 2
+    ctx.bind(R * max(n_in, n_out), 1, c)
     ctx.load_keys(None, {s: residues(allp, N, (plan.dnum, 2), 800 + i) for i, s in enumerate(steps)})
     pre = residues(plan.q, N, (nP, 1, nP, 1), 1900)
     pts = residues(plan.q[:-1], N, (c, n_out, n_in // nP, f), 1901)
@@ -164,7 +165,12 @@ def fast_conv_leg(ctx, plan, reps):
         fc.run(cts)
     torch.cuda.synchronize()
     t = time_events(lambda: fc.run(cts), reps)
-    return {"workload": (f"1D-CNN-64 conv3 shape, fast convolution: 8 punctured inputs (map 120 at stride {nP}, "
+    cts_b = cts + [ctx.import_ct(residues(plan.q, N, (2,), 1970 + i), plan.L, plan.scale) for i in range(n_in)]
+    fc.run(cts_b)
+    torch.cuda.synchronize()
+    tb = float(np.median(time_events(lambda: fc.run(cts_b), reps)))
+    return {"batched": {"requests": R, "ms_per_call": tb, "ms_per_request": tb / R},
+            "workload": (f"1D-CNN-64 conv3 shape, fast convolution: 8 punctured inputs (map 120 at stride {nP}, "
                          f"slot distance {dist}, {c} channels each), load number {nP}, 2 merged -> {n_out} outputs, "
                          f"kernel width {f}; N=2^{plan.log_n}, one request"),
             "ms_per_layer": float(np.median(t)),
@@ -188,9 +194,10 @@ def conv_leg(reps=5):
     dist = 1 << (L - 1).bit_length()
     baby = [k - f // 2 for k in range(f)]
     giant = [dist * l for l in range(c)]
+    R = 4                                      # requests per batched call
     ctx = he.Context(plan.log_n, plan.q, plan.p, plan.alpha)
     tune.apply_knobs(ctx, tune.load("cfg3"))
-    ctx.bind(max(n_in, n_out), 1, c)
+    ctx.bind(R * max(n_in, n_out), 1, c)
     allp = plan.q + plan.p
     steps = sorted(set(baby + giant) - {0})
     ctx.load_keys(None, {s: residues(allp, N, (plan.dnum, 2), 700 + i) for i, s in enumerate(steps)})
@@ -209,10 +216,16 @@ def conv_leg(reps=5):
     tab = ctx.trace_read()
     ctx.set_knob("trace", 0)
     ms = float(np.median(t))
-    del lt, cts, outs
+    # R requests in one call: the plaintexts are read once per batch
+    cts_b = [ctx.import_ct(residues(plan.q, N, (2,), 960 + i), plan.L, plan.scale) for i in range(R * n_in)]
+    outs_b = [ctx.new_ct(plan.L) for _ in range(R * n_out)]
+    ctx.eval_linear_batch(cts_b, lt, outs_b)
+    torch.cuda.synchronize()
+    tb = float(np.median(time_events(lambda: ctx.eval_linear_batch(cts_b, lt, outs_b), reps)))
+    del lt, cts, outs, cts_b, outs_b
     torch.cuda.synchronize()
     fast = fast_conv_leg(ctx, plan, reps)
-    return {"fast_conv": fast,
+    return {"fast_conv": fast, "batched": {"requests": R, "ms_per_call": tb, "ms_per_request": tb / R},
             "workload": (f"1D-CNN-64 conv2 shape: map {L} (slot distance {dist}), 64 -> 128 channels, {c} per "
                          f"ciphertext (n_in {n_in}, n_out {n_out}), kernel width {f}; N=2^{plan.log_n}, "
                          f"{L1} limbs, one request"),

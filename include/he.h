@@ -212,18 +212,26 @@ int he_linear_load(he_ctx* ctx, uint32_t level, uint32_t n_out, uint32_t n_giant
                    const int32_t* baby, const int32_t* giant, const uint64_t* pts, double pt_scale, void* dev,
                    size_t bytes, he_linear** out);
 int he_linear_free(he_linear* t);
-/* Caller-owned scratch for he_eval_linear: the baby rotations of every input
- * (he_linear_scratch_bytes(ctx, level, n_in, n_baby) bytes, device). */
+/* Caller-owned scratch for he_eval_linear, per request: every input under
+ * every baby rotation (he_linear_scratch_bytes(ctx, level, n_in, n_baby)
+ * bytes, device). */
 size_t he_linear_scratch_bytes(const he_ctx* ctx, uint32_t level, uint32_t n_in, uint32_t n_baby);
 /* Evaluates the transform on in[0..n_in) (equal level = the plaintexts' level,
  * equal scale) into out[0..n_out) (scale in.scale * pt_scale; outputs must
- * not alias inputs).  The workspace bound with he_ctx_bind must have
+ * not alias inputs).  scratch holds every term (the rotated and the unrotated
+ * inputs).  The workspace bound with he_ctx_bind must have
  * max_batch >= n_in, n_out and max_n2 >= n_giant (HE_ENOMEM otherwise); keys
  * for every nonzero rotation amount (HE_ENOKEY).  The baby rotations of all
  * inputs share one ModUp per input; all giant steps of all outputs form one
  * step-batched key switch. */
 int he_eval_linear(he_ctx* ctx, const he_ct* in, const he_linear* t, void* scratch, size_t scratch_bytes,
                    he_ct* out);
+/* The same for n_req requests sharing the plaintexts (read once per batch):
+ * in[r n_in + i], out[r n_out + j]; scratch >= n_req he_linear_scratch_bytes;
+ * n_req n_in and n_req n_out <= the bound max_batch.  Each output equals its
+ * single-request evaluation bit for bit. */
+int he_eval_linear_batch(he_ctx* ctx, uint32_t n_req, const he_ct* in, const he_linear* t, void* scratch,
+                         size_t scratch_bytes, he_ct* out);
 
 /* Ciphertext import/export.  *_import: host coefficient form -> inout->dev
  * (caller sets inout->dev; level and scale are written).  *_export: blocking

@@ -11,7 +11,9 @@ runs, on the device:
         giant rotations);
   (iii) post: rotate-and-sum by n_P/2, ..., 1 and a rescale.
 The plaintexts (masks, pre-rotated filter weights) come encoded from the model
-owner, in coefficient form, as for he_linear_load.
+owner, in coefficient form, as for he_linear_load.  For R requests per call
+the context's workspace must be bound with max_batch >= R n_in and R n_out
+and max_n2 >= max(n_P, channels per ciphertext).
 """
 from __future__ import annotations
 
@@ -25,15 +27,17 @@ class FastConv:
         self.merged = []
 
     def run(self, cts):
+        """cts: R x n_in punctured inputs (request-major); returns R x n_out
+        outputs.  Every step runs batched over the requests (plaintexts read
+        once per batch)."""
         ctx, nP = self.ctx, self.nP
-        if len(cts) % nP:
-            raise ValueError(f"{len(cts)} inputs for groups of {nP}")
-        self.merged = [ctx.rescale(ctx.eval_linear(cts[a * nP:(a + 1) * nP], self.pre)[0])
-                       for a in range(len(cts) // nP)]
-        outs = ctx.eval_linear(self.merged, self.conv)
-        res = []
-        for z in outs:
-            for t in self.post:
-                z = ctx.add(z, ctx.rotate(z, t))
-            res.append(ctx.rescale(z))
-        return res
+        n_in = self.conv.n_in * nP
+        if len(cts) % n_in:
+            raise ValueError(f"{len(cts)} inputs for layers of {n_in}")
+        # groups of nP consecutive inputs are independent requests of the merge transform
+        self.merged = ctx.rescale_batch(ctx.eval_linear_batch(list(cts), self.pre))
+        z = ctx.eval_linear_batch(self.merged, self.conv)
+        for t in self.post:
+            rz = ctx.rotate_hoisted_batch(z, [t])
+            z = [ctx.add(a, b) for a, b in zip(z, rz)]
+        return ctx.rescale_batch(z)

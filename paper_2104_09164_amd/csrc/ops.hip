@@ -667,19 +667,23 @@ size_t he_linear_scratch_bytes(const he_ctx* c, uint32_t level, uint32_t n_in, u
   return c ? (size_t)n_in * n_baby * 2 * (level + 1) * c->N * sizeof(u64) : 0;
 }
 
-int he_eval_linear(he_ctx* c, const he_ct* in, const he_linear* t, void* scratch, size_t scratch_bytes,
-                   he_ct* out) {
-  if (!t || t->ctx != c) return HE_EINVAL;
+int he_eval_linear_batch(he_ctx* c, uint32_t n_req, const he_ct* in, const he_linear* t, void* scratch,
+                         size_t scratch_bytes, he_ct* out) {
+  if (!t || t->ctx != c || n_req == 0) return HE_EINVAL;
   const u32 n_in = t->n_in, n_out = t->n_out, NB = t->n_baby, NG = t->n_giant, l = t->level;
-  int rc = check_batch(c, n_in, in, out, n_out);
+  const u32 I = n_req * n_in, M = n_req * n_out, T = n_in * NB;
+  if (I > HE_MAXB || M > HE_MAXB) return HE_ENOMEM;
+  int rc = check_batch(c, I, in, out, M);
   if (rc) return rc;
   if (in[0].level != l) return HE_ELEVEL;
-  if (n_out > c->ws_batch) return HE_ENOMEM;
+  if (M > c->ws_batch) return HE_ENOMEM;
   if (NG > std::max<u32>(c->ws_n2, 1) || (NG > 1 && NG - 1 > giant_group(c->ws_n2))) return HE_ENOMEM;
-  for (u32 j = 0; j < n_out; ++j)
-    for (u32 i = 0; i < n_in; ++i)
+  for (u32 j = 0; j < M; ++j)
+    for (u32 i = 0; i < I; ++i)
       if (out[j].dev == in[i].dev) return HE_EINVAL;
-  // keys and the rotated copies' storage, checked before anything is enqueued
+  const size_t N = c->N, csz = (size_t)2 * (l + 1) * N;
+  if (!scratch || scratch_bytes < (size_t)I * NB * csz * sizeof(u64)) return HE_ENOMEM;
+  // keys, checked before anything is enqueued
   std::vector<int32_t> bsteps;
   std::vector<u32> bslot(NB, 0xFFFFFFFFu);
   for (u32 b = 0; b < NB; ++b)
@@ -687,9 +691,6 @@ int he_eval_linear(he_ctx* c, const he_ct* in, const he_linear* t, void* scratch
       bslot[b] = (u32)bsteps.size();
       bsteps.push_back(t->baby[b]);
     }
-  const size_t N = c->N, csz = (size_t)2 * (l + 1) * N;
-  if (!bsteps.empty() && (!scratch || scratch_bytes < (size_t)n_in * bsteps.size() * csz * sizeof(u64)))
-    return HE_ENOMEM;
   StepKeys sk;
   std::memset(&sk, 0, sizeof(sk));
   for (u32 g = 1; g < NG; ++g) {
@@ -702,47 +703,52 @@ int he_eval_linear(he_ctx* c, const he_ct* in, const he_linear* t, void* scratch
   for (int32_t st : bsteps)
     if (!find_rot(c, galois_of(c, st))) return HE_ENOKEY;
   const WS w = carve(c);
-  // 1. baby rotations of every input: one hoisted ModUp per input, step-batched key switches
-  std::vector<he_ct> rot(n_in * bsteps.size());
-  for (u32 i = 0; i < n_in; ++i)
-    for (size_t u = 0; u < bsteps.size(); ++u)
-      rot[i * bsteps.size() + u].dev = (u64*)scratch + (i * bsteps.size() + u) * csz;
-  if (!bsteps.empty() &&
-      (rc = he_rotate_hoisted_batch(c, n_in, in, (u32)bsteps.size(), bsteps.data(), rot.data())))
-    return rc;
-  // 2. inner sums s[g][j] = sum_{i, b} pt[g][j][i][b] (.) rho^{baby b}(in i): output o = g n_out + j
-  //    at giant + o csz (the layout of the dense layer's giant region)
-  Items terms;
-  terms.n = n_in * NB;
-  for (u32 i = 0; i < n_in; ++i)
+  u64* x = (u64*)scratch;   // term (item, b) of input item = r n_in + i at x + (item NB + b) csz
+  // 1. baby rotations of every input (one hoisted ModUp per input, step-batched key switches);
+  //    the unrotated terms are copied next to them
+  if (!bsteps.empty()) {
+    std::vector<he_ct> rot(I * bsteps.size());
+    for (u32 it = 0; it < I; ++it)
+      for (u32 b = 0; b < NB; ++b)
+        if (bslot[b] != 0xFFFFFFFFu) rot[it * bsteps.size() + bslot[b]].dev = x + ((size_t)it * NB + b) * csz;
+    if ((rc = he_rotate_hoisted_batch(c, I, in, (u32)bsteps.size(), bsteps.data(), rot.data()))) return rc;
+  }
+  for (u32 it = 0; it < I; ++it)
     for (u32 b = 0; b < NB; ++b)
-      terms.p[i * NB + b] = bslot[b] == 0xFFFFFFFFu ? in[i].dev : rot[i * bsteps.size() + bslot[b]].dev;
-  if ((rc = launch_mp_acc(c, l, terms, NG * n_out, t->pts, w.giant))) return rc;
-  // 3. out[j] = s[0][j] + sum_{g >= 1} rho^{giant g}(s[g][j]): every giant step of every output in
-  //    one step-batched key switch (one ModUp per (g, j)), summed in one epilogue
+      if (bslot[b] == 0xFFFFFFFFu && (rc = copy_ct(c, l, in[it].dev, x + ((size_t)it * NB + b) * csz))) return rc;
+  // 2. inner sums s[g][r n_out + j] = sum_{i, b} pt[g][j][i][b] (.) rho^{baby b}(in[r n_in + i]),
+  //    at giant + (g M + r n_out + j) csz (the layout of the dense layer's giant region)
+  if ((rc = launch_mp_acc(c, l, n_req, T, n_out, NG, x, t->pts, w.giant))) return rc;
+  // 3. out[m] = s[0][m] + sum_{g >= 1} rho^{giant g}(s[g][m]): every giant step of every output in
+  //    one step-batched key switch (one ModUp per (g, m)), summed in one epilogue
   if (NG == 1) {
-    for (u32 j = 0; j < n_out; ++j)
-      if ((rc = copy_ct(c, l, w.giant + (size_t)j * csz, out[j].dev))) return rc;
+    for (u32 m = 0; m < M; ++m)
+      if ((rc = copy_ct(c, l, w.giant + (size_t)m * csz, out[m].dev))) return rc;
   } else {
     const u32 J = NG - 1;
-    u64* c1base = w.giant + (size_t)n_out * csz + (size_t)(l + 1) * N;
-    if ((rc = modup_strided(c, l, J * n_out, c1base, csz, w))) return rc;
+    u64* c1base = w.giant + (size_t)M * csz + (size_t)(l + 1) * N;
+    if ((rc = modup_strided(c, l, J * M, c1base, csz, w))) return rc;
     OwnMap own;
     std::memset(&own, 0, sizeof(own));
     own.base = c1base;
-    own.os = (size_t)n_out * csz;
+    own.os = (size_t)M * csz;
     own.ob = csz;
-    if ((rc = ks_steps_inner(c, l, n_out, J, w, own, n_out, sk))) return rc;
+    if ((rc = ks_steps_inner(c, l, M, J, w, own, M, sk))) return rc;
     OutMap om;
     std::memset(&om, 0, sizeof(om));
-    for (u32 j = 0; j < n_out; ++j) om.ptr[j] = out[j].dev;
-    if ((rc = launch_ks_final_sum(c, l, n_out, J, w.u, w.conv, sk, w.giant, nullptr, om))) return rc;
+    for (u32 m = 0; m < M; ++m) om.ptr[m] = out[m].dev;
+    if ((rc = launch_ks_final_sum(c, l, M, J, w.u, w.conv, sk, w.giant, nullptr, om))) return rc;
   }
-  for (u32 j = 0; j < n_out; ++j) {
-    out[j].level = l;
-    out[j].scale = in[0].scale * t->pt_scale;
+  for (u32 m = 0; m < M; ++m) {
+    out[m].level = l;
+    out[m].scale = in[0].scale * t->pt_scale;
   }
   return HE_OK;
+}
+
+int he_eval_linear(he_ctx* c, const he_ct* in, const he_linear* t, void* scratch, size_t scratch_bytes,
+                   he_ct* out) {
+  return he_eval_linear_batch(c, 1, in, t, scratch, scratch_bytes, out);
 }
 
 }  // extern "C"

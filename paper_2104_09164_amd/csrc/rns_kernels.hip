@@ -643,38 +643,58 @@ __global__ void __launch_bounds__(BS) k_multplain(Items in, const u64* __restric
   }
 }
 
-// Plaintext multiply-accumulate over a list of T ciphertexts (the inner sums
-// of a multi-input linear transform): for output o < n_o,
-//   s[o] = sum_{t < T} pts[o][t] (.) terms.p[t]   (both polynomials),
-// pts = [n_o][T][l+1][N] then companions, s[o] at s + o 2 (l+1) N.  1-D grid
-// over n_o x (N/BS, l+1) tiles: the outputs of a tile share its ciphertext words.
+// Plaintext multiply-accumulate for R requests over T ciphertext terms each
+// (the inner sums of a multi-input linear transform): term t of request r at
+// x + (r T + t) csz; for output o = g n_out + j < NG n_out,
+//   s(r, o) = sum_{t < T} pts[o][t] (.) term(r, t)   (both polynomials),
+// written at s + (g R n_out + r n_out + j) csz (giant-major, the layout the
+// step-batched giant key switch reads).  pts = [NG n_out][T][l+1][N] then
+// companions.  Each thread keeps RC requests' sums, so a plaintext word is
+// loaded once per RC requests.  1-D grid over n_o x (N/BS, l+1) tiles.
+constexpr int RC = 8;
 template <bool LAZY>
-__device__ __forceinline__ void mp_acc_body(const Items& terms, const u64* __restrict__ pts, u64* __restrict__ s,
-                                            const PrimeConst& pk, u32 N, u32 l, u32 n_o, u32 o, u32 k, u32 li) {
-  const u32 T = terms.n;
+__device__ __forceinline__ void mp_acc_body(const u64* __restrict__ x, const u64* __restrict__ pts,
+                                            u64* __restrict__ s, const PrimeConst& pk, u32 N, u32 l, u32 R, u32 T,
+                                            u32 n_out, u32 n_o, u32 o, u32 k, u32 li) {
+  const size_t csz = (size_t)2 * (l + 1) * N;
   const size_t comp = (size_t)n_o * T * (l + 1) * N;
-  u64 a0 = 0, a1 = 0;
-  for (u32 t = 0; t < T; ++t) {
-    const u64* x = terms.p[t];
-    const size_t po = (((size_t)o * T + t) * (l + 1) + li) * N + k;
-    const u64 pt = pts[po], ps = pts[comp + po];
-    a0 = mp_add<LAZY>(a0, x[(size_t)li * N + k], pt, ps, pk);
-    a1 = mp_add<LAZY>(a1, x[(size_t)(l + 1 + li) * N + k], pt, ps, pk);
+  const u32 g = o / n_out, j = o % n_out;
+  for (u32 r0 = 0; r0 < R; r0 += RC) {
+    const u32 rn = min((u32)RC, R - r0);
+    u64 a0[RC], a1[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) a0[r] = a1[r] = 0;
+    for (u32 t = 0; t < T; ++t) {
+      const size_t po = (((size_t)o * T + t) * (l + 1) + li) * N + k;
+      const u64 pt = pts[po], ps = pts[comp + po];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        if ((u32)r >= rn) break;
+        const u64* xt = x + ((size_t)(r0 + r) * T + t) * csz;
+        a0[r] = mp_add<LAZY>(a0[r], xt[(size_t)li * N + k], pt, ps, pk);
+        a1[r] = mp_add<LAZY>(a1[r], xt[(size_t)(l + 1 + li) * N + k], pt, ps, pk);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      if ((u32)r >= rn) break;
+      u64* out = s + ((size_t)g * R * n_out + (size_t)(r0 + r) * n_out + j) * csz;
+      out[(size_t)li * N + k] = mp_final<LAZY>(a0[r], pk);
+      out[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(a1[r], pk);
+    }
   }
-  u64* out = s + (size_t)o * 2 * (l + 1) * N;
-  out[(size_t)li * N + k] = mp_final<LAZY>(a0, pk);
-  out[(size_t)(l + 1 + li) * N + k] = mp_final<LAZY>(a1, pk);
 }
 
-__global__ void __launch_bounds__(BS) k_mp_acc(Items terms, const u64* __restrict__ pts, u64* __restrict__ s,
-                                               const PrimeConst* __restrict__ pc, u32 N, u32 l, u32 n_o) {
+__global__ void __launch_bounds__(BS) k_mp_acc(const u64* __restrict__ x, const u64* __restrict__ pts,
+                                               u64* __restrict__ s, const PrimeConst* __restrict__ pc, u32 N, u32 l,
+                                               u32 R, u32 T, u32 n_out, u32 n_o) {
   const u32 nkb = N / BS;
   u32 o, tile;
   xcd_decode(blockIdx.x, n_o, nkb * (l + 1), o, tile);
   const u32 k = (tile % nkb) * BS + threadIdx.x, li = tile / nkb;
   const PrimeConst pk = pc[li];
-  if (pk.q < kLazyMP) mp_acc_body<true>(terms, pts, s, pk, N, l, n_o, o, k, li);
-  else mp_acc_body<false>(terms, pts, s, pk, N, l, n_o, o, k, li);
+  if (pk.q < kLazyMP) mp_acc_body<true>(x, pts, s, pk, N, l, R, T, n_out, n_o, o, k, li);
+  else mp_acc_body<false>(x, pts, s, pk, N, l, R, T, n_out, n_o, o, k, li);
 }
 
 // grid: (N/BS, l+1, B)
@@ -981,13 +1001,14 @@ int launch_moddown_final(he_ctx* c, u32 l, u32 Z, const u64* y, const u64* conv,
   return ok();
 }
 
-int launch_mp_acc(he_ctx* c, u32 l, const Items& terms, u32 n_o, const u64* pts, u64* s) {
-  if (!terms.n || terms.n > HE_MAXB || !n_o) return HE_EINVAL;
-  // the T terms (2 polys each) once, plaintexts (value + companion), the outputs
+int launch_mp_acc(he_ctx* c, u32 l, u32 R, u32 T, u32 n_out, u32 NG, const u64* x, const u64* pts, u64* s) {
+  if (!R || !T || T > 64 || !n_out || !NG) return HE_EINVAL;
+  const u32 n_o = NG * n_out;
+  // every term of every request once, plaintexts (value + companion) once, the sums
   TraceScope ts(c, TK_MP_ACC,
-                ((double)terms.n * 2.0 + (double)n_o * terms.n * 2.0 + n_o * 2.0) * (l + 1) * (8.0 * (double)c->N));
-  HE_LAUNCH(ts, k_mp_acc, dim3(n_o * (c->N / BS) * (l + 1)), dim3(BS), c->stream, terms, pts, s, c->d_pc, c->N, l,
-            n_o);
+                ((double)R * T * 2.0 + (double)n_o * T * 2.0 + (double)R * n_o * 2.0) * (l + 1) * (8.0 * (double)c->N));
+  HE_LAUNCH(ts, k_mp_acc, dim3(n_o * (c->N / BS) * (l + 1)), dim3(BS), c->stream, x, pts, s, c->d_pc, c->N, l, R, T,
+            n_out, n_o);
   return ok();
 }
 

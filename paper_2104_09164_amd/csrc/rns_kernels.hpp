@@ -115,10 +115,12 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
                         const StepKeys& keys, const Items& in, const u64* pts, u64* sqp);
 
 
-// Inner sums of a multi-input linear transform: s[o] = sum_{t < terms.n}
-// pts[o][t] (.) terms.p[t] for o < n_o (both polynomials), pts = [n_o][T][l+1][N]
-// then companions; s[o] at s + o 2 (l+1) N.  T = terms.n <= HE_MAXB.
-int launch_mp_acc(he_ctx* c, u32 l, const Items& terms, u32 n_o, const u64* pts, u64* s);
+// Inner sums of a multi-input linear transform for R requests: term t < T of
+// request r at x + (r T + t) csz; for o = g n_out + j < NG n_out,
+// s(r, o) = sum_t pts[o][t] (.) term(r, t) (both polynomials) at
+// s + (g R n_out + r n_out + j) csz.  pts = [NG n_out][T][l+1][N] then
+// companions.  T <= 64.
+int launch_mp_acc(he_ctx* c, u32 l, u32 R, u32 T, u32 n_out, u32 NG, const u64* x, const u64* pts, u64* s);
 
 // comp[i][r][k] = floor(pts[i][r][k] 2^64 / q) for m arrays of nlimbs limbs,
 // limb r over prime r for r <= l, else p_{r-l-1} (the Shoup companions of

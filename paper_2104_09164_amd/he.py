@@ -80,6 +80,7 @@ def lib() -> C.CDLL:
             "he_linear_free": (C.c_int, [vp]),
             "he_linear_scratch_bytes": (sz, [vp, u32, u32, u32]),
             "he_eval_linear": (C.c_int, [vp, ctp, vp, vp, sz, ctp]),
+            "he_eval_linear_batch": (C.c_int, [vp, u32, ctp, vp, vp, sz, ctp]),
             "he_ct_import": (C.c_int, [vp, vp, u32, dbl, ctp]),
             "he_ct_export": (C.c_int, [vp, ctp, vp]),
             "he_ct_from_coeff_dev": (C.c_int, [vp, vp, u32, dbl, ctp]),
@@ -115,7 +116,7 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
             "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
             "he_dense_load_ex", "he_linear_bytes", "he_linear_load", "he_linear_free", "he_linear_scratch_bytes",
-            "he_eval_linear")
+            "he_eval_linear", "he_eval_linear_batch")
 
 HE_DENSE_QP = 1
 HE_DENSE_RS_SHIFT = 8
@@ -283,15 +284,21 @@ class Context:
         return Linear(self, h, buf, level, n_out, n_giant, n_in, n_baby, baby, giant, pt_scale)
 
     def eval_linear(self, cts, lt: Linear, outs=None):
-        if len(cts) != lt.n_in:
+        """One request: cts = its n_in inputs; returns its n_out outputs."""
+        return self.eval_linear_batch(cts, lt, outs)
+
+    def eval_linear_batch(self, cts, lt: Linear, outs=None):
+        """R requests: cts = R x n_in inputs (request-major); returns R x n_out outputs."""
+        if len(cts) % lt.n_in:
             raise ValueError(f"{len(cts)} inputs for a transform of {lt.n_in}")
-        outs = outs or [self.new_ct(lt.level) for _ in range(lt.n_out)]
-        if lt.scratch is None:
-            nb = int(lib().he_linear_scratch_bytes(self.h, lt.level, lt.n_in, lt.n_baby))
-            lt.scratch = self._alloc(max(nb, 256))
+        R = len(cts) // lt.n_in
+        outs = outs or [self.new_ct(lt.level) for _ in range(R * lt.n_out)]
+        nb = R * int(lib().he_linear_scratch_bytes(self.h, lt.level, lt.n_in, lt.n_baby))
+        if lt.scratch is None or lt.scratch.numel() * lt.scratch.element_size() < nb:
+            lt.scratch = self._alloc(nb)
         ia, oa = self._arr(cts), self._arr(outs)
-        _check(lib().he_eval_linear(self.h, ia, lt.h, C.c_void_p(lt.scratch.data_ptr()),
-                                    lt.scratch.numel() * lt.scratch.element_size(), oa), "he_eval_linear")
+        _check(lib().he_eval_linear_batch(self.h, R, ia, lt.h, C.c_void_p(lt.scratch.data_ptr()),
+                                          lt.scratch.numel() * lt.scratch.element_size(), oa), "he_eval_linear_batch")
         self._sync_meta(outs, oa)
         return outs
 

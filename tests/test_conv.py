@@ -81,6 +81,16 @@ def test_conv_gpu_parity_small():
     # a second call (rotation scratch reused) gives the same words
     again = ctx.eval_linear(gs, lt)
     assert np.array_equal(ctx.export_ct(again[1]), want[1].data)
+    # two requests batched over the same plaintexts: each equals its single evaluation
+    cts2 = [o.encrypt(v, keys.pk, 70 + i) for i, v in enumerate(conv.pack(X[::-1].copy(), c, dist, pr.slots))]
+    gs2 = [ctx.import_ct(ct.data, ct.level, ct.scale) for ct in cts2]
+    ctx.bind(2 * max(n_in, n_out), 1, len(giant))
+    both = ctx.eval_linear_batch(gs + gs2, lt)
+    single2 = ctx.eval_linear(gs2, lt)
+    for j in range(n_out):
+        assert np.array_equal(ctx.export_ct(both[j]), want[j].data)
+        assert np.array_equal(ctx.export_ct(both[n_out + j]), ctx.export_ct(single2[j]))
+    assert np.array_equal(ctx.export_ct(both[n_out]), o.linear(cts2, pts, baby, giant, pr.scale, keys, only=[0])[0].data)
 
 
 @pytest.mark.gpu
@@ -195,7 +205,7 @@ def test_fast_conv_gpu_parity_small():
     merged_w, outs_w = conv.fast_conv(o, cts, pre, fast, rot, pr.scale, keys)
     ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
     n_in, n_out, nP = FAST_SMALL["n_in"], FAST_SMALL["n_out"], FAST_SMALL["nP"]
-    ctx.bind(max(nP, n_out, n_in // nP), 1, max(nP, FAST_SMALL["c"]))
+    ctx.bind(max(n_in, n_out), 1, max(nP, FAST_SMALL["c"]))      # the merge step batches all n_in inputs
     ctx.load_keys(None, keys.rot)
     fc, outs = _gpu_fast(ctx, pr, FAST_SMALL, rot, pre, fast, [ctx.import_ct(c.data, c.level, c.scale) for c in cts])
     for a, m in enumerate(merged_w):
@@ -221,9 +231,11 @@ def test_fast_conv_gpu_table1_1d64_conv3():
     keys = o.keygen(3, sorted(set(rot["pre"] + rot["baby"] + rot["giant"] + rot["post"]) - {0}), relin=False)
     cts = [o.encrypt(v, keys.pk, 120 + i) for i, v in enumerate(xs)]
     ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
-    ctx.bind(16, 1, 16)
+    ctx.bind(32, 1, 16)
     ctx.load_keys(None, keys.rot)
-    fc, outs = _gpu_fast(ctx, pr, case, rot, pre, fast, [ctx.import_ct(c.data, c.level, c.scale) for c in cts])
+    gcts = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+    fc, outs = _gpu_fast(ctx, pr, case, rot, pre, fast, gcts + gcts[::-1])     # two requests in one batch
+    assert len(outs) == 32
     print("[conv] fast conv3: oracle", flush=True)
     merged_w, outs_w = conv.fast_conv(o, cts, pre, fast, rot, pr.scale, keys, only=[0, 15])
     for a, m in enumerate(merged_w):
