@@ -69,6 +69,7 @@ def lib():
         L.orc_keygen_public.argtypes = [C.c_void_p, I64P, C.c_uint64, U64P]
         L.orc_keygen_switch.argtypes = [C.c_void_p, I64P, U64P, C.c_uint64, U64P]
         L.orc_encrypt.argtypes = [C.c_void_p, U64P, U64P, C.c_uint64, U64P]
+        L.orc_encrypt_noise.argtypes = [C.c_void_p, U64P, U64P, C.c_int, I64P, I64P, I64P, U64P]
         L.orc_decrypt.argtypes = [C.c_void_p, I64P, U64P, C.c_int, U64P]
         L.orc_add.argtypes = [C.c_void_p, U64P, U64P, C.c_int, U64P]
         L.orc_add_plain.argtypes = [C.c_void_p, U64P, U64P, C.c_int, U64P]
@@ -202,6 +203,18 @@ class Oracle:
         ct = np.empty((2, pr.L + 1, self.N), dtype=np.uint64)
         self.L.orc_encrypt(self._h, _p(pk), _p(m), seed, _p(ct))
         return Ciphertext(ct, pr.L, scale)
+
+    def encrypt_noise(self, m: np.ndarray, pk: np.ndarray, level: int, v, e0, e1, scale: float) -> Ciphertext:
+        """Encryption of plaintext residues m ([level+1][N]) with the given
+        random polynomials (v ternary, e0, e1 small): (v b + e0 + m, v a + e1)."""
+        m = np.ascontiguousarray(m, dtype=np.uint64)
+        assert m.shape == (level + 1, self.N)
+        vs = [np.ascontiguousarray(x, dtype=np.int64) for x in (v, e0, e1)]
+        assert all(x.shape == (self.N,) for x in vs)
+        ct = np.empty((2, level + 1, self.N), dtype=np.uint64)
+        self.L.orc_encrypt_noise(self._h, _p(np.ascontiguousarray(pk, dtype=np.uint64)), _p(m), level,
+                                 *(_p(x, I64P) for x in vs), _p(ct))
+        return Ciphertext(ct, level, scale)
 
     def decrypt(self, ct: Ciphertext, sk: np.ndarray) -> np.ndarray:
         m = np.empty((ct.level + 1, self.N), dtype=np.uint64)

@@ -246,23 +246,35 @@ void orc_keygen_switch(void* h, const i64* s, const u64* s_prime, u64 seed, u64*
   }
 }
 
-// Public-key encryption of plaintext residues m ([L+1][N]) at the top level:
-// v <- ternary, e0, e1 <- chi;  ct = (v*b + e0 + m, v*a + e1).
-void orc_encrypt(void* h, const u64* pk, const u64* m, u64 seed, u64* ct) {
-  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = c.nq;
+// Public-key encryption of plaintext residues m ([level+1][N]) with the
+// random polynomials given: v ternary, e0, e1 small (signed coefficients);
+// pk = (b, a) over q_0..q_L, used on q_0..q_level:
+//   ct = (v*b + e0 + m, v*a + e1)   ([2][level+1][N]).
+void orc_encrypt_noise(void* h, const u64* pk, const u64* m, int level, const i64* v, const i64* e0, const i64* e1,
+                       u64* ct) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N; const int nl = level + 1;
   std::vector<int> idx(nl); for (int i = 0; i < nl; ++i) idx[i] = i;
-  std::vector<i64> v(N), e0(N), e1(N);
-  orc_sample_ternary(derive_seed(seed, 0x21), c.N, v.data());
-  orc_sample_gaussian(derive_seed(seed, 0x22), c.N, e0.data());
-  orc_sample_gaussian(derive_seed(seed, 0x23), c.N, e1.data());
-  std::vector<u64> vr(nl * N); signed_to_rns(c, v.data(), nl, idx.data(), vr.data());
+  std::vector<u64> vr(nl * N); signed_to_rns(c, v, nl, idx.data(), vr.data());
+  std::vector<u64> pa(nl * N);
+  std::memcpy(pa.data(), pk + (size_t)c.nq * N, nl * N * sizeof(u64));
   orc_polymul(h, nl, idx.data(), vr.data(), pk, ct);
-  orc_polymul(h, nl, idx.data(), vr.data(), pk + nl * N, ct + nl * N);
+  orc_polymul(h, nl, idx.data(), vr.data(), pa.data(), ct + nl * N);
   for (int l = 0; l < nl; ++l) { u64 q = c.primes[l];
     for (size_t k = 0; k < N; ++k) {
       ct[l * N + k] = addmod(addmod(ct[l * N + k], from_signed(e0[k], q), q), m[l * N + k], q);
       ct[(nl + l) * N + k] = addmod(ct[(nl + l) * N + k], from_signed(e1[k], q), q);
     } }
+}
+
+// Public-key encryption at the top level with the polynomials drawn from
+// the seed: v <- ternary, e0, e1 <- chi.
+void orc_encrypt(void* h, const u64* pk, const u64* m, u64 seed, u64* ct) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N;
+  std::vector<i64> v(N), e0(N), e1(N);
+  orc_sample_ternary(derive_seed(seed, 0x21), c.N, v.data());
+  orc_sample_gaussian(derive_seed(seed, 0x22), c.N, e0.data());
+  orc_sample_gaussian(derive_seed(seed, 0x23), c.N, e1.data());
+  orc_encrypt_noise(h, pk, m, c.nq - 1, v.data(), e0.data(), e1.data(), ct);
 }
 
 // m = c0 + c1 * s over Q_l.

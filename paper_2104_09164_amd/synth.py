@@ -54,3 +54,19 @@ def rotation_steps_random(count: int, slots: int, seed: int = SEED_STEPS) -> lis
     """`count` distinct steps drawn uniformly from [1, slots)."""
     rng = np.random.default_rng(seed)
     return sorted(int(v) for v in rng.choice(np.arange(1, slots), size=count, replace=False))
+
+
+def encryption_noise(n: int, seed: int) -> np.ndarray:
+    """Random polynomials of one public-key encryption, int32 [3][n]:
+    v with coefficients uniform in {-1, 0, 1}, then e0 and e1, rounded
+    N(0, 3.2^2) clipped to |e| <= 19."""
+    rng = np.random.default_rng(seed)
+    v = rng.integers(-1, 2, n)
+    e = np.clip(np.rint(rng.normal(0.0, 3.2, (2, n))), -19, 19)
+    return np.concatenate([v[None, :], e]).astype(np.int32)
+
+
+def slot_vectors(count: int, slots: int, seed: int) -> np.ndarray:
+    """`count` complex slot vectors, real and imaginary parts U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, (count, slots)) + 1j * rng.uniform(-1.0, 1.0, (count, slots))
