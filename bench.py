@@ -1,7 +1,7 @@
 """Benchmark: encrypted inferences/s of the small dense net, batched vs plain.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--large-batch B]
-                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-conv] [--no-cpu]
+                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-conv] [--no-client] [--no-cpu]
 
 One step = one batched encrypted inference of B requests through the whole
 small network (N=2^15; dense 1024->128 with 32 baby steps -> rescale ->
@@ -234,6 +234,60 @@ def conv_leg(reps=5):
                         for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])},
             "paper_context_ms": {"ordinary_conv": 409, "fast_conv_total": 390,
                                  "note": "Table 1, 1D-CNN-64 conv2, 16-thread Xeon with SEAL; context only"}}
+
+
+def client_leg(reps=10, R=16):
+    """Client side on the small net's ring (N = 2^15, 7 limbs): the end users'
+    encode + public-key encryption of R request inputs at the top level, and
+    the monitoring service's decryption + decode of R network outputs at the
+    output level, each one batched call sequence.  Random residues as pk and
+    as the ciphertexts, a random ternary sk (the timing does not depend on
+    the key values; the calls are tested bit for bit against the oracle)."""
+    import torch
+    from paper_2104_09164_amd import he, netplan, synth, tune
+    plan = netplan.preset_plan("cfg3")
+    N = 1 << plan.log_n
+    ctx = he.Context(plan.log_n, plan.q, plan.p, plan.alpha)
+    tune.apply_knobs(ctx, tune.load("cfg3"))
+    ctx.bind(1, 1, 1)
+    pk = residues(plan.q, N, (2,), 1200)
+    sk = np.random.default_rng(1201).integers(-1, 2, N).astype(np.int64)
+    cl = ctx.client(R, pk=pk, sk=sk)
+    xs = [synth.request_input(1024, r) for r in range(R)]
+    z = torch.zeros((R, N // 2), dtype=torch.complex128)
+    for r, x in enumerate(xs):
+        z[r, :1024] = torch.from_numpy(x)
+    z = z.cuda()
+    noise = torch.from_numpy(np.stack([synth.encryption_noise(N, 1300 + r) for r in range(R)])).cuda()
+    cts = [ctx.new_ct(plan.L) for _ in range(R)]
+    lo = plan.out_level
+    outs = [ctx.import_ct(residues(plan.q[: lo + 1], N, (2,), 1400 + r), lo, plan.scale) for r in range(R)]
+
+    def enc():
+        cl.encrypt(cl.encode(z, plan.scale, plan.L), noise, plan.L, plan.scale, outs=cts)
+
+    def dec():
+        cl.decode(cl.decrypt(outs), lo, plan.scale)
+
+    for f in (enc, dec):
+        f()
+    torch.cuda.synchronize()
+    te = float(np.median(time_events(enc, reps)))
+    td = float(np.median(time_events(dec, reps)))
+    ctx.trace_read()
+    ctx.set_knob("trace", 1)
+    enc()
+    dec()
+    tab = ctx.trace_read()
+    ctx.set_knob("trace", 0)
+    return {"workload": (f"N=2^{plan.log_n}: encode + encrypt at level {plan.L} ({plan.L + 1} limbs), decrypt + "
+                         f"decode at level {lo}; {R} requests per batched call"),
+            "requests": R, "encrypt_ms_per_call": te, "encrypt_us_per_request": te * 1e3 / R,
+            "decrypt_ms_per_call": td, "decrypt_us_per_request": td * 1e3 / R,
+            "classes": {k: {"launches": v[0], "ms": v[1], "gbs": v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None}
+                        for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])},
+            "paper_context_ms": {"encrypt_per_sample": "22-25", "decrypt": 1.6,
+                                 "note": "Results, time requirement, steps (iii) and (v); CPU with SEAL; context only"}}
 
 
 def ks_leg(reps=3, items=64, n_steps=32):
@@ -607,6 +661,7 @@ def main():
     ap.add_argument("--no-ks", action="store_true")
     ap.add_argument("--no-tuned-split", action="store_true", help="skip the small-net leg with tuned baby steps")
     ap.add_argument("--no-conv", action="store_true", help="skip the multi-channel convolution leg")
+    ap.add_argument("--no-client", action="store_true", help="skip the client encode/encrypt/decrypt leg")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--roofline-only", action="store_true",
@@ -685,6 +740,9 @@ def main():
     if not args.no_conv:
         log("convolution leg")
         out["conv"] = conv_leg()
+    if not args.no_client:
+        log("client leg")
+        out["client"] = client_leg()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         # weighted by the operation counts of the paper's evaluation order (one

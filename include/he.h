@@ -324,6 +324,55 @@ int he_trace_read(he_ctx* ctx, he_trace_entry* out, uint32_t capacity, uint32_t*
 /* Waits for all work enqueued on the context's stream. */
 int he_sync(he_ctx* ctx);
 
+/* ----------------------------------------------------------- client side
+ * Encoding, encryption, decryption and decoding on the device for the
+ * parties that hold keys (the protocol's parties: end-users encrypt with pk,
+ * the monitoring service decrypts with sk; Results, "Time requirement of
+ * secure action recognition", steps (iii) and (v); Methods, threat model).
+ * The evaluation entry points above never take pk or sk.  All calls enqueue
+ * on the context's stream and return without waiting.
+ *
+ * Slots: z in C^(N/2), element j at zeta^(5^j mod 2N), zeta = exp(i pi/N)
+ * (the ordering under which rho^r rotates left by r); the plaintext of z at
+ * scale D is the integer polynomial with coefficients
+ *   M_k = round(D (2/N) Re sum_j z_j zeta^(-5^j k))   (half away from zero),
+ * reduced mod each q_i.  Device slot arrays: [n][N/2] complex numbers, each
+ * as two doubles (re, im).  Device plaintext arrays: [n][level+1][N]
+ * coefficient residues (uint64, item stride (level+1) N words). */
+typedef struct he_client he_client;
+/* pk_host: [2][L+1][N] coefficient residues (b, a) with b = -a s + e, or
+ * NULL (no encryption); sk_host: the N secret coefficients in {-1, 0, 1}, or
+ * NULL (no decryption).  Both are copied to library-owned device memory in
+ * NTT form; with scratch for batches of up to max_batch requests
+ * (1 <= max_batch <= HE_MAX_BATCH). */
+int he_client_create(he_ctx* ctx, uint32_t max_batch, const uint64_t* pk_host, const int64_t* sk_host,
+                     he_client** out);
+int he_client_destroy(he_client* cl);
+/* Encodes n slot vectors at `scale` into plaintexts over q_0..q_level.  The
+ * caller keeps scale * max |z_j| below 2^62 (M_k then fits a signed 64-bit
+ * word; larger values give unspecified residues).  The embedding is a
+ * double-precision FFT, so a coefficient can differ by 1 from an exact
+ * evaluation of the sum when its value lies within rounding of a half. */
+int he_encode(he_client* cl, uint32_t n, const double* slots_dev, double scale, uint32_t level,
+              uint64_t* pt_dev);
+/* Public-key encryption at `level` (pk restricted to q_0..q_level):
+ *   c0 = v b + e0 + m,  c1 = v a + e1  (mod q_i),
+ * with the random polynomials given by the caller: noise_dev [n][3][N]
+ * signed 32-bit coefficients (v, e0, e1), v ternary and e0, e1 small.
+ * pt_dev: [n][level+1][N] coefficient residues (he_encode's output);
+ * out[r].dev receives ciphertext r (NTT form), level and scale are set.
+ * HE_ENOKEY without pk. */
+int he_encrypt(he_client* cl, uint32_t n, const uint64_t* pt_dev, const int32_t* noise_dev, uint32_t level,
+               double scale, he_ct* out);
+/* m = c0 + c1 s (mod q_i, i <= level) of n ciphertexts at one level, as
+ * coefficient residues [n][level+1][N] in pt_dev.  HE_ENOKEY without sk. */
+int he_decrypt(he_client* cl, uint32_t n, const he_ct* in, uint64_t* pt_dev);
+/* Slots of n plaintexts over q_0..q_level at `scale`: each coefficient is
+ * lifted exactly to its centred integer in (-Q/2, Q/2] (mixed-radix digits,
+ * Q = q_0...q_level), divided by scale, and evaluated at the slot roots by a
+ * double-precision FFT.  Writes [n][N/2] complex slots to slots_dev. */
+int he_decode(he_client* cl, uint32_t n, const uint64_t* pt_dev, uint32_t level, double scale, double* slots_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,6 +100,12 @@ def lib() -> C.CDLL:
             "he_ctx_set_knob": (C.c_int, [vp, C.c_char_p, C.c_int64]),
             "he_ctx_get_knob": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int64)]),
             "he_trace_read": (C.c_int, [vp, C.POINTER(_TraceEntry), u32, C.POINTER(u32)]),
+            "he_client_create": (C.c_int, [vp, u32, vp, vp, C.POINTER(vp)]),
+            "he_client_destroy": (C.c_int, [vp]),
+            "he_encode": (C.c_int, [vp, u32, vp, dbl, u32, vp]),
+            "he_encrypt": (C.c_int, [vp, u32, vp, vp, u32, dbl, ctp]),
+            "he_decrypt": (C.c_int, [vp, u32, ctp, vp]),
+            "he_decode": (C.c_int, [vp, u32, vp, u32, dbl, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -116,7 +122,8 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_eval_dense_batch", "he_square_batch", "he_rescale_batch", "he_rotate_hoisted_batch", "he_ntt",
             "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
             "he_dense_load_ex", "he_linear_bytes", "he_linear_load", "he_linear_free", "he_linear_scratch_bytes",
-            "he_eval_linear", "he_eval_linear_batch")
+            "he_eval_linear", "he_eval_linear_batch", "he_client_create", "he_client_destroy", "he_encode",
+            "he_encrypt", "he_decrypt", "he_decode")
 
 HE_DENSE_QP = 1
 HE_DENSE_RS_SHIFT = 8
@@ -182,6 +189,75 @@ class Linear:
             lib().he_linear_free(self.h)
         except Exception:
             pass
+
+
+class Client:
+    """Device-side encode / encrypt / decrypt / decode for the key holders
+    (he_client_*).  Slot tensors: complex128 [n][N/2]; plaintext tensors:
+    int64 storage of uint64 residues [n][level+1][N]; noise: int32 [n][3][N]."""
+
+    def __init__(self, ctx: "Context", max_batch: int, pk: np.ndarray | None = None, sk: np.ndarray | None = None):
+        self.ctx, self.max_batch = ctx, max_batch
+        pkh = np.ascontiguousarray(pk, dtype=np.uint64) if pk is not None else None
+        skh = np.ascontiguousarray(sk, dtype=np.int64) if sk is not None else None
+        if pkh is not None and pkh.shape != (2, len(ctx.q), ctx.N):
+            raise ValueError(f"pk shape {pkh.shape}, expected {(2, len(ctx.q), ctx.N)}")
+        if skh is not None and skh.shape != (ctx.N,):
+            raise ValueError(f"sk shape {skh.shape}, expected {(ctx.N,)}")
+        h = C.c_void_p()
+        _check(lib().he_client_create(ctx.h, max_batch, C.c_void_p(pkh.ctypes.data) if pkh is not None else None,
+                                      C.c_void_p(skh.ctypes.data) if skh is not None else None, C.byref(h)),
+               "he_client_create")
+        self.h = h
+
+    def __del__(self):
+        try:
+            lib().he_client_destroy(self.h)
+        except Exception:
+            pass
+
+    def encode(self, slots, scale: float, level: int):
+        torch = _torch()
+        z = slots.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        n = z.shape[0]
+        if z.shape != (n, self.ctx.N // 2):
+            raise ValueError(f"slots shape {tuple(z.shape)}, expected (n, {self.ctx.N // 2})")
+        pt = torch.empty((n, level + 1, self.ctx.N), dtype=torch.int64, device=self.ctx.device)
+        _check(lib().he_encode(self.h, n, C.c_void_p(z.data_ptr()), scale, level, C.c_void_p(pt.data_ptr())),
+               "he_encode")
+        return pt
+
+    def encrypt(self, pt, noise, level: int, scale: float, outs=None):
+        torch = _torch()
+        n = pt.shape[0]
+        if pt.shape != (n, level + 1, self.ctx.N) or noise.shape != (n, 3, self.ctx.N) or noise.dtype != torch.int32:
+            raise ValueError("plaintexts [n][level+1][N] and int32 noise [n][3][N] expected")
+        outs = outs or [self.ctx.new_ct(level) for _ in range(n)]
+        arr = (_Ct * max(1, n))(*[o._c() for o in outs])
+        _check(lib().he_encrypt(self.h, n, C.c_void_p(pt.data_ptr()), C.c_void_p(noise.data_ptr()), level, scale,
+                                arr), "he_encrypt")
+        for o in outs:
+            o.level, o.scale = level, scale
+        return outs
+
+    def decrypt(self, cts):
+        torch = _torch()
+        n = len(cts)
+        level = cts[0].level if n else 0
+        pt = torch.empty((n, level + 1, self.ctx.N), dtype=torch.int64, device=self.ctx.device)
+        arr = (_Ct * max(1, n))(*[c._c() for c in cts])
+        _check(lib().he_decrypt(self.h, n, arr, C.c_void_p(pt.data_ptr())), "he_decrypt")
+        return pt
+
+    def decode(self, pt, level: int, scale: float):
+        torch = _torch()
+        n = pt.shape[0]
+        if pt.shape != (n, level + 1, self.ctx.N):
+            raise ValueError("plaintexts [n][level+1][N] expected")
+        z = torch.empty((n, self.ctx.N // 2), dtype=torch.complex128, device=self.ctx.device)
+        _check(lib().he_decode(self.h, n, C.c_void_p(pt.data_ptr()), level, scale, C.c_void_p(z.data_ptr())),
+               "he_decode")
+        return z
 
 
 class Context:
@@ -402,6 +478,9 @@ class Context:
         _check(lib().he_trace_read(self.h, arr, cap, C.byref(n)), "he_trace_read")
         return {arr[i].kernel.decode(): (int(arr[i].launches), float(arr[i].ms), float(arr[i].bytes))
                 for i in range(min(n.value, cap))}
+
+    def client(self, max_batch: int, pk: np.ndarray | None = None, sk: np.ndarray | None = None) -> Client:
+        return Client(self, max_batch, pk, sk)
 
     def sync(self) -> None:
         _check(lib().he_sync(self.h), "he_sync")
