@@ -12,10 +12,11 @@
 // u = N - 1 - (e_j - 1)/2:
 //   encode:  m_k = (1/N) Re( zeta^-k  sum_u w_u exp(-2 pi i u k / N) )
 //   decode:  z_j = sum_k (m_k zeta^k) exp(+2 pi i u k / N)  at u = (e_j - 1)/2.
-// Both are one length-N complex FFT in double precision: log2 N Stockham
-// radix-2 passes (self-sorting, natural order in and out), each an HBM
-// streaming kernel over the whole batch, consecutive threads on consecutive
-// complex words.
+// Both are one length-N complex FFT in double precision: Stockham passes of
+// radix 8 (one radix-2 or radix-4 pass first when 3 does not divide
+// log2 N), self-sorting, natural order in and out; each pass is an HBM
+// streaming kernel over the whole batch, consecutive threads reading
+// consecutive complex words, 8 points per thread in registers.
 //
 // Encryption and decryption are limb-local (one thread per coefficient per
 // limb): residues of the small polynomials, forward NTTs (the library's
@@ -32,7 +33,7 @@ struct he_client {
   u32 max_batch = 0;
   u64* pk = nullptr;       // [2][L+1][N] NTT form, Montgomery form (x 2^64 mod q_i)
   u64* sk = nullptr;       // [L+1][N] NTT form, Montgomery form
-  double2* tw = nullptr;   // [N/2] exp(-2 pi i k / N)
+  double2* tw = nullptr;   // [N] exp(-2 pi i k / N)
   double2* twist = nullptr;  // [N] zeta^k = exp(i pi k / N)
   u32* pos = nullptr;      // [N/2] (e_j - 1) / 2
   u64* garner = nullptr;   // [nq][nq][2]: q_j^{-1} mod q_i and its Shoup companion (j < i)
@@ -79,26 +80,65 @@ __global__ void __launch_bounds__(BS) k_cl_scatter(const double2* __restrict__ z
   o[N - 1 - u] = make_double2(v.x, -v.y);
 }
 
-// One Stockham radix-2 pass, sub-transform length 2 ns (ns = 2^lns); grid
-// (N/2/BS, n).  Butterfly j: a = x[j], b = x[j + N/2] times the twiddle
-// exp(-+2 pi i (j mod ns) / (2 ns)); outputs at (j / ns) 2 ns + (j mod ns) and
-// + ns.  After log2 N passes with ns = 1, 2, ..., N/2 the output is the DFT
-// in natural order (sign - forward, + inverse, unnormalised).
+// In-register DFT of R = 2, 4 or 8 points, natural order in and out:
+// V_t = sum_s v_s exp(-+2 pi i s t / R), by radix-2 Stockham passes over the
+// register array (all indices compile-time after unrolling).
+template <int R>
+__device__ __forceinline__ void dft_regs(double2 (&v)[R], bool inverse) {
+  constexpr double h = 0.70710678118654752440;   // cos(pi/4)
+  const double2 w8[8] = {{1.0, 0.0}, {h, -h}, {0.0, -1.0}, {-h, -h}, {-1.0, 0.0}, {-h, h}, {0.0, 1.0}, {h, h}};
+#pragma unroll
+  for (int ns = 1; ns < R; ns *= 2) {
+    double2 o[R];
+#pragma unroll
+    for (int jj = 0; jj < R / 2; ++jj) {
+      const int k = jj & (ns - 1);
+      double2 w = w8[k * (8 / (2 * ns))];   // exp(-2 pi i k / (2 ns))
+      if (inverse) w.y = -w.y;
+      const double2 a = v[jj], b = v[jj + R / 2];
+      const double2 t = make_double2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+      const int d = (jj / ns) * 2 * ns + k;
+      o[d] = make_double2(a.x + t.x, a.y + t.y);
+      o[d + ns] = make_double2(a.x - t.x, a.y - t.y);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = o[m];
+  }
+}
+
+// One Stockham radix-R pass (R = 2^LR) after sub-transforms of length
+// ns = 2^lns; grid (N/R/BS, n).  Thread j: v_t = x[j + t N/R] times the
+// twiddle W^(t (j mod ns)), W = exp(-+2 pi i / (R ns)); R-point DFT; V_t to
+// y[(j / ns) R ns + (j mod ns) + t ns].  Passes whose radices multiply to N,
+// with ns the product of the radices before, give the DFT in natural order
+// (sign - forward, + inverse, unnormalised).
+template <int LR>
 __global__ void __launch_bounds__(BS) k_cl_fft_pass(const double2* __restrict__ x, double2* __restrict__ y,
                                                     const double2* __restrict__ tw, u32 N, u32 logn, u32 lns,
                                                     int inverse) {
+  constexpr int R = 1 << LR;
   const u32 j = blockIdx.x * BS + threadIdx.x, bi = blockIdx.y;
-  const u32 half = N >> 1, ns = 1u << lns;
+  const u32 stride = N >> LR, k = j & ((1u << lns) - 1);
+  if (j >= stride) return;   // N / R < BS for the smallest rings
   const double2* xi = x + (size_t)bi * N;
   double2* yo = y + (size_t)bi * N;
-  const u32 k = j & (ns - 1);
-  const double2 a = xi[j], b = xi[j + half];
-  double2 w = tw[(size_t)k << (logn - 1 - lns)];
-  if (inverse) w.y = -w.y;
-  const double2 t = make_double2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
-  const u32 o = ((j >> lns) << (lns + 1)) | k;
-  yo[o] = make_double2(a.x + t.x, a.y + t.y);
-  yo[o + ns] = make_double2(a.x - t.x, a.y - t.y);
+  const u32 tsh = logn - LR - lns;   // W^(t k) = exp(-2 pi i (t k 2^tsh) / N)
+  double2 v[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const double2 a = xi[j + t * stride];
+    if (t == 0) {
+      v[t] = a;
+    } else {
+      double2 w = tw[(size_t)(t * k) << tsh];
+      if (inverse) w.y = -w.y;
+      v[t] = make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+    }
+  }
+  dft_regs<R>(v, inverse != 0);
+  const u32 o = ((j >> lns) << (lns + LR)) | k;
+#pragma unroll
+  for (int t = 0; t < R; ++t) yo[o + (t << lns)] = v[t];
 }
 
 // grid (N/BS, n): M_k = round_half_away(scale Re(zeta^-k V_k) / N), residues
@@ -221,15 +261,24 @@ __global__ void __launch_bounds__(BS) k_cl_gather(const double2* __restrict__ va
 u32 grid_x(u32 work) { return (work + BS - 1) / BS; }
 
 // Length-N FFT of n vectors starting in cl->fa; returns the buffer holding
-// the result (fa or fb).
+// the result (fa or fb).  log2 N = 3 a + b: one radix-2^b pass (b > 0), then
+// a radix-8 passes.
 int fft(he_client* cl, u32 n, bool inverse, double2** result) {
   he_ctx* c = cl->ctx;
   double2 *x = cl->fa, *y = cl->fb;
-  for (u32 lns = 0; lns < c->log_n; ++lns) {
+  u32 lns = 0;
+  while (lns < c->log_n) {
+    const u32 rem = (c->log_n - lns) % 3, lr = (lns == 0 && rem) ? rem : 3;
     TraceScope ts(c, TK_CLIENT_FFT, (double)n * c->N * 32.0);
-    HE_LAUNCH(ts, k_cl_fft_pass, dim3(grid_x(c->N / 2), n), dim3(BS), c->stream, x, y, cl->tw, c->N, c->log_n, lns,
-              (int)inverse);
+    const dim3 g(grid_x(c->N >> lr), n);
+    if (lr == 1)
+      HE_LAUNCH(ts, k_cl_fft_pass<1>, g, dim3(BS), c->stream, x, y, cl->tw, c->N, c->log_n, lns, (int)inverse);
+    else if (lr == 2)
+      HE_LAUNCH(ts, k_cl_fft_pass<2>, g, dim3(BS), c->stream, x, y, cl->tw, c->N, c->log_n, lns, (int)inverse);
+    else
+      HE_LAUNCH(ts, k_cl_fft_pass<3>, g, dim3(BS), c->stream, x, y, cl->tw, c->N, c->log_n, lns, (int)inverse);
     std::swap(x, y);
+    lns += lr;
   }
   *result = x;
   return ok();
@@ -299,9 +348,9 @@ int he_client_create(he_ctx* c, uint32_t max_batch, const uint64_t* pk_host, con
   auto fail = [&](int e) { he_client_destroy(cl); return e; };
 
   // host tables: FFT twiddles, the twist zeta^k, slot positions, Garner inverses
-  std::vector<double2> tw(N / 2), twist(N);
+  std::vector<double2> tw(N), twist(N);
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (u32 k = 0; k < N / 2; ++k) {
+  for (u32 k = 0; k < N; ++k) {
     const long double a = -2.0L * pi * (long double)k / (long double)N;
     tw[k] = make_double2((double)cosl(a), (double)sinl(a));
   }
@@ -324,7 +373,7 @@ int he_client_create(he_ctx* c, uint32_t max_batch, const uint64_t* pk_host, con
       garner[((size_t)i * nq + j) * 2 + 1] = (u64)(((unsigned __int128)inv << 64) / q);
     }
 
-  if ((rc = dev_alloc(&cl->tw, N / 2)) || (rc = dev_alloc(&cl->twist, N)) || (rc = dev_alloc(&cl->pos, N / 2)) ||
+  if ((rc = dev_alloc(&cl->tw, N)) || (rc = dev_alloc(&cl->twist, N)) || (rc = dev_alloc(&cl->pos, N / 2)) ||
       (rc = dev_alloc(&cl->garner, garner.size())) || (rc = dev_alloc(&cl->fa, (size_t)max_batch * N)) ||
       (rc = dev_alloc(&cl->fb, (size_t)max_batch * N)))
     return fail(rc);
