@@ -6,8 +6,10 @@
  * Inference", Methods.  The cloud holds only evaluation keys and the
  * cleartext model, receives encrypted inputs and returns one encrypted result;
  * it never holds the secret key and never decrypts (Methods, "Threat model";
- * Results, the three-party protocol).  Hence no call here takes a secret key,
- * samples randomness, encrypts or decrypts: those belong to the client.
+ * Results, the three-party protocol).  Hence no evaluation call takes a key
+ * of the parties, samples randomness, encrypts or decrypts.  The client
+ * section at the end (he_client_*) serves the parties that do: it keeps pk
+ * and/or sk in an object of its own, apart from the evaluation context.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -347,6 +349,8 @@ typedef struct he_client he_client;
  * (1 <= max_batch <= HE_MAX_BATCH). */
 int he_client_create(he_ctx* ctx, uint32_t max_batch, const uint64_t* pk_host, const int64_t* sk_host,
                      he_client** out);
+/* Waits for the context's stream, frees the client's device memory.  Destroy
+ * every client before its context. */
 int he_client_destroy(he_client* cl);
 /* Encodes n slot vectors at `scale` into plaintexts over q_0..q_level.  The
  * caller keeps scale * max |z_j| below 2^62 (M_k then fits a signed 64-bit
