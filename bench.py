@@ -667,6 +667,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the small-net traced pass (profiling runs): 1 GiB calibration copy, "
                          "setup, one untimed step, --steps traced steps")
+    ap.add_argument("--client-only", action="store_true",
+                    help="only the client encode/encrypt/decrypt leg (profiling runs)")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the NTT leg (profiling runs), preceded by a 1 GiB device copy whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -676,6 +678,9 @@ def main():
               "GPUs with no exchange between them). Run with --gpus 1.", file=sys.stderr)
         return 2
     import torch
+    if args.client_only:
+        print(json.dumps({"client": client_leg()}), flush=True)
+        return 0
     if args.ntt_only:
         calibration_copy()
         print(json.dumps({"ntt": ntt_leg()}), flush=True)
