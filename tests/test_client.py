@@ -226,6 +226,35 @@ def test_decode_large_values_and_signs():
 
 
 @pytest.mark.gpu
+def test_client_max_batch():
+    """The largest batch (64 requests per call) at N = 2^10: encryption bit
+    for bit, decryption bit for bit, decode within the bound, for every
+    request."""
+    import torch
+    from paper_2104_09164_amd import he
+    pr = small_params()
+    o = ckks.Oracle(pr)
+    keys = o.keygen(12, relin=False)
+    ctx = _ctx(pr)
+    R = he.HE_MAX_BATCH
+    cl = ctx.client(R, pk=keys.pk, sk=keys.sk)
+    print(f"[client] max batch {R}", flush=True)
+    zs = synth.slot_vectors(R, pr.slots, 90)
+    ms = np.stack([o.encode(zs[r], pr.scale, pr.L) for r in range(R)])
+    noise = np.stack([synth.encryption_noise(pr.n, 200 + r) for r in range(R)])
+    outs = cl.encrypt(torch.from_numpy(ms.view(np.int64)).cuda(), torch.from_numpy(noise).cuda(), pr.L, pr.scale)
+    pt = cl.decrypt(outs)
+    z = cl.decode(pt, pr.L, pr.scale).cpu().numpy()
+    got_pt = pt.cpu().numpy().view(np.uint64)
+    for r in range(R):
+        ct = o.encrypt_noise(ms[r], keys.pk, pr.L, *noise[r], pr.scale)
+        assert np.array_equal(ctx.export_ct(outs[r]), ct.data), f"request {r}: ciphertext"
+        want = o.decrypt(ct, keys.sk)
+        assert np.array_equal(got_pt[r], want), f"request {r}: residues"
+        assert np.max(np.abs(z[r] - enc.decode(want, pr.scale, pr.q, pr.n))) <= 2.0 ** -30
+
+
+@pytest.mark.gpu
 def test_client_errors():
     import torch
     from paper_2104_09164_amd import he
