@@ -443,13 +443,15 @@ def trace_steps(ctx, runner, batch, steps):
 
 def traffic_record(kernel, launches_per_step):
     """rocprofv3 FETCH_SIZE/WRITE_SIZE of one kernel class, per launch, from
-    profiles/; dropped unless taken on the current kernel sources."""
+    profiles/; dropped unless taken on the current sources of the evaluation
+    kernels (every file under csrc/ but the client path's client.hip)."""
     import hashlib
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", "roofline_traffic.json")))
         h = hashlib.sha256()
         for f in sorted(os.listdir(os.path.join(ROOT, "paper_2104_09164_amd", "csrc"))):
-            h.update(open(os.path.join(ROOT, "paper_2104_09164_amd", "csrc", f), "rb").read())
+            if f != "client.hip":
+                h.update(open(os.path.join(ROOT, "paper_2104_09164_amd", "csrc", f), "rb").read())
         rec = prof.get("kernels", {}).get(kernel)
         if (rec and prof["csrc_sha256"] == h.hexdigest()
                 and rec["launches_per_step"] == launches_per_step):

@@ -339,12 +339,16 @@ int he_sync(he_ctx* ctx);
  * scale D is the integer polynomial with coefficients
  *   M_k = round(D (2/N) Re sum_j z_j zeta^(-5^j k))   (half away from zero),
  * reduced mod each q_i.  Device slot arrays: [n][N/2] complex numbers, each
- * as two doubles (re, im).  Device plaintext arrays: [n][level+1][N]
- * coefficient residues (uint64, item stride (level+1) N words). */
+ * as two doubles (re, im), 16-byte aligned.  Device plaintext arrays:
+ * [n][level+1][N] coefficient residues (uint64, item stride (level+1) N
+ * words).  HE_EINVAL for misaligned device arrays, n > max_batch, a null
+ * array with n > 0, or a scale that is not positive and finite; n = 0 is a
+ * no-op. */
 typedef struct he_client he_client;
 /* pk_host: [2][L+1][N] coefficient residues (b, a) with b = -a s + e, or
  * NULL (no encryption); sk_host: the N secret coefficients in {-1, 0, 1}, or
- * NULL (no decryption).  Both are copied to library-owned device memory in
+ * NULL (no decryption); HE_EINVAL for a residue >= its prime or a secret
+ * coefficient outside {-1, 0, 1}.  Both are copied to library-owned device memory in
  * NTT form; with scratch for batches of up to max_batch requests
  * (1 <= max_batch <= HE_MAX_BATCH). */
 int he_client_create(he_ctx* ctx, uint32_t max_batch, const uint64_t* pk_host, const int64_t* sk_host,

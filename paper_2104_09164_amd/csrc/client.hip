@@ -341,6 +341,10 @@ int he_client_create(he_ctx* c, uint32_t max_batch, const uint64_t* pk_host, con
   if (sk_host)
     for (u32 k = 0; k < N; ++k)
       if (sk_host[k] < -1 || sk_host[k] > 1) return HE_EINVAL;
+  if (pk_host)
+    for (u32 r = 0; r < 2 * nq; ++r)
+      for (u32 k = 0; k < N; ++k)
+        if (pk_host[(size_t)r * N + k] >= c->primes[r % nq]) return HE_EINVAL;
   he_client* cl = new he_client;
   cl->ctx = c;
   cl->max_batch = max_batch;
@@ -415,6 +419,7 @@ int he_client_create(he_ctx* c, uint32_t max_batch, const uint64_t* pk_host, con
 
 int he_encode(he_client* cl, uint32_t n, const double* slots, double scale, uint32_t level, uint64_t* pt) {
   if (!cl || ((!slots || !pt) && n) || n > cl->max_batch) return HE_EINVAL;
+  if (((uintptr_t)slots & 15) || ((uintptr_t)pt & 7)) return HE_EINVAL;
   he_ctx* c = cl->ctx;
   if (level >= c->nq) return HE_ELEVEL;
   if (!(scale > 0.0) || !std::isfinite(scale)) return HE_EINVAL;
@@ -493,6 +498,7 @@ int he_decrypt(he_client* cl, uint32_t n, const he_ct* in, uint64_t* pt) {
 
 int he_decode(he_client* cl, uint32_t n, const uint64_t* pt, uint32_t level, double scale, double* slots) {
   if (!cl || ((!pt || !slots) && n) || n > cl->max_batch) return HE_EINVAL;
+  if (((uintptr_t)slots & 15) || ((uintptr_t)pt & 7)) return HE_EINVAL;
   he_ctx* c = cl->ctx;
   if (level >= c->nq) return HE_ELEVEL;
   if (!(scale > 0.0) || !std::isfinite(scale)) return HE_EINVAL;

@@ -280,6 +280,24 @@ def test_client_errors():
     with pytest.raises(he.HeError) as e:
         ctx.client(2, sk=np.full(pr.n, 2, dtype=np.int64))
     assert e.value.code == -1
+    bad_pk = keys.pk.copy()
+    bad_pk[1, 2, 5] = pr.q[2]                # a residue equal to its prime
+    with pytest.raises(he.HeError) as e:
+        ctx.client(2, pk=bad_pk)
+    assert e.value.code == -1
+    # misaligned slot arrays are rejected before anything is enqueued
+    zbuf = torch.zeros(pr.slots + 1, dtype=torch.complex128, device="cuda")
+    out = torch.zeros((1, 1, pr.n), dtype=torch.int64, device="cuda")
+    import ctypes
+    rc = he.lib().he_encode(cl.h, 1, ctypes.c_void_p(zbuf.data_ptr() + 8), 2.0 ** 30, 0,
+                            ctypes.c_void_p(out.data_ptr()))
+    assert rc == -1
+    rc = he.lib().he_decode(cl.h, 1, ctypes.c_void_p(out.data_ptr()), 0, 2.0 ** 30,
+                            ctypes.c_void_p(zbuf.data_ptr() + 8))
+    assert rc == -1
+    with pytest.raises(he.HeError) as e:     # scale must be positive and finite
+        cl.encode(torch.zeros((1, pr.slots), dtype=torch.complex128), 0.0, 0)
+    assert e.value.code == -1
     # empty batches are no-ops
     cl2 = ctx.client(2, pk=keys.pk, sk=keys.sk)
     assert cl2.encode(torch.zeros((0, pr.slots), dtype=torch.complex128), 2.0 ** 30, 0).shape[0] == 0
