@@ -12,7 +12,8 @@ dense layers (bit for bit, and against the FP64 quadratic network).
 cfg4 (N = 2^16): the oracle's full network is minutes of CPU work, so the
 property checked at full size is the plaintext one: decrypted logits within
 2^-12 of the FP64 network and the same predicted class, for two requests
-evaluated in one batched graph replay.
+evaluated in one batched graph replay; once more with the inputs encoded and
+encrypted, and the outputs decrypted and decoded, by the device client path.
 """
 import numpy as np
 import pytest
@@ -23,7 +24,7 @@ from paper_2104_09164_amd import netplan, synth, tune
 pytestmark = pytest.mark.gpu
 
 
-def run_network(name, requests, check_bits, tuned_split=True, quadratic=False):
+def run_network(name, requests, check_bits, tuned_split=True, quadratic=False, client=False):
     import torch
     from paper_2104_09164_amd import he
     from paper_2104_09164_amd.batch import NetworkRunner
@@ -56,10 +57,18 @@ def run_network(name, requests, check_bits, tuned_split=True, quadratic=False):
     cts, xs = [], []
     for i, r in enumerate(requests):
         x = synth.request_input(shapes[0][1], r)
-        ct = o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r))
-        runner.inputs[i].buf.copy_(ctx.import_ct(ct.data, ct.level, ct.scale).buf)
-        cts.append(ct)
         xs.append(x)
+        if not client:
+            ct = o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r))
+            runner.inputs[i].buf.copy_(ctx.import_ct(ct.data, ct.level, ct.scale).buf)
+            cts.append(ct)
+    cl = None
+    if client:
+        # the end users' side on the device: encode and encrypt every request in one batch
+        cl = ctx.client(B, pk=keys.pk, sk=keys.sk)
+        z = torch.from_numpy(np.stack([plan.input_slots(x, pr.slots) for x in xs]).astype(np.complex128))
+        noise = torch.from_numpy(np.stack([synth.encryption_noise(pr.n, synth.request_seed(r)) for r in requests]))
+        cl.encrypt(cl.encode(z, pr.scale, pr.L), noise.cuda(), pr.L, pr.scale, outs=runner.inputs[:B])
     g = runner.capture(B)
     g.replay()
     torch.cuda.synchronize()
@@ -73,6 +82,10 @@ def run_network(name, requests, check_bits, tuned_split=True, quadratic=False):
             assert want.scale == outs[i].scale
             assert np.array_equal(got, want.data), f"{name} request {requests[i]} differs from the oracle"
         y = o.decrypt_decode(ckks.Ciphertext(got, outs[i].level, outs[i].scale), keys.sk).real[:2]
+        if cl is not None:
+            # the monitoring service's side on the device: decrypt and decode
+            yd = cl.decode(cl.decrypt([outs[i]]), outs[i].level, outs[i].scale).cpu().numpy()[0].real[:2]
+            assert np.max(np.abs(yd - y)) <= 2.0 ** -30
         yr = plainnet.forward(xs[i], Wr, br, acts)
         assert np.max(np.abs(y - yr)) <= 2.0 ** -12
         if abs(yr[0] - yr[1]) >= 2.0 ** -11:
@@ -93,6 +106,14 @@ def test_cfg3_network_quadratic_activation_bit_exact():
 
 def test_cfg4_network_full_size_fp64():
     run_network("cfg4", [0, 1], check_bits=False)
+
+
+def test_cfg4_network_device_client_round_trip():
+    """The large net's ring (N = 2^16, 11 limbs) end to end on the device:
+    inputs encoded and encrypted by he_encode / he_encrypt, the network from
+    its graph, outputs decrypted and decoded by he_decrypt / he_decode (equal
+    to the oracle's decryption within 2^-30), logits within 2^-12 of FP64."""
+    run_network("cfg4", [2, 3], check_bits=False, client=True)
 
 
 def test_cfg2_key_switch_batch_full_size():
