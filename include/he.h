@@ -359,8 +359,10 @@ int he_client_destroy(he_client* cl);
 /* Encodes n slot vectors at `scale` into plaintexts over q_0..q_level.  The
  * caller keeps scale * max |z_j| below 2^62 (M_k then fits a signed 64-bit
  * word; larger values give unspecified residues).  The embedding is a
- * double-precision FFT, so a coefficient can differ by 1 from an exact
- * evaluation of the sum when its value lies within rounding of a half. */
+ * double-precision FFT: while |scale m_k| < 2^52 a coefficient can differ by
+ * 1 from an exact evaluation of the sum, when its value lies within rounding
+ * of a half; above 2^52 the scaled value itself carries the FP64 spacing
+ * (2^(e - 52) at magnitude 2^e) and the difference is a few such units. */
 int he_encode(he_client* cl, uint32_t n, const double* slots_dev, double scale, uint32_t level,
               uint64_t* pt_dev);
 /* Public-key encryption at `level` (pk restricted to q_0..q_level):
