@@ -598,7 +598,7 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     return plan, ctx, runner, res
 
 
-def serving_leg(nets, rates, seconds, seed=21):
+def serving_leg(nets, rates, seconds, seed=21, window=4, per_network=False):
     """Poisson arrivals (total rate lambda, the superposition of 256 camera
     streams), 70% small-net / 30% large-net requests, keys and plaintexts
     resident, admission by device-memory footprint, continuous batching."""
@@ -619,7 +619,7 @@ def serving_leg(nets, rates, seconds, seed=21):
         times = serve.poisson_arrivals(rate, count, seed + int(rate))
         kinds = np.where(rng.random(count) < 0.7, "small", "large")
         reqs = [serve.Request(i, str(kinds[i]), payloads[str(kinds[i])][i % 4], float(times[i])) for i in range(count)]
-        sched = serve.Scheduler(backends, budget_bytes=budget, window=4)
+        sched = serve.Scheduler(backends, budget_bytes=budget, window=window, per_network=per_network)
         log(f"serving: {count} requests at {rate} req/s")
         serve.run_arrivals(sched, reqs, timeout_s=120)
         torch.cuda.synchronize()

@@ -74,10 +74,15 @@ class Dispatch:
 
 
 class Scheduler:
-    def __init__(self, backends: dict, budget_bytes: int, window: int = 3, clock=time.perf_counter):
+    def __init__(self, backends: dict, budget_bytes: int, window: int = 3, clock=time.perf_counter,
+                 per_network: bool = False):
+        """window: dispatches in flight, over all networks, or per network
+        when per_network is set (networks on their own streams then never
+        wait for a slot held by another network's batch)."""
         self.backends = backends
         self.budget = budget_bytes
         self.window = window
+        self.per_network = per_network
         self.clock = clock
         self.queue: collections.deque = collections.deque()     # arrived, not admitted
         self.active: dict = {k: [] for k in backends}           # admitted, unfinished
@@ -104,7 +109,7 @@ class Scheduler:
         self._retire()
         self._admit()
         n = 0
-        while len(self.inflight) < self.window:
+        while self.per_network or len(self.inflight) < self.window:
             d = self._pick()
             if d is None:
                 break
@@ -143,6 +148,8 @@ class Scheduler:
         network waiting at the same stage."""
         best = None
         for name, reqs in self.active.items():
+            if self.per_network and sum(d.backend == name for d in self.inflight) >= self.window:
+                continue
             for r in reqs:
                 if r.stage < len(self.backends[name].stages) and not self._busy(r):
                     if best is None or r.arrival < best.arrival:

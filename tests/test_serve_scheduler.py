@@ -216,3 +216,38 @@ def test_late_retirement_exports_once(net):
     assert sorted(r.rid for r in sched.done) == [0, 1, 2]
     for r in sched.done:
         assert np.array_equal(r.result.data, expected(net, inputs[r.rid]).data)
+
+
+@pytest.mark.parametrize("per_network", [False, True])
+def test_dispatch_window_global_or_per_network(net, per_network):
+    """window = 1: over all networks, one dispatch in flight at a time; per
+    network, each network (its own stream, here its own simulated device) keeps
+    one in flight, so both run at once.  Results bit for bit either way."""
+    clock = SimClock()
+    pr, o, keys, layers, _ = net
+    a = OracleBackend("small", o, keys, layers, clock, max_batch=2)
+    b = OracleBackend("large", o, keys, layers, clock, max_batch=2)
+    sched = serve.Scheduler({"small": a, "large": b}, budget_bytes=10 ** 9, window=1, clock=clock.now,
+                            per_network=per_network)
+    seen = []
+    step = sched.step
+
+    def recording_step():
+        n = step()
+        seen.append([d.backend for d in sched.inflight])
+        return n
+
+    sched.step = recording_step
+    reqs = requests(net, 6, [0.0] * 6)
+    for r in reqs[1::2]:
+        r.net = "large"
+    inputs = {r.rid: r.payload.copy() for r in reqs}
+    serve.run_arrivals(sched, reqs, clock=clock.now, sleep=clock.sleep)
+    assert len(sched.done) == 6 and all(r.error is None for r in sched.done)
+    for r in sched.done:
+        assert np.array_equal(r.result.data, expected(net, inputs[r.rid]).data)
+    if per_network:
+        assert max(len(s) for s in seen) == 2
+        assert all(s.count("small") <= 1 and s.count("large") <= 1 for s in seen)
+    else:
+        assert max(len(s) for s in seen) == 1
