@@ -534,6 +534,47 @@ def step_roofline(tab, steps, alu_ops_per_step=0):
                         for k, v in sorted(tab.items(), key=lambda kv: -kv[1][1])}}
 
 
+def pcie_inclusive(ctx, runner, plan, batch, step, steps):
+    """The batched step with the host interchange included: every input
+    ciphertext copied from pinned host memory in coefficient form and
+    converted on the device (he_ct_from_coeff_dev), the step, every output
+    converted back (he_ct_to_coeff_dev) and copied to pinned host memory, all
+    in order on the context's stream."""
+    import ctypes
+    import torch
+    from paper_2104_09164_amd import he
+    lib = he.lib()
+    ins, outs = runner.inputs[:batch], runner.outputs(batch)
+    host_in = [torch.from_numpy(ctx.export_ct(c).view(np.int64).reshape(-1).copy()).pin_memory() for c in ins]
+    dev_in = [torch.empty_like(h, device=ctx.device) for h in host_in]
+    ow = 2 * (outs[0].level + 1) * (1 << plan.log_n)
+    dev_out = [torch.empty(ow, dtype=torch.int64, device=ctx.device) for _ in outs]
+    host_out = [torch.empty(ow, dtype=torch.int64, pin_memory=True) for _ in outs]
+
+    def run():
+        for h, d, c in zip(host_in, dev_in, ins):
+            d.copy_(h, non_blocking=True)
+            cs = c._c()
+            rc = lib.he_ct_from_coeff_dev(ctx.h, ctypes.c_void_p(d.data_ptr()), c.level, c.scale, ctypes.byref(cs))
+            if rc:
+                raise he.HeError(rc, "he_ct_from_coeff_dev")
+        step()
+        for c, d, h in zip(outs, dev_out, host_out):
+            rc = lib.he_ct_to_coeff_dev(ctx.h, ctypes.byref(c._c()), ctypes.c_void_p(d.data_ptr()))
+            if rc:
+                raise he.HeError(rc, "he_ct_to_coeff_dev")
+            h.copy_(d, non_blocking=True)
+
+    run()
+    torch.cuda.synchronize()
+    t = time_events(run, steps)
+    ms = float(np.median(t))
+    in_mb = sum(h.numel() for h in host_in) * 8 / 1e6
+    out_mb = sum(h.numel() for h in host_out) * 8 / 1e6
+    return {"inferences_per_s": batch * 1000.0 / ms, "ms_per_step": ms, "host_to_device_mb": in_mb,
+            "device_to_host_mb": out_mb}
+
+
 def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=True, tuned_n1=True, trace=True):
     """Batched (graph replay) and plain (one request at a time) legs of one preset.
     A committed tuning file (paper_2104_09164_amd/tuning/<gfx>_<name>.json)
@@ -562,6 +603,8 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"{name}: PCIe-inclusive leg")
+    pcie = pcie_inclusive(ctx, runner, plan, batch, step, steps)
     log(f"{name}: plain leg")
     lat_eager = [float("nan")]
     if plain_n > 0:
@@ -592,6 +635,7 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
                       "lazy_moddown": [l.qp for l in plan.layers],
                       "rotate_sum_bits": [l.rs_bits for l in plan.layers]} if tuned else None}
     res["batched_over_plain"] = res["inferences_per_s"] / res["plain_inferences_per_s"]
+    res["pcie_inclusive"] = pcie
     if trace:
         log(f"{name}: traced eager pass")
         res["trace"] = trace_steps(ctx, runner, batch, steps)
@@ -713,6 +757,7 @@ def main():
                           "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
            "roofline": step_roofline(small.pop("trace"), args.steps, fused_ops(plan3, args.batch)),
            "plain_inferences_per_s": small["plain_inferences_per_s"],
+           "pcie_inclusive": small["pcie_inclusive"],
            "batched_over_plain": small["batched_over_plain"]}
     nets = {"small": (plan3, ctx3, args.batch)}
     if not args.no_tuning and not args.no_tuned_split:
