@@ -715,6 +715,8 @@ def main():
                          "setup, one untimed step, --steps traced steps")
     ap.add_argument("--client-only", action="store_true",
                     help="only the client encode/encrypt/decrypt leg (profiling runs)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large-net batched and plain legs (profiling runs)")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the NTT leg (profiling runs), preceded by a 1 GiB device copy whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -726,6 +728,11 @@ def main():
     import torch
     if args.client_only:
         print(json.dumps({"client": client_leg()}), flush=True)
+        return 0
+    if args.large_only:
+        _, _, _, large = network_legs("cfg4", args.large_batch, max(3, args.steps // 2), 1, max(3, args.plain // 2),
+                                      graph=not args.no_graph, use_tuning=not args.no_tuning, trace=False)
+        print(json.dumps({"large_net": large}), flush=True)
         return 0
     if args.ntt_only:
         calibration_copy()
