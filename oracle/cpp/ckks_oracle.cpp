@@ -139,15 +139,21 @@ static u64 uniform_mod(SplitMix64& g, u64 q) {
 static i64 ternary(SplitMix64& g) {
   for (;;) { u64 v = g.next() & 3; if (v != 3) return (i64)v - 1; }
 }
-// Rounded Gaussian, sigma = 3.2, Box-Muller (one output per pair), |e| <= 19.
-static i64 gaussian(SplitMix64& g) {
+// Error distribution of keys and encryptions (a reading: the paper names only
+// 128-bit security): rounded Gaussian of standard deviation 3.2, draws with
+// |e| > 19 (about 6 sigma) rejected.
+static const double kErrSigma = 3.2;
+static const i64 kErrBound = 19;
+// Rounded Gaussian by Box-Muller (one output per pair of uniforms), rejected
+// and redrawn while |e| > bound.
+static i64 gaussian(SplitMix64& g, double sigma, i64 bound) {
   const double two_pi = 6.283185307179586476925286766559;
   for (;;) {
     double u1 = (double)((g.next() >> 11) + 1) * 0x1.0p-53;    // (0, 1]
     double u2 = (double)(g.next() >> 11) * 0x1.0p-53;          // [0, 1)
-    double x = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2) * 3.2;
+    double x = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2) * sigma;
     double r = x < 0 ? -std::floor(-x + 0.5) : std::floor(x + 0.5);
-    if (std::fabs(r) <= 19.0) return (i64)r;
+    if (std::fabs(r) <= (double)bound) return (i64)r;
   }
 }
 
@@ -169,7 +175,20 @@ u64 orc_psi(void* h, int prime_index) { return ((Ctx*)h)->tab[prime_index].psi; 
 
 // ---------------------------------------------------------------- sampling
 void orc_sample_ternary(u64 seed, int n, i64* out) { SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = ternary(g); }
-void orc_sample_gaussian(u64 seed, int n, i64* out) { SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = gaussian(g); }
+void orc_sample_gaussian(u64 seed, int n, i64* out) {
+  SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = gaussian(g, kErrSigma, kErrBound);
+}
+// The same sampler at any standard deviation and bound (distribution tests).
+void orc_sample_gaussian_sb(u64 seed, int n, double sigma, i64 bound, i64* out) {
+  SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = gaussian(g, sigma, bound);
+}
+void orc_noise_params(double* sigma, i64* bound) { *sigma = kErrSigma; *bound = kErrBound; }
+// Uniform words modulo any q >= 1 (distribution tests of the rejection rule).
+void orc_sample_uniform_q(u64 seed, int n, u64 q, u64* out) {
+  SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = uniform_mod(g, q);
+}
+// Raw generator outputs (published test vectors).
+void orc_splitmix_stream(u64 seed, int n, u64* out) { SplitMix64 g(seed); for (int i = 0; i < n; ++i) out[i] = g.next(); }
 // Uniform residues for the listed primes, limb by limb, coefficient by coefficient.
 void orc_sample_uniform(void* h, u64 seed, int nl, const int* prime_idx, u64* out) {
   Ctx& c = *(Ctx*)h; SplitMix64 g(seed);
