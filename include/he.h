@@ -235,10 +235,23 @@ int he_eval_linear(he_ctx* ctx, const he_ct* in, const he_linear* t, void* scrat
 int he_eval_linear_batch(he_ctx* ctx, uint32_t n_req, const he_ct* in, const he_linear* t, void* scratch,
                          size_t scratch_bytes, he_ct* out);
 
-/* Ciphertext import/export.  *_import: host coefficient form -> inout->dev
- * (caller sets inout->dev; level and scale are written).  *_export: blocking
- * (synchronises the stream), writes host coefficient form [2][level+1][N].
- * The _dev variants take device coefficient buffers and are asynchronous. */
+/* Ciphertext import/export: the encrypted input a user sends to the cloud and
+ * the single encrypted result it returns (Methods, "Data encryption": one
+ * ciphertext holds the whole padded, replicated input; Results, the three-party
+ * protocol: the cloud returns one ciphertext to the monitoring service).
+ * he_ct_import: coeff_host = host uint64[2][level+1][N] coefficient residues,
+ * each below its prime (not checked: larger words give unspecified residues),
+ * level <= L (HE_ELEVEL otherwise); scale is stored as given.  The caller sets
+ * inout->dev (>= he_ct_bytes(ctx, level), device, caller-owned); the call
+ * converts to NTT form into it and writes inout->level and inout->scale.
+ * Blocking (returns after the stream has finished the conversion).
+ * he_ct_export: writes host coefficient form [2][level+1][N] to coeff_host
+ * (caller-owned); needs a bound workspace (HE_ESTATE; the conversion is
+ * staged there); blocking (synchronises the stream, so device faults of
+ * earlier calls surface here as HE_EDEVICE).  The _dev variants take
+ * caller-owned device coefficient buffers of the same layout and are
+ * asynchronous (enqueued on the context's stream; the caller keeps the
+ * buffers alive until the stream reaches them). */
 int he_ct_import(he_ctx* ctx, const uint64_t* coeff_host, uint32_t level, double scale, he_ct* inout);
 int he_ct_export(he_ctx* ctx, const he_ct* ct, uint64_t* coeff_host);
 int he_ct_from_coeff_dev(he_ctx* ctx, const uint64_t* coeff_dev, uint32_t level, double scale, he_ct* inout);
@@ -252,20 +265,42 @@ int he_ct_to_coeff_dev(he_ctx* ctx, const he_ct* ct, uint64_t* coeff_dev);
  * out->scale = in->scale * pt_scale; out->level = in->level.
  * Needs rotation keys for every step used.  out->dev must not alias in->dev. */
 int he_eval_dense(he_ctx* ctx, const he_ct* in, const he_dense* layer, he_ct* out);
-/* Square with relinearisation: (c0^2, 2 c0 c1, c1^2), key switch of c1^2 with
- * the relinearisation key, added.  out->scale = scale^2.  No rescale. */
+/* Square with relinearisation: the activation between dense layers (Methods,
+ * "Non-convolutional layers": the activation is a polynomial of degree 2;
+ * x^2 here, a x^2 + b x + c folded into the neighbouring dense layers by the
+ * caller).  (c0^2, 2 c0 c1, c1^2), then the hybrid key switch of c1^2 with
+ * the relinearisation key (s' = s^2; ModUp of its digits, inner product,
+ * ModDown), added to (c0^2, 2 c0 c1).  out->scale = in->scale^2, out->level =
+ * in->level; no rescale (lazy rescaling, the caller rescales once).
+ * in, out: caller-owned device ciphertexts at one level (out->dev sized for
+ * it; out may not alias in).  HE_ENOKEY without a relinearisation key,
+ * HE_ESTATE without a bound workspace, HE_EINVAL for null pointers. */
 int he_square(he_ctx* ctx, const he_ct* in, he_ct* out);
-/* Left rotation by step (rho^step): ModUp(c1), automorphism of every digit,
- * key inner product, ModDown, + automorphism of c0.  step = 0 mod N/2 copies. */
+/* Left slot rotation by step, rho^step (Methods, "Single-channel homomorphic
+ * convolutions": rho rotates the slot vector left; rotations use the
+ * rotation key of that amount, the hybrid RNS key switch of "Algorithmic and
+ * cryptographic optimizations"): ModUp(c1), automorphism X -> X^(5^step) of
+ * every extended digit, key inner product over Q_l u P, ModDown, plus the
+ * automorphism of c0.  step = 0 mod N/2 copies.  Scale and level unchanged.
+ * HE_ENOKEY if no key for step was loaded; out must not alias in. */
 int he_rotate(he_ctx* ctx, const he_ct* in, int32_t step, he_ct* out);
-/* Hoisted rotations of one ciphertext by steps[0..n_steps): one ModUp shared
- * by all (Methods, hoisting); out[u] = rho^steps[u](in), bit-identical to
- * he_rotate(in, steps[u]). */
+/* Hoisted rotations of one ciphertext by steps[0..n_steps) (Methods,
+ * "Algorithmic and cryptographic optimizations", hoisting: the decomposition
+ * and base extension of c1 are common to every rotation of one ciphertext, so
+ * they are computed once): one ModUp shared by all; out[u] =
+ * rho^steps[u](in), bit-identical to he_rotate(in, steps[u]).  out: n_steps
+ * caller-owned device ciphertexts at in's level, none aliasing in. */
 int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, uint32_t n_steps, const int32_t* steps, he_ct* out);
-/* Rescale by q_level: c_i <- (c_i - (c_level mod q_i)) q_level^{-1} mod q_i
- * (floor form), level - 1, scale / q_level.  out may alias in. */
+/* Rescale by q_level (Methods, "Algorithmic and cryptographic
+ * optimizations", lazy rescaling: once per dense layer and once per square):
+ * c_i <- (c_i - (c_level mod q_i)) q_level^{-1} mod q_i (floor form, c_level
+ * the coefficient-form residue in [0, q_level)), level - 1, scale / q_level.
+ * out may alias in.  HE_ELEVEL at level 0. */
 int he_rescale(he_ctx* ctx, const he_ct* in, he_ct* out);
-/* Limb-wise sum of two ciphertexts at equal level and scale. */
+/* Limb-wise sum of two ciphertexts at equal level and scale (the sums of the
+ * convolution and dense equations of Methods, "Single-channel homomorphic
+ * convolutions").  HE_ELEVEL for different levels, HE_ESCALE for scales
+ * further apart than 2^-30 relative; out may alias a or b. */
 int he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out);
 
 /* Batched forms: n <= HE_MAX_BATCH independent ciphertexts (e.g. from

@@ -272,6 +272,27 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------------- GPU
+SCALE_RTOL_LOG2 = -30      # the library's rule: operand scales agree within a relative 2^-30
+
+
+def check_payload(plan, payload) -> None:
+    """Rejects a request input that would fail a whole batched launch: the
+    batched entry points check level and scale over every item of a call
+    (HE_ELEVEL / HE_ESCALE for all of them), so an input at another level or
+    scale must be refused when it is admitted, where it fails only its own
+    request.  payload = (coefficient-form residues [2][L+1][N] uint64, level,
+    scale); raises ValueError."""
+    coeff, level, scale = payload
+    N = 1 << plan.log_n
+    if level != plan.L:
+        raise ValueError(f"input at level {level}, the network starts at level {plan.L}")
+    a = np.asarray(coeff)
+    if a.dtype != np.uint64 or a.shape != (2, plan.L + 1, N):
+        raise ValueError(f"input array {a.dtype} {a.shape}, expected uint64 {(2, plan.L + 1, N)}")
+    if not (np.isfinite(scale) and abs(scale - plan.scale) <= np.ldexp(abs(plan.scale), SCALE_RTOL_LOG2)):
+        raise ValueError(f"input scale {scale!r}, the network expects {plan.scale!r}")
+
+
 class NetBackend(Backend):
     """One encrypted network on the HIP library: slot pool of device
     ciphertext buffers for every stage, batched launches, async import/export."""
@@ -336,6 +357,7 @@ class NetBackend(Backend):
             return self._export(slot)
 
     def _load(self, slot, payload):
+        check_payload(self.plan, payload)
         coeff, level, scale = payload
         b = self.bufs[slot]
         host = self.torch.from_numpy(np.ascontiguousarray(coeff).view(np.int64).reshape(-1))

@@ -56,3 +56,33 @@ def test_serving_mix_equals_alone_and_oracle():
         assert np.array_equal(s1.done[0].result[0], mixed[r][0])
     m = sched.metrics()
     assert m["completed"] == count and m["p99_ms"] >= m["p50_ms"] > 0
+
+
+def test_bad_scale_request_fails_alone():
+    """One request of a batch carries a wrong scale: it fails at admission
+    and every other request of the mix still completes, bit for bit equal to
+    the oracle."""
+    pr = params.make(12, [50, 40, 40, 40, 40], [50, 50], 2, 30)
+    shapes = [(8, 64, 4), (2, 8, 2)]
+    o, keys, lays, be = build(pr, shapes, 30, max_batch=4, slots=6)
+    count, bad = 8, 3
+    cts = []
+    for r in range(count):
+        x = synth.request_input(shapes[0][1], r)
+        cts.append(o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r)))
+    reqs = []
+    for r in range(count):
+        scale = cts[r].scale * (1.5 if r == bad else 1.0)
+        reqs.append(serve.Request(r, "small", (cts[r].data, cts[r].level, scale), 0.0))
+    sched = serve.Scheduler({"small": be}, budget_bytes=8 * be.slot_bytes, window=3)
+    serve.run_arrivals(sched, reqs, timeout_s=120)
+    done = {r.rid: r for r in sched.done}
+    assert len(done) == count
+    assert done[bad].error is not None and "scale" in done[bad].error
+    assert max(s for _, _, s in sched.batches) > 1
+    for r in range(count):
+        if r == bad:
+            continue
+        assert done[r].error is None
+        want = o.eval_network(cts[r], lays, keys)
+        assert np.array_equal(done[r].result[0], want.data), f"request {r} differs from the oracle"

@@ -251,3 +251,25 @@ def test_dispatch_window_global_or_per_network(net, per_network):
         assert all(s.count("small") <= 1 and s.count("large") <= 1 for s in seen)
     else:
         assert max(len(s) for s in seen) == 1
+
+
+def test_check_payload_rejects_what_fails_a_batch():
+    """A request input at another level, scale or shape is refused at
+    admission (it would make the batched launch fail for every request in
+    it); a valid one passes."""
+    from paper_2104_09164_amd import netplan
+    pr = params.make(10, [50, 40, 40, 40, 40], [50, 50], 2, 30)
+    npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, 30, [(8, 64, 4), (2, 8, 2)])
+    N, L = pr.n, pr.L
+    good = np.zeros((2, L + 1, N), dtype=np.uint64)
+    serve.check_payload(npl, (good, L, npl.scale))
+    serve.check_payload(npl, (good, L, npl.scale * (1 + 2.0 ** -32)))
+    bad = [(good, L - 1, npl.scale),                                # level
+           (good, L, npl.scale * (1 + 2.0 ** -20)),                 # scale beyond 2^-30 relative
+           (good, L, float("nan")),
+           (good[:, :L], L, npl.scale),                             # limbs
+           (good.astype(np.int64), L, npl.scale),                   # dtype
+           (np.zeros((2, L + 1, N // 2), dtype=np.uint64), L, npl.scale)]
+    for b in bad:
+        with pytest.raises(ValueError):
+            serve.check_payload(npl, b)
