@@ -65,6 +65,9 @@ def lib():
         L.orc_splitmix_first.restype = C.c_uint64
         L.orc_splitmix_first.argtypes = [C.c_uint64]
         L.orc_polymul.argtypes = [C.c_void_p, C.c_int, I32P, U64P, U64P, U64P]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = [C.c_int]
+        L.orc_ntt_roundtrip.argtypes = [C.c_void_p, C.c_int, I32P, U64P]
         L.orc_automorph.argtypes = [C.c_void_p, C.c_int, I32P, C.c_uint64, U64P, U64P]
         L.orc_keygen_public.argtypes = [C.c_void_p, I64P, C.c_uint64, U64P]
         L.orc_keygen_switch.argtypes = [C.c_void_p, I64P, U64P, C.c_uint64, U64P]
@@ -375,11 +378,15 @@ class Oracle:
                 level -= 1
         return layers
 
-    def eval_network(self, ct: Ciphertext, layers: list, keys: Keys) -> Ciphertext:
+    def eval_network(self, ct: Ciphertext, layers: list, keys: Keys, progress=None) -> Ciphertext:
+        """progress: optional callable(layer index) after each layer (long runs
+        report that they are alive)."""
         for li, lay in enumerate(layers):
             ct = self.rescale(self.dense(ct, lay, keys))
             if li + 1 < len(layers):
                 ct = self.rescale(self.square(ct, keys))
+            if progress is not None:
+                progress(li)
         return ct
 
 

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <vector>
 #include <stdexcept>
+#include <omp.h>
 
 typedef uint64_t u64;
 typedef int64_t i64;
@@ -100,16 +101,26 @@ static void cyclic_ntt(std::vector<u64>& a, const std::vector<u64>& wp, u64 q, i
   }
 }
 
+// Negacyclic transform of one limb-poly in place: twist by psi^i, then the
+// cyclic transform (evaluation at the odd powers of psi); and its inverse.
+static void nega_forward(const Ctx& c, const NttTables& t, std::vector<u64>& A) {
+  for (int i = 0; i < c.N; ++i) A[i] = mulmod(A[i], t.psi_pow[i], t.q);
+  cyclic_ntt(A, t.w_pow, t.q, c.N, c.logN);
+}
+static void nega_inverse(const Ctx& c, const NttTables& t, std::vector<u64>& A) {
+  cyclic_ntt(A, t.w_inv_pow, t.q, c.N, c.logN);
+  for (int i = 0; i < c.N; ++i) A[i] = mulmod(mulmod(A[i], t.n_inv, t.q), t.psi_inv_pow[i], t.q);
+}
+
 // out = a * b mod (X^N + 1, q): twist by psi^i, cyclic convolution, untwist.
 static void polymul(const Ctx& c, int pi, const u64* a, const u64* b, u64* out) {
   const NttTables& t = c.tab[pi]; const int N = c.N; const u64 q = t.q;
-  std::vector<u64> A(N), B(N);
-  for (int i = 0; i < N; ++i) { A[i] = mulmod(a[i], t.psi_pow[i], q); B[i] = mulmod(b[i], t.psi_pow[i], q); }
-  cyclic_ntt(A, t.w_pow, q, N, c.logN);
-  cyclic_ntt(B, t.w_pow, q, N, c.logN);
+  std::vector<u64> A(a, a + N), B(b, b + N);
+  nega_forward(c, t, A);
+  nega_forward(c, t, B);
   for (int i = 0; i < N; ++i) A[i] = mulmod(A[i], B[i], q);
-  cyclic_ntt(A, t.w_inv_pow, q, N, c.logN);
-  for (int i = 0; i < N; ++i) out[i] = mulmod(mulmod(A[i], t.n_inv, q), t.psi_inv_pow[i], q);
+  nega_inverse(c, t, A);
+  std::memcpy(out, A.data(), N * sizeof(u64));
 }
 
 // Prime index of limb 'i' in a basis "q_0..q_l then p_0..p_{K-1}".
@@ -195,6 +206,22 @@ void orc_sample_uniform(void* h, u64 seed, int nl, const int* prime_idx, u64* ou
   for (int l = 0; l < nl; ++l) { u64 q = c.primes[prime_idx[l]]; for (int k = 0; k < c.N; ++k) out[(size_t)l * c.N + k] = uniform_mod(g, q); }
 }
 u64 orc_derive_seed(u64 master, u64 tag) { return derive_seed(master, tag); }
+
+// Threads of the OpenMP loops (limbs of the polynomial products); 0 = query.
+int orc_threads(int n) { if (n > 0) omp_set_num_threads(n); return omp_get_max_threads(); }
+
+// Forward then inverse negacyclic transform of nl limb-polys in place (the
+// transforms inside every polynomial product; timed by the CPU baseline).
+void orc_ntt_roundtrip(void* h, int nl, const int* prime_idx, u64* a) {
+  Ctx& c = *(Ctx*)h; const size_t N = c.N;
+  #pragma omp parallel for schedule(dynamic)
+  for (int l = 0; l < nl; ++l) {
+    std::vector<u64> A(a + l * N, a + (l + 1) * N);
+    nega_forward(c, c.tab[prime_idx[l]], A);
+    nega_inverse(c, c.tab[prime_idx[l]], A);
+    std::memcpy(a + l * N, A.data(), N * sizeof(u64));
+  }
+}
 u64 orc_splitmix_first(u64 seed) { SplitMix64 g(seed); return g.next(); }
 
 // --------------------------------------------------- polynomial primitives
