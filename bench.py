@@ -1,32 +1,40 @@
-"""Benchmark: encrypted inferences/s of the small dense net, batched vs plain.
+"""Benchmark: encrypted inferences/s of the large dense net, batched vs plain.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--large-batch B]
-                [--serve-rates 50,200,400] [--no-large] [--no-serve] [--no-ntt] [--no-ks] [--no-conv] [--no-client] [--no-cpu]
+                [--serve-rates 50,100,200,300,400] [--serve-requests 2000] [--serve-requests-top 10000]
+                [--no-small] [--no-serve] [--no-ntt] [--no-ks] [--no-conv] [--no-client] [--no-cpu] ...
 
-One step = one batched encrypted inference of B requests through the whole
-small network (N=2^15; dense 1024->128 with 32 baby steps -> rescale ->
-square -> rescale -> dense 128->2 -> rescale; every dense layer = hoisted
-baby-step rotations,
-MultPlain inner sums, giant-step and rotate-and-sum key switches, bias),
-replayed from a captured HIP graph, inputs resident in HBM.  `value` is that
-leg's inferences/s.  Reported beside it, in the same JSON line:
-  * plain one-request-at-a-time inferences/s and p50/p99 latency (a batch of
-    one replayed from its own graph; the eager-launch latency beside it);
-  * the small net again with the autotuner's baby-step counts;
-  * the same two legs for the large network (N=2^16, 4096->256->64->2);
-  * serving: Poisson arrivals at several rates, 70% small / 30% large
-    requests, continuous batching, p50/p99 from arrival to exported result;
+One step = one batched encrypted inference of B = 32 requests through the
+whole large network (N=2^16, 11 limbs, P = 3 x 60b; dense 4096->256 ->
+rescale -> square -> rescale -> dense 256->64 -> rescale -> square -> rescale
+-> dense 64->2 -> rescale; every dense layer = hoisted baby-step rotations,
+MultPlain inner sums, giant-step and rotate-and-sum key switches, bias, in the
+committed tuned plan), replayed from a captured HIP graph, inputs resident in
+HBM.  `value` is that leg's inferences/s.  Reported beside it, in the same
+JSON line:
+  * plain one-request-at-a-time inferences/s and p50/p99 latency of the large
+    net (a batch of one replayed from its own graph; eager launches beside it);
+  * the small net (N=2^15, 1024->128->2, 16 per launch) batched and plain,
+    with its own roofline, and with the autotuner's baby-step counts;
+  * the plain RNS-CKKS request (N=2^13, 256->64->2): one request at a time,
+    p50/p99;
+  * serving: Poisson arrivals at five rates, 70% small / 30% large requests,
+    continuous batching, p50/p99 from arrival to exported result;
   * the NTT micro-benchmark (64 ciphertexts x 2 x 24 limbs at N=2^16,
     forward + inverse) in algorithmic HBM GB/s;
   * the key-switch micro-benchmark (the same 64 ciphertexts' shape, dnum = 3,
-    32 random rotation steps) in key switches/s, with its kernel classes;
-  * the roofline of the step's dominant kernel class: the same step run
-    eagerly with the library tracer on (HIP events around every launch on the
-    library stream, algorithmic bytes per launch), plus the NTT leg's;
-  * the CPU oracle on a bounded sample, scaled to inferences/s.
+    32 random rotation steps; hoisted: one ModUp per ciphertext), with the
+    whole pass's HBM roofline and its dominant kernel class;
+  * the roofline of the headline step's dominant kernel class: the same step
+    run eagerly with the library tracer on (HIP events around every launch on
+    the library stream, algorithmic bytes per launch), plus the NTT leg's;
+  * the CPU oracle, untuned, timed end to end on this host: one large-net
+    request (cpu_baseline), and in cpu_protocol the small net (median of 3),
+    the plain request at 1 thread and at all threads (median of 3) and the
+    oracle's NTT throughput, with the CPU model and thread counts.
 Inputs are seeded uniform residues (keys, plaintext diagonals, ciphertexts):
 every kernel's work and memory traffic is independent of the residue values,
-and the arithmetic of exactly this call sequence is checked bit for bit
+and the arithmetic of exactly these call sequences is checked bit for bit
 against the oracle by the GPU tests.
 """
 from __future__ import annotations
@@ -293,9 +301,21 @@ def client_leg(reps=10, R=16):
 def ks_leg(reps=3, items=64, n_steps=32):
     """Kernel micro-benchmark, key switching: 64 ciphertexts at N=2^16 with 24
     limbs of 50-bit primes, hybrid key switching with dnum = 3 (8 special
-    primes), rotated by each of 32 random steps (every rotation a full key
-    switch: ModUp, inner product, ModDown).  Rotation keys are resident
-    (32 keys x 3 digits x 2 x 32 limbs x 2^16 words = 3.2 GB)."""
+    primes), every ciphertext rotated by each of 32 random steps.
+
+    Hoisted (the paper's hoisting, Methods "Algorithmic and cryptographic
+    optimizations": the decomposition and base extension of c1 are common to
+    every rotation of one ciphertext): one he_rotate_hoisted_batch call per
+    pass, one ModUp per ciphertext for all 32 steps, then per step the inner
+    product, ModDown and epilogue of all 64 ciphertexts; 2048 output
+    ciphertexts (48 GiB) written.  Per step (the second figure): one call per
+    step, so every (ciphertext, step) pays its own ModUp.  Rotation keys are
+    resident (32 keys x 3 digits x 2 x 32 limbs x 2^16 words, with their
+    Shoup companions 6.4 GB).
+
+    Whole-pass HBM roofline of the hoisted pass: the algorithmic bytes of the
+    whole pass (read the 64 ciphertexts and the 32 keys once, write the 2048
+    rotated ciphertexts) over its time, against 8 TB/s."""
     import torch
     from paper_2104_09164_amd import he, synth
     log_n, limbs, K = 16, 24, 8
@@ -319,27 +339,44 @@ def ks_leg(reps=3, items=64, n_steps=32):
         ct.buf.view(2, limbs, N).copy_(torch.randint(0, 2 ** 62, (2, limbs, N), device="cuda", generator=g,
                                                      dtype=torch.int64) % qt)
         cts.append(ct)
-    outs = [ctx.new_ct(limbs - 1) for _ in range(items)]
+    outs_all = [ctx.new_ct(limbs - 1) for _ in range(items * n_steps)]
 
-    def run():
+    def hoisted():
+        ctx.rotate_hoisted_batch(cts, steps, outs_all)
+    outs = outs_all[:items]
+
+    def per_step():
         for st in steps:
             ctx.rotate_hoisted_batch(cts, [st], outs)
-    run()
+    res = {}
+    for name, fn in (("hoisted", hoisted), ("per_step", per_step)):
+        fn()
+        torch.cuda.synchronize()
+        ms = float(np.median(time_events(fn, reps)))
+        ctx.trace_read()
+        ctx.set_knob("trace", 1)
+        fn()
+        tab = ctx.trace_read()
+        ctx.set_knob("trace", 0)
+        res[name] = {"key_switches_per_s": items * n_steps / (ms * 1e-3), "ms_per_pass": ms,
+                     "modups_per_pass": items if name == "hoisted" else items * n_steps,
+                     "dominant_class": step_roofline(tab, 1)}
+    ct_bytes = 2 * limbs * N * 8
+    key_bytes = n_steps * dnum * 2 * (limbs + K) * N * 8
+    alg = items * ct_bytes + key_bytes + items * n_steps * ct_bytes
+    ms = res["hoisted"]["ms_per_pass"]
+    achieved = alg / (ms * 1e-3) / 1e9
+    out = {"workload": (f"{items} ct x N=2^16, 24 x 50-bit limbs, dnum={dnum} (8 x 50-bit special primes), "
+                        f"{n_steps} random rotation steps; hoisted: one ModUp per ciphertext for all steps"),
+           "key_switches_per_s": res["hoisted"]["key_switches_per_s"], "ms_per_pass": ms,
+           "hoisted": res["hoisted"], "per_step": res["per_step"],
+           "roofline": {"bound": "hbm", "scope": "whole hoisted pass (every launch of one call)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_pass": alg,
+                        "alg_bytes_note": "read 64 ciphertexts and 32 keys once, write 2048 rotated ciphertexts"}}
+    del ctx, cts, outs, outs_all
     torch.cuda.synchronize()
-    t = time_events(run, reps)
-    ms = float(np.median(t))
-    ctx.trace_read()
-    ctx.set_knob("trace", 1)
-    run()
-    tab = ctx.trace_read()
-    ctx.set_knob("trace", 0)
-    res = {"workload": (f"{items} ct x N=2^16, 24 x 50-bit limbs, dnum={dnum} (8 x 50-bit special primes), "
-                        f"{n_steps} random rotation steps, one full key switch per (ct, step)"),
-           "key_switches_per_s": items * n_steps / (ms * 1e-3), "ms_per_pass": ms,
-           "roofline": step_roofline(tab, 1)}
-    del ctx, cts, outs
-    torch.cuda.synchronize()
-    return res
+    return out
 
 
 def ntt_roofline(nt):
@@ -366,46 +403,94 @@ def ntt_roofline(nt):
             "traffic": traffic, "alg_bytes": alg, "ms_per_call": t_call * 1e3}
 
 
-def cpu_baseline(plan, budget_s=20.0):
-    """The oracle, untuned, on a bounded sample at the same ring and primes:
-    timed key switch (rotation), MultPlain, square and rescale on one request,
-    weighted by the per-inference operation counts of `plan`."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_inference_times(plan, threads, runs, seed=3):
+    """The oracle (untuned) evaluating one request end to end through `plan`
+    (the same layers, baby-step splits, lazy-ModDown flags and rotate-and-sum
+    groups the GPU ran): dense -> rescale -> square -> rescale -> ... ->
+    dense -> rescale.  Evaluation only: keys, plaintext diagonals, biases and
+    the input ciphertext are random residues of their real shapes (the
+    oracle's work does not depend on the values).  Returns (seconds per run,
+    OpenMP threads used)."""
     from oracle import ckks, params as oparams
     from paper_2104_09164_amd import synth
-    pr = oparams.Params(plan.log_n, plan.q, plan.p, plan.alpha, int(np.log2(plan.scale)))
+    L = ckks.lib()
+    used = L.orc_threads(threads)
+    pr = oparams.Params(plan.log_n, plan.q, plan.p, plan.alpha, int(round(np.log2(plan.scale))))
     o = ckks.Oracle(pr)
     N = 1 << plan.log_n
-    key = synth.uniform_residues(plan.q + plan.p, N, (plan.dnum, 2), seed=3)
-    keys = ckks.Keys(None, None, key, {1: key})
-    ct = ckks.Ciphertext(synth.uniform_residues(plan.q, N, (2,), seed=4), plan.L, plan.scale)
-    t = {}
-    t0 = time.perf_counter()
-    o.rotate(ct, 1, keys)
-    t["ks"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o.mult_plain(ct, ct.data[0], plan.scale)
-    t["mp"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o.rescale(ct)
-    t["rs"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o.square(ct, keys)
-    t["sq"] = time.perf_counter() - t0
-    reps = 1
-    while time.perf_counter() - t0 < budget_s * 0.5 and reps < 4:
-        t1 = time.perf_counter()
-        o.rotate(ct, 1, keys)
-        t["ks"] = min(t["ks"], time.perf_counter() - t1)
-        reps += 1
-    c = plan.op_counts()
-    per_inf = (c["key_switches"] - c["squares"]) * t["ks"] + c["squares"] * t["sq"] + c["multplain"] * t["mp"] \
-        + c["rescales"] * t["rs"]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / per_inf, "unit": "inferences/s", "cores": threads, "kind": "oracle",
-            "sample": (f"one request at the same ring and primes (top level): key switch {t['ks']:.2f}s, "
-                       f"MultPlain {t['mp']:.3f}s, square {t['sq']:.2f}s, rescale {t['rs']:.3f}s, weighted by "
-                       f"{c['key_switches']} key switches, {c['multplain']} MultPlain, {c['rescales']} rescales "
-                       f"per inference (est. {per_inf:.1f} s/inference)")}
+    key = synth.uniform_residues(plan.q + plan.p, N, (plan.dnum, 2), seed)
+    keys = ckks.Keys(None, None, key, {s: key for s in plan.steps()})
+    lays = []
+    for li, lay in enumerate(plan.layers):
+        primes = plan.q[: lay.level + 1] + (plan.p if lay.qp else [])
+        one = synth.uniform_residues(primes, N, (), seed + 10 + li)
+        pts = np.ascontiguousarray(np.broadcast_to(one, (lay.m,) + one.shape))
+        bias = synth.uniform_residues(plan.q[: lay.level + 1], N, (), seed + 20 + li)
+        lays.append(ckks.DenseLayer(lay.m, lay.n, lay.n1, lay.level, pts, bias, lay.pt_scale, lay.bias_scale,
+                                    lay.qp, lay.rs_bits))
+    ct = ckks.Ciphertext(synth.uniform_residues(plan.q, N, (2,), seed + 30), plan.L, plan.scale)
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        o.eval_network(ct, lays, keys, progress=lambda li: log(f"  oracle layer {li} done"))
+        ts.append(time.perf_counter() - t0)
+    del lays, keys, o
+    return ts, used
+
+
+def oracle_ntt_gbs(threads, reps=3):
+    """The oracle's negacyclic transform, forward then inverse, on one
+    ciphertext of the key-switch ring (2 x 24 limbs of 50-bit primes at 2^16)
+    in algorithmic GB/s (one read and one write of every word per transform)."""
+    import ctypes as C
+    from oracle import ckks, params as oparams
+    from paper_2104_09164_amd import he, synth
+    L = ckks.lib()
+    used = L.orc_threads(threads)
+    q, p = he.prime_chain(16, [50] * 24, [50] * 8)
+    o = ckks.Oracle(oparams.Params(16, q, p, 8, 40))
+    a = np.ascontiguousarray(synth.uniform_residues(q, 1 << 16, (2,), 17).reshape(48, 1 << 16))
+    idx = np.array(list(range(24)) * 2, dtype=np.int32)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        L.orc_ntt_roundtrip(o._h, 48, idx.ctypes.data_as(C.POINTER(C.c_int)), a.ctypes.data_as(C.POINTER(C.c_uint64)))
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    alg = 2 * 48 * (1 << 16) * 8 * 2
+    return {"workload": "1 ct x 2 x 24 limbs x 2^16 (50-bit primes), forward + inverse", "threads": used,
+            "s_per_roundtrip": t, "gbs": alg / t / 1e9, "alg_bytes": alg}
+
+
+def cpu_protocol(plans, gpu_plans_note):
+    """The oracle timed on this host's cores: the large net once at all
+    threads (the headline workload), the small net at all threads (median of
+    3), the plain-request net at 1 thread and at all threads (median of 3),
+    and the oracle's NTT throughput."""
+    nproc = os.cpu_count() or 1
+    out = {"cpu_model": cpu_model(), "nproc": nproc, "plans": gpu_plans_note}
+    for name, runs, threads in (("cfg1", 3, (1, nproc)), ("cfg3", 3, (nproc,)), ("cfg4", 1, (nproc,))):
+        r = {}
+        for th in threads:
+            log(f"cpu baseline: oracle {name}, {th} thread(s), {runs} run(s)")
+            ts, used = oracle_inference_times(plans[name], th, runs)
+            r[f"threads_{used}"] = {"s_per_inference": float(np.median(ts)), "runs_s": ts,
+                                    "inferences_per_s": 1.0 / float(np.median(ts)),
+                                    "statistic": "median of 3" if runs == 3 else "single run"}
+        out[name] = r
+    log("cpu baseline: oracle NTT")
+    out["ntt"] = oracle_ntt_gbs(nproc)
+    return out
 
 
 KERNEL_LABEL = {
@@ -441,10 +526,11 @@ def trace_steps(ctx, runner, batch, steps):
     return tab
 
 
-def traffic_record(kernel, launches_per_step):
-    """rocprofv3 FETCH_SIZE/WRITE_SIZE of one kernel class, per launch, from
-    profiles/; dropped unless taken on the current sources of the evaluation
-    kernels (every file under csrc/ but the client path's client.hip)."""
+def traffic_record(kernel, launches_per_step, workload="cfg4"):
+    """rocprofv3 FETCH_SIZE/WRITE_SIZE of one kernel class of one workload's
+    step, per launch, from profiles/; dropped unless taken on the current
+    sources of the evaluation kernels (every file under csrc/ but the client
+    path's client.hip)."""
     import hashlib
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", "roofline_traffic.json")))
@@ -452,10 +538,10 @@ def traffic_record(kernel, launches_per_step):
         for f in sorted(os.listdir(os.path.join(ROOT, "paper_2104_09164_amd", "csrc"))):
             if f != "client.hip":
                 h.update(open(os.path.join(ROOT, "paper_2104_09164_amd", "csrc", f), "rb").read())
-        rec = prof.get("kernels", {}).get(kernel)
-        if (rec and prof["csrc_sha256"] == h.hexdigest()
-                and rec["launches_per_step"] == launches_per_step):
-            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        rec = prof.get("workloads", {}).get(workload, {})
+        k = rec.get("kernels", {}).get(kernel)
+        if k and rec["csrc_sha256"] == h.hexdigest() and k["launches_per_step"] == launches_per_step:
+            return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -505,7 +591,7 @@ def fused_ops(plan, batch) -> int:
     return total
 
 
-def step_roofline(tab, steps, alu_ops_per_step=0):
+def step_roofline(tab, steps, alu_ops_per_step=0, workload="cfg4"):
     """Roofline of the dominant kernel class of one step (largest summed time):
     achieved = its algorithmic bytes per launch / its mean launch duration
     (HBM), or, for a VALU-bound class, its algorithmic VALU lane operations
@@ -526,7 +612,7 @@ def step_roofline(tab, steps, alu_ops_per_step=0):
     else:
         head = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     return {**head, "kernel": KERNEL_LABEL.get(kern, kern), "kernel_class": kern,
-            "traffic": traffic_record(kern, per_step), "alg_bytes_per_launch": by / n,
+            "traffic": traffic_record(kern, per_step, workload), "alg_bytes_per_launch": by / n,
             "us_per_launch": ms * 1e3 / n, "launches_per_step": per_step,
             "share_of_kernel_time": ms / total_ms,
             "classes": {k: {"launches_per_step": v[0] // steps, "ms_per_step": v[1] / steps,
@@ -642,7 +728,38 @@ def network_legs(name, batch, steps, warmup, plain_n, graph=True, use_tuning=Tru
     return plan, ctx, runner, res
 
 
-def serving_leg(nets, rates, seconds, seed=21, window=4, per_network=False):
+def plain_request_leg(reps=50):
+    """The plain RNS-CKKS request (N = 2^13, q0 45b + 3 x 35b, P 45b, alpha =
+    1; dense 256->64 with 8 baby steps, x^2, dense 64->2): one request at a
+    time, its whole network replayed from a captured graph of a batch of one,
+    p50/p99 over `reps` requests; eager launches beside it.  Random residues
+    as keys, diagonals and ciphertext (the same call sequence is checked bit
+    for bit against the oracle at this ring by the GPU tests)."""
+    import torch
+    from paper_2104_09164_amd import netplan
+    plan = netplan.preset_plan("cfg1")
+    ctx, runner = setup(plan, 1)
+    one = runner.capture(1).replay
+    for _ in range(3):
+        one()
+        runner.run(1)
+    torch.cuda.synchronize()
+    lat = time_events(one, reps)
+    eager = time_events(lambda: runner.run(1), reps)
+    c = netplan.PRESETS["cfg1"]
+    res = {"workload": (f"cfg1: N=2^13, q bits {c['q_bits'][0]}+{len(c['q_bits']) - 1}x{c['q_bits'][1]}, P 1x45b, "
+                        f"alpha=1, layers " + ", ".join(f"{l.n}->{l.m} (n1={l.n1})" for l in plan.layers)
+                        + ", x^2 between; one request at a time, graph replay"),
+           "requests": reps, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "inferences_per_s": 1000.0 / float(np.mean(lat)),
+           "eager_p50_ms": float(np.percentile(eager, 50)), "eager_p99_ms": float(np.percentile(eager, 99)),
+           "ops_per_inference": plan.op_counts()}
+    del ctx, runner
+    torch.cuda.synchronize()
+    return plan, res
+
+
+def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False):
     """Poisson arrivals (total rate lambda, the superposition of 256 camera
     streams), 70% small-net / 30% large-net requests, keys and plaintexts
     resident, admission by device-memory footprint, continuous batching."""
@@ -657,8 +774,7 @@ def serving_leg(nets, rates, seconds, seed=21, window=4, per_network=False):
         payloads[name] = [(residues(plan.q, N, (2,), seed + 50 + k), plan.L, plan.scale) for k in range(4)]
     budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
     out = {}
-    for rate in rates:
-        count = max(60, int(rate * seconds))
+    for rate, count in zip(rates, counts):
         rng = np.random.default_rng(seed + int(rate))
         times = serve.poisson_arrivals(rate, count, seed + int(rate))
         kinds = np.where(rng.random(count) < 0.7, "small", "large")
@@ -673,6 +789,9 @@ def serving_leg(nets, rates, seconds, seed=21, window=4, per_network=False):
             if lat:
                 m[f"{name}_p50_ms"] = float(np.percentile(lat, 50))
                 m[f"{name}_p99_ms"] = float(np.percentile(lat, 99))
+                m[f"{name}_samples"] = len(lat)
+        m["requests"] = count
+        m["p99_tail_samples"] = max(1, int(round(0.01 * m.get("completed", 0))))
         out[str(rate)] = m
     return out
 
@@ -696,27 +815,32 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16, help="requests per launch, small net")
-    ap.add_argument("--large-batch", type=int, default=32, help="requests per launch, large net")
-    ap.add_argument("--plain", type=int, default=8, help="one-request inferences timed for the plain leg")
-    ap.add_argument("--serve-rates", default="50,200,400")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--large-batch", type=int, default=32, help="requests per launch, large net (headline)")
+    ap.add_argument("--plain", type=int, default=8, help="one-request inferences timed for the plain legs")
+    ap.add_argument("--serve-rates", default="50,100,200,300,400")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per rate below the top rate")
+    ap.add_argument("--serve-requests-top", type=int, default=10000, help="requests at the top rate")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tuning", action="store_true", help="ignore committed tuning files")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ntt", action="store_true")
     ap.add_argument("--no-ks", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-net legs")
+    ap.add_argument("--no-plain-request", action="store_true", help="skip the N=2^13 plain-request leg")
     ap.add_argument("--no-tuned-split", action="store_true", help="skip the small-net leg with tuned baby steps")
     ap.add_argument("--no-conv", action="store_true", help="skip the multi-channel convolution leg")
     ap.add_argument("--no-client", action="store_true", help="skip the client encode/encrypt/decrypt leg")
-    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the small-net traced pass (profiling runs): 1 GiB calibration copy, "
-                         "setup, one untimed step, --steps traced steps")
+                    help="only a traced pass (profiling runs): 1 GiB calibration copy, setup, one untimed "
+                         "step, --steps traced steps of --roofline-net")
+    ap.add_argument("--roofline-net", default="cfg4", choices=("cfg4", "cfg3"))
     ap.add_argument("--client-only", action="store_true",
                     help="only the client encode/encrypt/decrypt leg (profiling runs)")
     ap.add_argument("--large-only", action="store_true",
                     help="only the large-net batched and plain legs (profiling runs)")
+    ap.add_argument("--ks-only", action="store_true", help="only the key-switch leg (profiling runs)")
+    ap.add_argument("--cpu-only", action="store_true", help="only the CPU oracle baseline (no GPU use)")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the NTT leg (profiling runs), preceded by a 1 GiB device copy whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -725,9 +849,21 @@ def main():
         print("bench.py measures one MI355X: the library has no multi-GPU path (requests would shard across "
               "GPUs with no exchange between them). Run with --gpus 1.", file=sys.stderr)
         return 2
+    from paper_2104_09164_amd import netplan, tune
+
+    def gpu_plan(name, tuned_n1):
+        tuned = tune.load(name, "gfx950") if not args.no_tuning else None
+        return netplan.preset_plan(name, netplan.tuned_shapes(name, tuned, tuned_n1))
+    if args.cpu_only:
+        plans = {"cfg1": netplan.preset_plan("cfg1"), "cfg3": gpu_plan("cfg3", False), "cfg4": gpu_plan("cfg4", True)}
+        print(json.dumps({"cpu_protocol": cpu_protocol(plans, "as the GPU legs")}), flush=True)
+        return 0
     import torch
     if args.client_only:
         print(json.dumps({"client": client_leg()}), flush=True)
+        return 0
+    if args.ks_only:
+        print(json.dumps({"key_switch": ks_leg()}), flush=True)
         return 0
     if args.large_only:
         _, _, _, large = network_legs("cfg4", args.large_batch, max(3, args.steps // 2), 1, max(3, args.plain // 2),
@@ -739,53 +875,61 @@ def main():
         print(json.dumps({"ntt": ntt_leg()}), flush=True)
         return 0
     if args.roofline_only:
-        from paper_2104_09164_amd import netplan, tune
         calibration_copy()
-        tuned = tune.load("cfg3")
-        plan = netplan.preset_plan("cfg3", netplan.tuned_shapes("cfg3", tuned, tuned_n1=False))
-        ctx, runner = setup(plan, args.batch)
+        name = args.roofline_net
+        tuned = tune.load(name)
+        plan = netplan.preset_plan(name, netplan.tuned_shapes(name, tuned, tuned_n1=(name == "cfg4")))
+        batch = args.large_batch if name == "cfg4" else args.batch
+        ctx, runner = setup(plan, batch)
         tune.apply_knobs(ctx, tuned)
-        tab = trace_steps(ctx, runner, args.batch, args.steps)
-        print(json.dumps({"roofline": step_roofline(tab, args.steps, fused_ops(plan, args.batch))}), flush=True)
+        tab = trace_steps(ctx, runner, batch, args.steps)
+        print(json.dumps({"roofline": step_roofline(tab, args.steps, fused_ops(plan, batch), name)}), flush=True)
         return 0
-    # headline: the preset's BSGS split (32 baby steps in the first layer), tuned execution knobs
-    plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
-                                            graph=not args.no_graph, use_tuning=not args.no_tuning,
-                                            tuned_n1=False)
-    runner_layers["small"] = run3.layers
-    out = {"metric": METRIC, "value": small["inferences_per_s"], "unit": "inferences/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": small["ms_per_step"],
+    # headline: the large net (the largest single-GPU configuration), 32 requests per launch, the
+    # committed tuned plan (baby-step splits, lazy ModDown, rotate-and-sum groups) and knobs
+    plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, args.steps, args.warmup, max(3, args.plain // 2),
+                                            graph=not args.no_graph, use_tuning=not args.no_tuning)
+    runner_layers["large"] = run4.layers
+    out = {"metric": METRIC, "value": large["inferences_per_s"], "unit": "inferences/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": large["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-           "config": {"workload": ("small-net batched encrypted inference, " + small["workload"]
-                                   + f", {args.batch} requests per launch, HIP graph replay"),
-                      "batch": args.batch, "ops_per_inference": small["ops_per_inference"],
-                      "tuning": small["tuning"]},
-           "latency_ms": {"batched_p50": small["batched_p50_ms"], "batched_p99": small["batched_p99_ms"],
-                          "plain_p50": small["plain_p50_ms"], "plain_p99": small["plain_p99_ms"]},
-           "roofline": step_roofline(small.pop("trace"), args.steps, fused_ops(plan3, args.batch)),
-           "plain_inferences_per_s": small["plain_inferences_per_s"],
-           "pcie_inclusive": small["pcie_inclusive"],
-           "batched_over_plain": small["batched_over_plain"]}
-    nets = {"small": (plan3, ctx3, args.batch)}
-    if not args.no_tuning and not args.no_tuned_split:
-        # same workload with the autotuner's baby-step counts
-        _, ctx3t, _, small_t = network_legs("cfg3", args.batch, args.steps, 1, 0, graph=not args.no_graph,
-                                            tuned_n1=True, trace=False)
-        out["small_net_tuned_split"] = {k: small_t[k] for k in ("inferences_per_s", "ms_per_step", "batched_p50_ms",
-                                                                "batched_p99_ms", "workload", "tuning")}
-        del ctx3t, small_t
-    if not args.no_large:
-        large_steps = max(3, args.steps // 2)
-        plan4, ctx4, run4, large = network_legs("cfg4", args.large_batch, large_steps, 1,
-                                                max(3, args.plain // 2), graph=not args.no_graph,
-                                                use_tuning=not args.no_tuning)
-        runner_layers["large"] = run4.layers
-        large["roofline"] = step_roofline(large.pop("trace"), large_steps, fused_ops(plan4, args.large_batch))
-        out["large_net"] = large
-        nets["large"] = (plan4, ctx4, args.large_batch)
-    if not args.no_serve and not args.no_large:
+           "config": {"workload": ("large-net batched encrypted inference, " + large["workload"]
+                                   + f", {args.large_batch} requests per launch, HIP graph replay"),
+                      "batch": args.large_batch, "ops_per_inference": large["ops_per_inference"],
+                      "tuning": large["tuning"]},
+           "latency_ms": {"batched_p50": large["batched_p50_ms"], "batched_p99": large["batched_p99_ms"],
+                          "plain_p50": large["plain_p50_ms"], "plain_p99": large["plain_p99_ms"],
+                          "plain_eager_p50": large["plain_eager_p50_ms"]},
+           "roofline": step_roofline(large.pop("trace"), args.steps, fused_ops(plan4, args.large_batch), "cfg4"),
+           "plain_inferences_per_s": large["plain_inferences_per_s"],
+           "pcie_inclusive": large["pcie_inclusive"],
+           "batched_over_plain": large["batched_over_plain"]}
+    nets = {"large": (plan4, ctx4, args.large_batch)}
+    plan3 = None
+    if not args.no_small:
+        # the small net with the preset split (32 baby steps in the first layer) and the lazy-ModDown /
+        # rotate-and-sum forms the tuner chose for it
+        plan3, ctx3, run3, small = network_legs("cfg3", args.batch, args.steps, args.warmup, args.plain,
+                                                graph=not args.no_graph, use_tuning=not args.no_tuning,
+                                                tuned_n1=False)
+        runner_layers["small"] = run3.layers
+        small["roofline"] = step_roofline(small.pop("trace"), args.steps, fused_ops(plan3, args.batch), "cfg3")
+        out["small_net"] = small
+        nets["small"] = (plan3, ctx3, args.batch)
+        if not args.no_tuning and not args.no_tuned_split:
+            _, ctx3t, _, small_t = network_legs("cfg3", args.batch, args.steps, 1, 0, graph=not args.no_graph,
+                                                tuned_n1=True, trace=False)
+            out["small_net_tuned_split"] = {k: small_t[k] for k in ("inferences_per_s", "ms_per_step",
+                                                                    "batched_p50_ms", "batched_p99_ms", "workload",
+                                                                    "tuning")}
+            del ctx3t, small_t
+    if not args.no_plain_request:
+        log("plain-request leg (N=2^13)")
+        plan1, out["plain_request"] = plain_request_leg()
+    if not args.no_serve and not args.no_small:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
-        out["serving"] = serving_leg(nets, rates, args.serve_seconds)
+        counts = [args.serve_requests_top if r == max(rates) else args.serve_requests for r in rates]
+        out["serving"] = serving_leg(nets, rates, counts)
     del nets
     torch.cuda.synchronize()
     if not args.no_ntt:
@@ -803,11 +947,17 @@ def main():
         log("client leg")
         out["client"] = client_leg()
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        # weighted by the operation counts of the paper's evaluation order (one
-        # ModDown per key switch), which is what one oracle key switch times
-        from paper_2104_09164_amd import netplan as _np
-        out["cpu_baseline"] = cpu_baseline(_np.preset_plan("cfg3"))
+        plans = {"cfg1": netplan.preset_plan("cfg1"), "cfg3": plan3 or gpu_plan("cfg3", False), "cfg4": plan4}
+        proto = cpu_protocol(plans, "the plans of the GPU legs (cfg4 tuned, cfg3 preset split, cfg1 preset)")
+        c4 = proto["cfg4"]
+        key = next(iter(c4))
+        out["cpu_baseline"] = {
+            "value": c4[key]["inferences_per_s"], "unit": "inferences/s", "cores": int(key.split("_")[1]),
+            "kind": "oracle",
+            "sample": (f"one large-net request (the headline workload, same plan as the GPU) evaluated end to end "
+                       f"by the oracle, evaluation only, single run: {c4[key]['s_per_inference']:.1f} s; "
+                       f"{proto['cpu_model']}, nproc {proto['nproc']}; more runs in cpu_protocol")}
+        out["cpu_protocol"] = proto
     print(json.dumps(out), flush=True)
     return 0
 
