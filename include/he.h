@@ -336,6 +336,12 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *   "ks_fuse"       lazy-ModDown dense layers with n2 <= 8: 1 (default) = the
  *                   baby steps' key inner products computed inside the
  *                   inner-sum kernel (never stored), 0 = two launches
+ *   "ks_fuse_g"     fused lazy-ModDown inner sums: 1 = half the default
+ *                   number of requests per thread (fewer registers), 0
+ *                   (default) = 8 / 8 / 4 / 2 requests for 1 / 2 / 4 / 8
+ *                   giant sums
+ *   "ks_fuse_waves" fused lazy-ModDown inner sums: 3 = the kernel compiled for
+ *                   three waves per SIMD, 0 (default) = the compiler's choice
  *   "trace"         1 = bracket every kernel launch with HIP events on the
  *                   context stream (not while the stream is being captured
  *                   into a graph); read with he_trace_read.  0 = off.

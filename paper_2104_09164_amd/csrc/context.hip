@@ -585,6 +585,16 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_g")) {
+    if (value > 1) return HE_EINVAL;
+    c->ks_fuse_g = value;
+    return HE_OK;
+  }
+  if (!std::strcmp(key, "ks_fuse_waves")) {
+    if (value != 0 && value != 3) return HE_EINVAL;
+    c->ks_fuse_waves = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "trace")) {
     if (value > 1) return HE_EINVAL;
     return trace_enable(c, value == 1);
@@ -623,6 +633,8 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ntt_cols_b")) { *value = c->ntt_cols_b; return HE_OK; }
   if (!std::strcmp(key, "ntt_single_pass")) { *value = c->ntt_single_pass; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse")) { *value = c->ks_fuse; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_g")) { *value = c->ks_fuse_g; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_waves")) { *value = c->ks_fuse_waves; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

@@ -102,7 +102,9 @@ struct he_ctx {
   int64_t ntt_cols = 16;      // sub-transforms per NTT workgroup tile: 8, 16 or 32
   int64_t ntt_cols_b = 0;     // the same for the row phase (0 = ntt_cols)
   int64_t ntt_single_pass = 0;
-  int64_t ks_fuse = 1;          // lazy-ModDown baby steps: inner product fused into the inner sums  // N = 2^15: register-resident single-pass transform (off: VALU-bound either way)
+  int64_t ks_fuse = 1;          // lazy-ModDown baby steps: inner product fused into the inner sums
+  int64_t ks_fuse_g = 0;        // fused extended sums: 1 = half the items per thread
+  int64_t ks_fuse_waves = 0;    // fused extended sums: 3 = compiled for 3 waves per SIMD
 
   Tracer tr;
 

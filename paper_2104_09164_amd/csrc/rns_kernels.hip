@@ -473,8 +473,11 @@ __device__ __forceinline__ void ks_ext_fused_body(const u64* __restrict__ ext, c
   }
 }
 
-template <int BETA, int JC, int G>
-__global__ void __launch_bounds__(BS) k_ks_ext_fused(const u64* __restrict__ ext, OwnMap own, StepKeys keys,
+// W > 0: compiled for W waves per SIMD (the register budget that allows);
+// W = 0: the compiler's own allocation.
+template <int BETA, int JC, int G, int W>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, W > 0 ? W : 8)))
+k_ks_ext_fused(const u64* __restrict__ ext, OwnMap own, StepKeys keys,
                                                      Items in, const u64* __restrict__ pts, u64* __restrict__ sqp,
                                                      const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
                                                      u32 N, u32 logn, u32 l, u32 nq, u32 np, u32 dstride, u32 alpha,
@@ -961,20 +964,28 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
   TraceScope ts(c, TK_KS_EXT_FUSED,
                 ((double)S * 4.0 * beta * ne + (double)B * (beta * ne + 2.0 * (l + 1) + 2.0 * n2 * ne) +
                  (pts ? 2.0 * n1 * n2 * ne : 0.0)) * (8.0 * (double)c->N));
-  // items per thread: G n2 <= 16 accumulator pairs (more items per thread
-  // measured faster than more waves: each key and plaintext word loaded is
-  // used G times)
-  const u32 G = n2 == 8 ? 2 : (n2 == 4 ? 4 : 8);
+  // items per thread: by default G n2 <= 16 accumulator pairs (each key and
+  // plaintext word loaded is used G times); knob ks_fuse_g halves G
+  // (fewer registers), knob ks_fuse_waves = 3 compiles for 3 waves per SIMD.
+  const u32 Gd = n2 == 8 ? 2 : (n2 == 4 ? 4 : 8);
+  const u32 G = c->ks_fuse_g ? Gd / 2 : Gd;
+  const bool w3 = c->ks_fuse_waves == 3;
   dim3 grid(((B + G - 1) / G) * (c->N / BS) * ne);
 #define HE_LAUNCH_FX(BT, J, GG)                                                                                   \
-  HE_LAUNCH(ts, (k_ks_ext_fused<BT, J, GG>), grid, dim3(BS), c->stream, ext, own, keys, in, pts, sqp, c->d_pc,      \
-            c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)
-#define HE_FX_J(BT)                                   \
-  switch (n2) {                                       \
-    case 8: HE_LAUNCH_FX(BT, 8, 2); break;            \
-    case 4: HE_LAUNCH_FX(BT, 4, 4); break;            \
-    case 2: HE_LAUNCH_FX(BT, 2, 8); break;            \
-    default: HE_LAUNCH_FX(BT, 1, 8); break;           \
+  do {                                                                                                            \
+    if (w3)                                                                                                       \
+      HE_LAUNCH(ts, (k_ks_ext_fused<BT, J, GG, 3>), grid, dim3(BS), c->stream, ext, own, keys, in, pts, sqp,      \
+                c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1);                   \
+    else                                                                                                          \
+      HE_LAUNCH(ts, (k_ks_ext_fused<BT, J, GG, 0>), grid, dim3(BS), c->stream, ext, own, keys, in, pts, sqp,      \
+                c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1);                   \
+  } while (0)
+#define HE_FX_J(BT)                                                            \
+  switch (n2) {                                                                \
+    case 8: if (G == 1) HE_LAUNCH_FX(BT, 8, 1); else HE_LAUNCH_FX(BT, 8, 2); break;  \
+    case 4: if (G == 2) HE_LAUNCH_FX(BT, 4, 2); else HE_LAUNCH_FX(BT, 4, 4); break;  \
+    case 2: if (G == 4) HE_LAUNCH_FX(BT, 2, 4); else HE_LAUNCH_FX(BT, 2, 8); break;  \
+    default: if (G == 4) HE_LAUNCH_FX(BT, 1, 4); else HE_LAUNCH_FX(BT, 1, 8); break; \
   }
   switch (beta) {
     case 1: HE_FX_J(1); break;
