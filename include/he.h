@@ -314,6 +314,19 @@ int he_rescale_batch(he_ctx* ctx, uint32_t n, const he_ct* in, he_ct* out);
 int he_rotate_hoisted_batch(he_ctx* ctx, uint32_t n, const he_ct* in, uint32_t n_steps, const int32_t* steps,
                             he_ct* out);
 
+/* Rescale that allocates nothing and needs no bound workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, checks
+ * and results as he_rescale_batch (bit for bit), except that its temporaries
+ * live in a library-owned static device array of HE_NOALLOC_SCRATCH_BYTES per
+ * GPU (held until the process ends): n (2 (l+1) + 2 l) N words, plus 2 l N n
+ * more when an output aliases its input, at the inputs' level l; HE_ENOMEM
+ * beyond the array.  The array is shared by every call on that GPU (all
+ * contexts, all streams): calls that overlap on one GPU race and must be
+ * ordered by the caller.  HE_ESTATE if no context was created on this GPU. */
+#define HE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int he_rescale_batch_noalloc(he_ctx* ctx, uint32_t n, const he_ct* in, he_ct* out);
+
 /* Kernel-level entry: negacyclic NTT (inverse != 0: INTT) in place on
  * n_items device buffers, each holding `limbs` consecutive limb-polys for
  * primes first_prime .. first_prime + limbs - 1 (indices into q_0..q_L,

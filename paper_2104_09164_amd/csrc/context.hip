@@ -318,6 +318,7 @@ int he_ctx_create(const he_params* pr, void* stream, he_ctx** out) {
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) { note_hip_error("hipGetDevice", e); rc = HE_EDEVICE; }
   }
+  if (!rc) noalloc_scratch_init(c->device);
   if (!rc) rc = build_tables(c);
   if (rc) {
     free_tables(c);

@@ -180,6 +180,10 @@ struct TraceScope {
       hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                              \
   } while (0)
 
+// Looks up the calling GPU's copy of the no-allocation scratch array (ops.hip);
+// called by he_ctx_create with that GPU current.
+void noalloc_scratch_init(int device);
+
 // kernel launchers (ntt.hip)
 int launch_ntt(he_ctx* c, const PolyBatch& pb, bool inverse);
 // kernel launchers (rns_kernels.hip) are declared in rns_kernels.hpp

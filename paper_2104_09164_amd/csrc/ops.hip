@@ -4,7 +4,40 @@
 // kernel launches on the context stream; nothing is computed on the CPU.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include "rns_kernels.hpp"
+
+// Scratch of the no-allocation rescale (he_rescale_batch_noalloc): one array
+// per GPU, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a host-side stand-in);
+// it uses the device address hipGetSymbolAddress returned for that GPU.
+static __device__ __align__(256) uint64_t scratch[HE_NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices];    // device address of `scratch` per GPU
+int g_noalloc_rc[kMaxDevices];       // HE_OK, or the error its look-up returned
+bool g_noalloc_done[kMaxDevices];
+}  // namespace
+
+// Called by he_ctx_create with `device` current: looks up that GPU's copy of
+// `scratch` once.
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_done[device]) return;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    note_hip_error("hipGetSymbolAddress(scratch)", e);
+    g_noalloc_rc[device] = HE_EDEVICE;
+  } else {
+    g_noalloc_ptr[device] = p;
+    g_noalloc_rc[device] = HE_OK;
+  }
+  g_noalloc_done[device] = true;
+}
 
 namespace {
 
@@ -236,6 +269,19 @@ FinalArgs no_final() {
   return fa;
 }
 
+// Pointers, levels and scales of a batched call (no workspace involved).
+int check_items(const he_ctx* c, u32 n, const he_ct* in, const he_ct* out, u32 n_out) {
+  if (!c || !in || !out || n == 0 || n > HE_MAXB) return HE_EINVAL;
+  for (u32 b = 0; b < n; ++b) {
+    if (!in[b].dev) return HE_EINVAL;
+    if (in[b].level >= c->nq || in[b].level != in[0].level) return HE_ELEVEL;
+    if (!same_scale(in[b].scale, in[0].scale)) return HE_ESCALE;
+  }
+  for (u32 b = 0; b < n_out; ++b)
+    if (!out[b].dev) return HE_EINVAL;
+  return HE_OK;
+}
+
 int check_batch(const he_ctx* c, u32 n, const he_ct* in, const he_ct* out, u32 n_out) {
   if (!c || !in || !out || n == 0 || n > HE_MAXB) return HE_EINVAL;
   if (!c->ws) return HE_ESTATE;
@@ -256,6 +302,51 @@ int copy_ct(he_ctx* c, u32 l, const u64* src, u64* dst) {
                  hipSuccess
              ? HE_OK
              : HE_EDEVICE;
+}
+
+// Rescale of n ciphertexts at level l > 0 (checked by the caller) with its
+// scratch regions: rtmp [n][2][l+1][N] (the inverse NTT of the last limbs, at
+// their positions), red [n][2][l][N] (those limbs reduced mod q_i, NTT form)
+// and, when an output aliases its input, z0 [n][2][l][N] (staging).
+int rescale_items(he_ctx* c, u32 n, const he_ct* in, he_ct* out, u64* rtmp, u64* red, u64* z0) {
+  int rc;
+  const u32 l = in[0].level;
+  const size_t N = c->N;
+  // INTT of the last limb of both polynomials into rtmp ([B][2][l+1][N] layout).
+  PolyBatch pb = batch_of(n);
+  pb.npoly = 2 * (l + 1);
+  for (u32 b = 0; b < n; ++b) {
+    pb.src[b] = in[b].dev;
+    pb.dst[b] = rtmp + (size_t)b * 2 * (l + 1) * N;
+  }
+  for (u32 r = 0; r < 2 * (l + 1); ++r) pb.prime[r] = (r % (l + 1)) == l ? (uint8_t)l : 0xFF;
+  if ((rc = launch_ntt(c, pb, true))) return rc;
+  if ((rc = launch_rescale_reduce(c, l, n, rtmp, red))) return rc;
+  PolyBatch pr = batch_of(n);
+  pr.npoly = 2 * l;
+  for (u32 b = 0; b < n; ++b) pr.src[b] = pr.dst[b] = red + (size_t)b * 2 * l * N;
+  for (u32 r = 0; r < 2 * l; ++r) pr.prime[r] = (uint8_t)(r % l);
+  if ((rc = launch_ntt(c, pr, false))) return rc;
+  Items ii, oo;
+  ii.n = oo.n = n;
+  bool alias = false;
+  for (u32 b = 0; b < n; ++b) {
+    ii.p[b] = in[b].dev;
+    alias |= out[b].dev == in[b].dev;
+  }
+  // An in-place rescale moves c1 down by one limb: stage through z0.
+  for (u32 b = 0; b < n; ++b) oo.p[b] = alias ? z0 + (size_t)b * 2 * l * N : out[b].dev;
+  if ((rc = launch_rescale_final(c, l, ii, red, oo))) return rc;
+  if (alias)
+    for (u32 b = 0; b < n; ++b)
+      if (hipMemcpyAsync(out[b].dev, oo.p[b], (size_t)2 * l * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
+          hipSuccess)
+        return HE_EDEVICE;
+  for (u32 b = 0; b < n; ++b) {
+    out[b].level = l - 1;
+    out[b].scale = in[b].scale / (double)c->primes[l];
+  }
+  return HE_OK;
 }
 
 }  // namespace
@@ -375,45 +466,33 @@ int he_square(he_ctx* c, const he_ct* in, he_ct* out) { return he_square_batch(c
 int he_rescale_batch(he_ctx* c, uint32_t n, const he_ct* in, he_ct* out) {
   int rc = check_batch(c, n, in, out, n);
   if (rc) return rc;
+  if (in[0].level == 0) return HE_ELEVEL;
+  const WS w = carve(c);
+  return rescale_items(c, n, in, out, w.rtmp, w.red, w.z0);
+}
+
+int he_rescale_batch_noalloc(he_ctx* c, uint32_t n, const he_ct* in, he_ct* out) {
+  int rc = check_items(c, n, in, out, n);
+  if (rc) return rc;
   const u32 l = in[0].level;
   if (l == 0) return HE_ELEVEL;
-  const size_t N = c->N;
-  const WS w = carve(c);
-  // INTT of the last limb of both polynomials into rtmp ([B][2][l+1][N] layout).
-  PolyBatch pb = batch_of(n);
-  pb.npoly = 2 * (l + 1);
-  for (u32 b = 0; b < n; ++b) {
-    pb.src[b] = in[b].dev;
-    pb.dst[b] = w.rtmp + (size_t)b * 2 * (l + 1) * N;
+  const int dev = c->device;
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (dev < 0 || dev >= kMaxDevices || !g_noalloc_done[dev]) return HE_ESTATE;
+    if (g_noalloc_rc[dev]) return g_noalloc_rc[dev];
+    base = g_noalloc_ptr[dev];
   }
-  for (u32 r = 0; r < 2 * (l + 1); ++r) pb.prime[r] = (r % (l + 1)) == l ? (uint8_t)l : 0xFF;
-  if ((rc = launch_ntt(c, pb, true))) return rc;
-  if ((rc = launch_rescale_reduce(c, l, n, w.rtmp, w.red))) return rc;
-  PolyBatch pr = batch_of(n);
-  pr.npoly = 2 * l;
-  for (u32 b = 0; b < n; ++b) pr.src[b] = pr.dst[b] = w.red + (size_t)b * 2 * l * N;
-  for (u32 r = 0; r < 2 * l; ++r) pr.prime[r] = (uint8_t)(r % l);
-  if ((rc = launch_ntt(c, pr, false))) return rc;
-  Items ii, oo;
-  ii.n = oo.n = n;
   bool alias = false;
-  for (u32 b = 0; b < n; ++b) {
-    ii.p[b] = in[b].dev;
-    alias |= out[b].dev == in[b].dev;
-  }
-  // An in-place rescale moves c1 down by one limb: stage through the workspace.
-  for (u32 b = 0; b < n; ++b) oo.p[b] = alias ? w.z0 + (size_t)b * 2 * l * N : out[b].dev;
-  if ((rc = launch_rescale_final(c, l, ii, w.red, oo))) return rc;
-  if (alias)
-    for (u32 b = 0; b < n; ++b)
-      if (hipMemcpyAsync(out[b].dev, oo.p[b], (size_t)2 * l * N * sizeof(u64), hipMemcpyDeviceToDevice, c->stream) !=
-          hipSuccess)
-        return HE_EDEVICE;
-  for (u32 b = 0; b < n; ++b) {
-    out[b].level = l - 1;
-    out[b].scale = in[b].scale / (double)c->primes[l];
-  }
-  return HE_OK;
+  for (u32 b = 0; b < n; ++b) alias |= out[b].dev == in[b].dev;
+  const size_t N = c->N;
+  const size_t rtmp_w = (size_t)n * 2 * (l + 1) * N, red_w = (size_t)n * 2 * l * N;
+  const size_t need = (rtmp_w + red_w + (alias ? red_w : 0)) * sizeof(u64);
+  if (need > HE_NOALLOC_SCRATCH_BYTES) return HE_ENOMEM;
+  u64* rtmp = (u64*)base;
+  u64* red = rtmp + rtmp_w;
+  return rescale_items(c, n, in, out, rtmp, red, red + red_w);
 }
 
 int he_rescale(he_ctx* c, const he_ct* in, he_ct* out) { return he_rescale_batch(c, 1, in, out); }

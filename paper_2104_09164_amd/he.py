@@ -94,6 +94,7 @@ def lib() -> C.CDLL:
             "he_eval_dense_batch": (C.c_int, [vp, u32, ctp, vp, ctp]),
             "he_square_batch": (C.c_int, [vp, u32, ctp, ctp]),
             "he_rescale_batch": (C.c_int, [vp, u32, ctp, ctp]),
+            "he_rescale_batch_noalloc": (C.c_int, [vp, u32, ctp, ctp]),
             "he_rotate_hoisted_batch": (C.c_int, [vp, u32, ctp, u32, C.POINTER(i32), ctp]),
             "he_ntt": (C.c_int, [vp, u32, C.POINTER(vp), u32, u32, C.c_int]),
             "he_sync": (C.c_int, [vp]),
@@ -123,7 +124,7 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
             "he_dense_load_ex", "he_linear_bytes", "he_linear_load", "he_linear_free", "he_linear_scratch_bytes",
             "he_eval_linear", "he_eval_linear_batch", "he_client_create", "he_client_destroy", "he_encode",
-            "he_encrypt", "he_decrypt", "he_decode")
+            "he_encrypt", "he_decrypt", "he_decode", "he_rescale_batch_noalloc")
 
 HE_DENSE_QP = 1
 HE_DENSE_RS_SHIFT = 8
@@ -430,6 +431,14 @@ class Context:
         outs = outs or [self.new_ct(c.level - 1) for c in cts]
         ia, oa = self._arr(cts), self._arr(outs)
         _check(lib().he_rescale_batch(self.h, len(cts), ia, oa), "he_rescale_batch")
+        self._sync_meta(outs, oa)
+        return outs
+
+    def rescale_batch_noalloc(self, cts, outs):
+        """he_rescale_batch_noalloc: the same results with the library's static
+        per-GPU scratch (no workspace, no allocation; outs must be given)."""
+        ia, oa = self._arr(cts), self._arr(outs)
+        _check(lib().he_rescale_batch_noalloc(self.h, len(cts), ia, oa), "he_rescale_batch_noalloc")
         self._sync_meta(outs, oa)
         return outs
 
