@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhe.so")
-SOURCES = ["ntt.hip", "rns_kernels.hip", "context.hip", "ops.hip", "client.hip"]
+SOURCES = ["ntt.hip", "rns_kernels.hip", "ext_sums.hip", "ext_sums_lds.hip", "context.hip", "ops.hip", "client.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed-FP32 forms are disabled for every HIP source of this project
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -596,6 +596,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse_waves = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_lds")) {
+    if (value != 0 && value != 4 && value != 8) return HE_EINVAL;
+    c->ks_fuse_lds = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "trace")) {
     if (value > 1) return HE_EINVAL;
     return trace_enable(c, value == 1);
@@ -636,6 +641,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ks_fuse")) { *value = c->ks_fuse; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_g")) { *value = c->ks_fuse_g; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_waves")) { *value = c->ks_fuse_waves; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_lds")) { *value = c->ks_fuse_lds; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

@@ -1,0 +1,214 @@
+// LDS-shared form of the fused lazy-ModDown inner sums (knob ks_fuse_lds):
+// the same words as k_ks_ext_fused (ext_sums.hip), with each baby step's key
+// and plaintext words shared through LDS by the threads of several requests.
+#include "rns_kernels.hpp"
+#include "modarith.hpp"
+#include "rns_device.hpp"
+
+namespace {
+
+// The same sums with the key and plaintext words shared through LDS.  A
+// workgroup covers 64 consecutive positions x of limb t for W requests (wave
+// g serves request b0 + g), so a thread keeps only its own 2 JC sums in
+// registers and the kernel runs at a higher
+// occupancy than the register form.  Baby step i's words of the tile (4 beta
+// key words and 2 JC plaintext words per position) are loaded once per
+// workgroup into an LDS buffer, double-buffered: the loads of step i + 1 are
+// issued before step i is computed and stored to LDS after it, with one
+// barrier per step that every thread reaches.  Digits and c0 are gathered at
+// y = perm_{g_i}(x) per request as in the register form, and every product
+// and sum is the register form's, in the same order: the same words.
+// Words per position per step (4 per digit: key b, its companion, key a,
+// its companion; 2 per giant sum: plaintext and companion), key rows each
+// wave moves (W waves: wave w moves kind w mod 4 of the digits j = w / 4,
+// w / 4 + W / 4, ...) and plaintext rows each wave moves.
+constexpr int lds_nw(int beta, int jc) { return 4 * beta + 2 * jc; }
+constexpr int lds_kr(int beta, int w) { return (beta + w / 4 - 1) / (w / 4); }
+constexpr int lds_pr(int jc, int w) { return (2 * jc + w - 1) / w; }
+constexpr int lds_st(int beta, int jc, int w) { return lds_kr(beta, w) + lds_pr(jc, w); }
+
+// Tile rows of one step: row 4 j + k holds the key words of digit j (k = 0:
+// b, 1: b companion, 2: a, 3: a companion); row 4 beta + 2 jj + {0, 1} the
+// plaintext word and companion of giant sum jj.  The wave index is read into
+// a scalar register, so every branch on a row is uniform over the wave.
+template <int BETA, int JC, int W>
+__device__ __forceinline__ void lds_tile_load(u64 (&st)[lds_st(BETA, JC, W)], u32 w, u32 i,
+                                              const u64* __restrict__ key, const u64* __restrict__ pts,
+                                              const PrimeConst& P, u32 N, u32 ne, u32 nt, u32 pr, u32 t, u32 n1,
+                                              size_t kw, size_t comp, u32 x) {
+  constexpr int KR = lds_kr(BETA, W), PRW = lds_pr(JC, W);
+  if (i > 0) {
+    const u32 k = w & 3, j0 = w >> 2;
+    const u64* kp = key + (k & 1 ? kw : 0) + ((size_t)(k >> 1) * nt + pr) * N + x;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+      const u32 j = j0 + (W / 4) * r;
+      if (j < (u32)BETA) st[r] = kp[(size_t)j * 2 * nt * N];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PRW; ++r) {
+    const u32 pw = w + W * r;                          // plaintext row (of 2 JC)
+    if (pw < 2 * JC) {
+      const u32 jj = pw >> 1;
+      if (!pts) st[KR + r] = pw & 1 ? P.mu : 1;       // no plaintexts: a plain sum (x 1, companion mu)
+      else st[KR + r] = pts[(pw & 1 ? comp : 0) + (((size_t)n1 * jj + i) * ne + t) * N + x];
+    }
+  }
+}
+template <int BETA, int JC, int W>
+__device__ __forceinline__ void lds_tile_store(const u64 (&st)[lds_st(BETA, JC, W)], u32 w, u32 i, u64 (*buf)[64],
+                                               u32 p) {
+  constexpr int KR = lds_kr(BETA, W), PRW = lds_pr(JC, W);
+  if (i > 0) {
+    const u32 k = w & 3, j0 = w >> 2;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+      const u32 j = j0 + (W / 4) * r;
+      if (j < (u32)BETA) buf[4 * j + k][p] = st[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PRW; ++r) {
+    const u32 pw = w + W * r;
+    if (pw < 2 * JC) buf[4 * BETA + pw][p] = st[KR + r];
+  }
+}
+
+template <int BETA, int JC, int W, bool LKS, bool LMP>
+__device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, const OwnMap& own,
+                                                const StepKeys& keys, const Items& in, const u64* __restrict__ pts,
+                                                u64* __restrict__ sqp, const PrimeConst& P, u64 pw, u64 pws, u32 N,
+                                                u32 logn, u32 l, u32 nt, u32 ne, u32 pr, u32 dstride, u32 alpha,
+                                                u32 n1, u32 b0, u32 x0, u32 t, u64 (*sh)[lds_nw(BETA, JC)][64]) {
+  const u32 B = in.n;
+  const u32 p = threadIdx.x & 63;
+  const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // the wave: request b0 + w
+  const u32 x = x0 + p, b = b0 + w;
+  const bool active = b < B;                          // idle waves still move tiles and reach barriers
+  const bool qlimb = t <= l;
+  const u64 q = P.q;
+  const size_t comp = (size_t)n1 * JC * ne * N;       // plaintext companions follow the m = n1 JC diagonals
+  const size_t kw = (size_t)dstride * 2 * nt * N;     // key companions follow the key words
+  const u32 own_digit = qlimb ? t / alpha : 0xFFFFFFFFu;
+  u64 a0[JC], a1[JC];
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) a0[jj] = a1[jj] = 0;
+  u64 st[lds_st(BETA, JC, W)];
+  lds_tile_load<BETA, JC, W>(st, w, 0, nullptr, pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
+  lds_tile_store<BETA, JC, W>(st, w, 0, sh[0], p);
+  for (u32 i = 0; i < n1; ++i) {
+    __syncthreads();                                  // step i's tile is in sh[i & 1]; sh[(i + 1) & 1] is free
+    if (i + 1 < n1)
+      lds_tile_load<BETA, JC, W>(st, w, i + 1, keys.key[i], pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
+    const u64 (*cur)[64] = sh[i & 1];
+    if (active) {
+      if (i == 0) {
+        if (qlimb) {
+          const u64* c = in.p[b];
+          const u64 r0 = shoup(c[(size_t)t * N + x], pw, pws, q), r1 = shoup(c[(size_t)(l + 1 + t) * N + x], pw, pws, q);
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) {
+            const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
+            a0[jj] = mp_add<LMP>(a0[jj], r0, pt, ps, P);
+            a1[jj] = mp_add<LMP>(a1[jj], r1, pt, ps, P);
+          }
+        }
+      } else {
+        const u32 y = galois_perm(x, keys.galois[i - 1], logn);
+        const u64* e = ext + ((size_t)b * dstride * ne + t) * N + y;
+        const u64* src = own.ptr[b];
+        u64 d[BETA], kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
+#pragma unroll
+        for (int j = 0; j < BETA; ++j) {
+          d[j] = (u32)j == own_digit ? src[(size_t)t * N + y] : e[(size_t)j * ne * N];
+          kb[j] = cur[4 * j][p];
+          kbs[j] = cur[4 * j + 1][p];
+          ka[j] = cur[4 * j + 2][p];
+          kas[j] = cur[4 * j + 3][p];
+        }
+        u64 r0, r1;
+        ks_dot<BETA, LKS>(d, kb, kbs, ka, kas, P, !qlimb, r0, r1);
+        if (qlimb) r0 += shoup_lazy(in.p[b][(size_t)t * N + y], pw, pws, q);
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj) {
+          const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
+          a0[jj] = mp_add<LMP>(a0[jj], r0, pt, ps, P);
+          a1[jj] = mp_add<LMP>(a1[jj], r1, pt, ps, P);
+        }
+      }
+    }
+    if (i + 1 < n1) lds_tile_store<BETA, JC, W>(st, w, i + 1, sh[(i + 1) & 1], p);
+  }
+  if (!active) return;
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = sqp + ((size_t)jj * B + b) * 2 * ne * N;
+    o[(size_t)t * N + x] = mp_final<LMP>(a0[jj], P);
+    o[(size_t)(ne + t) * N + x] = mp_final<LMP>(a1[jj], P);
+  }
+}
+
+// 1-D grid over request groups of W x (N/64, ne) tiles (xcd_decode: the
+// groups of a tile run back to back on one XCD and share its words in L2).
+template <int BETA, int JC, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
+k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, const u64* __restrict__ pts,
+             u64* __restrict__ sqp, const PrimeConst* __restrict__ pc, const u64* __restrict__ md, u32 N, u32 logn,
+             u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1) {
+  __shared__ u64 sh[2][lds_nw(BETA, JC)][64];
+  const u32 npb = N / 64, ne = l + 1 + np, nt = nq + np;
+  const u32 ngroups = (in.n + W - 1) / W;
+  u32 grp, tile;
+  xcd_decode(blockIdx.x, ngroups, npb * ne, grp, tile);
+  const u32 x0 = (tile % npb) * 64, t = tile / npb;
+  const u32 pr = t <= l ? t : nq + (t - l - 1);
+  const PrimeConst P = pc[pr];
+  const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
+  const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
+  const u32 b0 = grp * W;
+  const bool lks = P.q < kLazyKS, lmp = P.q < kLazyMP;
+  if (lks && lmp)
+    ks_ext_lds_body<BETA, JC, W, true, true>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
+                                             dstride, alpha, n1, b0, x0, t, sh);
+  else if (lks)
+    ks_ext_lds_body<BETA, JC, W, true, false>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
+                                              dstride, alpha, n1, b0, x0, t, sh);
+  else
+    ks_ext_lds_body<BETA, JC, W, false, false>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
+                                               dstride, alpha, n1, b0, x0, t, sh);
+}
+
+}  // namespace
+
+int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
+                      const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u32 beta, u32 ne,
+                      TraceScope& ts) {
+  // the LDS-shared form: W = ks_fuse_lds requests (waves) per workgroup, 64 positions
+  const u32 W = (u32)c->ks_fuse_lds;
+  dim3 grid_l(((B + W - 1) / W) * (c->N / 64) * ne);
+#define HE_LAUNCH_LX(BT, J, WW)                                                                                   \
+  HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW>), grid_l, dim3(64 * WW), c->stream, ext, own, keys, in, pts, sqp,         \
+            c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)
+#define HE_LX_J(BT)                                                                         \
+  switch (n2) {                                                                             \
+    case 8: if (W == 8) HE_LAUNCH_LX(BT, 8, 8); else HE_LAUNCH_LX(BT, 8, 4); break;          \
+    case 4: if (W == 8) HE_LAUNCH_LX(BT, 4, 8); else HE_LAUNCH_LX(BT, 4, 4); break;          \
+    case 2: if (W == 8) HE_LAUNCH_LX(BT, 2, 8); else HE_LAUNCH_LX(BT, 2, 4); break;          \
+    default: if (W == 8) HE_LAUNCH_LX(BT, 1, 8); else HE_LAUNCH_LX(BT, 1, 4); break;         \
+  }
+  switch (beta) {
+    case 1: HE_LX_J(1); break;
+    case 2: HE_LX_J(2); break;
+    case 3: HE_LX_J(3); break;
+    case 4: HE_LX_J(4); break;
+    case 5: HE_LX_J(5); break;
+    case 6: HE_LX_J(6); break;
+    case 7: HE_LX_J(7); break;
+    case 8: HE_LX_J(8); break;
+    default: return HE_EPARAM;
+  }
+#undef HE_LX_J
+#undef HE_LAUNCH_LX
+  return ok();
+}

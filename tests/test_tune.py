@@ -56,9 +56,41 @@ def test_knobs_preserve_bits():
             assert np.array_equal(ctx.export_ct(g), w), knobs
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,n,n1,rs", [(8, 64, 8, 0), (8, 64, 4, 2), (8, 64, 2, 0), (16, 64, 2, 3)])
+def test_fused_knobs_preserve_bits(m, n, n1, rs):
+    """The fused lazy-ModDown inner sums (n2 = 1, 2, 4, 8 giant sums) under
+    every setting of ks_fuse_g (requests per thread) and ks_fuse_waves (the
+    three-waves-per-SIMD build), and in the LDS-shared form (ks_fuse_lds):
+    three requests (a partial last group of requests per thread, an idle wave
+    in the LDS form), each equal to the oracle bit for bit."""
+    from oracle import ckks, params, plan
+    from paper_2104_09164_amd import he, synth
+    pr = params.make(12, [60, 45, 45, 45, 45], [60, 60, 60], 3, 40)
+    o = ckks.Oracle(pr)
+    keys = o.keygen(1, plan.rotation_steps(m, n, n1, rs))
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    ctx.bind(3, n1, m // n1)
+    ctx.load_keys(keys.rlk, keys.rot)
+    W, b = synth.network_weights([(m, n, n1)], 0.05)
+    cts = [o.encrypt(plan.input_slots(synth.request_input(n, r), pr.slots), keys.pk, 70 + r) for r in range(3)]
+    lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale, qp=True, rs_bits=rs)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True, rs_bits=rs)
+    want = [o.dense(c, lay, keys).data for c in cts]
+    for g, w, lds in [(0, 0, 0), (1, 0, 0), (0, 3, 0), (1, 3, 0), (0, 0, 4), (0, 0, 8)]:
+        ctx.set_knob("ks_fuse_g", g)
+        ctx.set_knob("ks_fuse_waves", w)
+        ctx.set_knob("ks_fuse_lds", lds)
+        gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
+        out = ctx.eval_dense_batch(gs, d)
+        for i, (x, y) in enumerate(zip(out, want)):
+            assert np.array_equal(ctx.export_ct(x), y), (g, w, lds, i)
+
+
 def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
-    assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse"}
+    assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse",
+                                    "ks_fuse_g", "ks_fuse_waves", "ks_fuse_lds"}
     assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
     assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
     assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
@@ -69,10 +101,12 @@ def test_knob_api_validation():
     from paper_2104_09164_amd import he
     q, p = he.prime_chain(12, [50, 40], [50])
     ctx = he.Context(12, q, p, 1)
-    defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1, "trace": 0}
+    defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
+                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 0, "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
     for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
+                   ("ks_fuse_g", 2), ("ks_fuse_waves", 2), ("ks_fuse_lds", 2),
                    ("ntt_chunk_mb", -1),
                    ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
