@@ -597,7 +597,7 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     return HE_OK;
   }
   if (!std::strcmp(key, "ks_fuse_lds")) {
-    if (value != 0 && value != 4 && value != 8) return HE_EINVAL;
+    if (value != 0 && value != 4 && value != 8 && value != 16) return HE_EINVAL;
     c->ks_fuse_lds = value;
     return HE_OK;
   }

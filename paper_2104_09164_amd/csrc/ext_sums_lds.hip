@@ -75,7 +75,10 @@ __device__ __forceinline__ void lds_tile_store(const u64 (&st)[lds_st(BETA, JC, 
   }
 }
 
-template <int BETA, int JC, int W, bool LKS, bool LMP>
+// MODE 0: q < 2^55 (key sums lazy, inner sums lazy); 1: q < 2^60 with at
+// most 4 digits (ks_dot_mid, mp_add_mid); 2: any other prime (every sum kept
+// below 4q after each term).
+template <int BETA, int JC, int W, int MODE>
 __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, const OwnMap& own,
                                                 const StepKeys& keys, const Items& in, const u64* __restrict__ pts,
                                                 u64* __restrict__ sqp, const PrimeConst& P, u64 pw, u64 pws, u32 N,
@@ -110,8 +113,13 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
 #pragma unroll
           for (int jj = 0; jj < JC; ++jj) {
             const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
-            a0[jj] = mp_add<LMP>(a0[jj], r0, pt, ps, P);
-            a1[jj] = mp_add<LMP>(a1[jj], r1, pt, ps, P);
+            if (MODE == 1) {
+              a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, false);
+              a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, false);
+            } else {
+              a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
+              a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);
+            }
           }
         }
       } else {
@@ -128,13 +136,23 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
           kas[j] = cur[4 * j + 3][p];
         }
         u64 r0, r1;
-        ks_dot<BETA, LKS>(d, kb, kbs, ka, kas, P, !qlimb, r0, r1);
+        if (MODE == 1) {
+          if constexpr (BETA <= 4) ks_dot_mid<BETA>(d, kb, kbs, ka, kas, P, r0, r1);
+        } else {
+          ks_dot<BETA, MODE == 0>(d, kb, kbs, ka, kas, P, false, r0, r1);
+        }
         if (qlimb) r0 += shoup_lazy(in.p[b][(size_t)t * N + y], pw, pws, q);
+        const bool red = i % 3 == 0;                  // the inner sums of MODE 1: reduced before every third product
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
           const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
-          a0[jj] = mp_add<LMP>(a0[jj], r0, pt, ps, P);
-          a1[jj] = mp_add<LMP>(a1[jj], r1, pt, ps, P);
+          if (MODE == 1) {
+            a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, red);
+            a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, red);
+          } else {
+            a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
+            a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);
+          }
         }
       }
     }
@@ -144,8 +162,8 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
     u64* o = sqp + ((size_t)jj * B + b) * 2 * ne * N;
-    o[(size_t)t * N + x] = mp_final<LMP>(a0[jj], P);
-    o[(size_t)(ne + t) * N + x] = mp_final<LMP>(a1[jj], P);
+    o[(size_t)t * N + x] = mp_final<MODE != 2>(a0[jj], P);
+    o[(size_t)(ne + t) * N + x] = mp_final<MODE != 2>(a1[jj], P);
   }
 }
 
@@ -167,16 +185,15 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
   const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
   const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
   const u32 b0 = grp * W;
-  const bool lks = P.q < kLazyKS, lmp = P.q < kLazyMP;
-  if (lks && lmp)
-    ks_ext_lds_body<BETA, JC, W, true, true>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
-                                             dstride, alpha, n1, b0, x0, t, sh);
-  else if (lks)
-    ks_ext_lds_body<BETA, JC, W, true, false>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
-                                              dstride, alpha, n1, b0, x0, t, sh);
+  if (P.q < kLazyMP)
+    ks_ext_lds_body<BETA, JC, W, 0>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
+                                    alpha, n1, b0, x0, t, sh);
+  else if (BETA <= 4 && P.q < kMidQ)
+    ks_ext_lds_body<BETA, JC, W, 1>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
+                                    alpha, n1, b0, x0, t, sh);
   else
-    ks_ext_lds_body<BETA, JC, W, false, false>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr,
-                                               dstride, alpha, n1, b0, x0, t, sh);
+    ks_ext_lds_body<BETA, JC, W, 2>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
+                                    alpha, n1, b0, x0, t, sh);
 }
 
 }  // namespace
@@ -190,12 +207,18 @@ int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, c
 #define HE_LAUNCH_LX(BT, J, WW)                                                                                   \
   HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW>), grid_l, dim3(64 * WW), c->stream, ext, own, keys, in, pts, sqp,         \
             c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)
+#define HE_LX_W(BT, J)                                                                      \
+  do {                                                                                      \
+    if (W == 16) HE_LAUNCH_LX(BT, J, 16);                                                   \
+    else if (W == 8) HE_LAUNCH_LX(BT, J, 8);                                                \
+    else HE_LAUNCH_LX(BT, J, 4);                                                            \
+  } while (0)
 #define HE_LX_J(BT)                                                                         \
   switch (n2) {                                                                             \
-    case 8: if (W == 8) HE_LAUNCH_LX(BT, 8, 8); else HE_LAUNCH_LX(BT, 8, 4); break;          \
-    case 4: if (W == 8) HE_LAUNCH_LX(BT, 4, 8); else HE_LAUNCH_LX(BT, 4, 4); break;          \
-    case 2: if (W == 8) HE_LAUNCH_LX(BT, 2, 8); else HE_LAUNCH_LX(BT, 2, 4); break;          \
-    default: if (W == 8) HE_LAUNCH_LX(BT, 1, 8); else HE_LAUNCH_LX(BT, 1, 4); break;         \
+    case 8: HE_LX_W(BT, 8); break;                                                          \
+    case 4: HE_LX_W(BT, 4); break;                                                          \
+    case 2: HE_LX_W(BT, 2); break;                                                          \
+    default: HE_LX_W(BT, 1); break;                                                         \
   }
   switch (beta) {
     case 1: HE_LX_J(1); break;
@@ -209,6 +232,7 @@ int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, c
     default: return HE_EPARAM;
   }
 #undef HE_LX_J
+#undef HE_LX_W
 #undef HE_LAUNCH_LX
   return ok();
 }

@@ -82,6 +82,35 @@ __device__ __forceinline__ u64 mp_final(u64 acc, const PrimeConst& k) {
   return csub_neg(csub_neg(acc, k.nq2), k.nq);
 }
 
+// Key inner product of the fused kernels for 2^55 <= q < 2^60 and at most 4
+// digits: the products (each in [0, 4q)) summed without reduction (below 16q
+// < 2^64), then one conditional subtraction of 8q (below 8q, so that the lift
+// of c0, below 2q, can still be added).  The fused kernels' consumers take any
+// 64-bit input and reduce at the end, so no other reduction is needed.
+template <int BETA>
+__device__ __forceinline__ void ks_dot_mid(const u64 (&x)[BETA], const u64 (&kb)[BETA], const u64 (&kbs)[BETA],
+                                           const u64 (&ka)[BETA], const u64 (&kas)[BETA], const PrimeConst& P,
+                                           u64& ob, u64& oa) {
+  static_assert(BETA <= 4, "the lazy sum of at most 4 products stays below 16q");
+  u64 sb = 0, sa = 0;
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    sb = add_shoup4(sb, x[j], kb[j], kbs[j], P.nq);
+    sa = add_shoup4(sa, x[j], ka[j], kas[j], P.nq);
+  }
+  ob = csub_signed(sb, P.q << 3);
+  oa = csub_signed(sa, P.q << 3);
+}
+// Inner sums of the fused kernels for 2^55 <= q < 2^60: products (each below
+// 4q) added without reduction and the running sum brought below 3q by
+// reduce_lazy before every third product (at most 3q + 3 * 4q = 15q < 2^64);
+// closed by mp_final<true>.
+constexpr u64 kMidQ = 1ull << 60;
+__device__ __forceinline__ u64 mp_add_mid(u64 acc, u64 x, u64 pt, u64 ps, const PrimeConst& k, bool reduce) {
+  if (reduce) acc = reduce_lazy(acc, k.q, k.mu);
+  return acc + shoup_lazy4(x, pt, ps, k.q);
+}
+
 inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
 
 }  // namespace

@@ -77,7 +77,7 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
     lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale, qp=True, rs_bits=rs)
     d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True, rs_bits=rs)
     want = [o.dense(c, lay, keys).data for c in cts]
-    for g, w, lds in [(0, 0, 0), (1, 0, 0), (0, 3, 0), (1, 3, 0), (0, 0, 4), (0, 0, 8)]:
+    for g, w, lds in [(0, 0, 0), (1, 0, 0), (0, 3, 0), (1, 3, 0), (0, 0, 4), (0, 0, 8), (0, 0, 16)]:
         ctx.set_knob("ks_fuse_g", g)
         ctx.set_knob("ks_fuse_waves", w)
         ctx.set_knob("ks_fuse_lds", lds)
@@ -102,7 +102,7 @@ def test_knob_api_validation():
     q, p = he.prime_chain(12, [50, 40], [50])
     ctx = he.Context(12, q, p, 1)
     defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
-                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 0, "trace": 0}
+                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
     for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
