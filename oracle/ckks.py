@@ -28,7 +28,13 @@ from .params import Params
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cpp", "ckks_oracle.cpp")
-_LIB = os.path.join(_HERE, "cpp", "liboracle.so")
+# ORACLE_SANITIZE=1: the same source built with AddressSanitizer and
+# UndefinedBehaviorSanitizer (errors fatal), for a test run of the pins under
+# them (the process must preload the ASan runtime).
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "cpp", "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_FLAGS = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+          if _SANITIZE else ["-O2"])
 
 U64P = C.POINTER(C.c_uint64)
 I64P = C.POINTER(C.c_int64)
@@ -39,7 +45,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle core with g++ (plain C++17, OpenMP over limbs)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["g++", *_FLAGS, "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -146,6 +146,17 @@ def plan_network(log_n: int, q, p, alpha: int, scale_bits: int, shapes) -> NetPl
     return pl
 
 
+# Bounds of the fold: the square's input is shifted by d = b / (2a) and the
+# constant a d^2 = b^2 / (4a) is cancelled by the next bias.  Both grow as |a|
+# shrinks: the encrypted values grow with |d| (eating scale headroom) and the
+# encrypted a (h + d)^2 carries a rounding error proportional to a d^2 that the
+# bias no longer cancels.  Within these bounds the folded networks stay inside
+# the 2^-12 logit tolerance at the configured scales; beyond them the fold is
+# refused.
+FOLD_MAX_SHIFT = 8.0
+FOLD_MAX_CANCEL = 8.0
+
+
 def fold_quadratic_activations(weights, biases, acts):
     """Collapse per-feature quadratic activations a x^2 + b x + c (paper,
     "Non-convolutional layers": bias, batch normalisation and the polynomial
@@ -154,7 +165,8 @@ def fold_quadratic_activations(weights, biases, acts):
         a x^2 + b x + c = a (x + d)^2 + e,   d = b / (2a),  e = c - a d^2,
     d moves into the bias of the layer before, a scales the columns of the
     next layer's weights and W_next e moves into its bias.  Needs a != 0 in
-    every feature.  Returns new (weights, biases) lists (FP64); the network
+    every feature, |b / 2a| <= FOLD_MAX_SHIFT and |b^2 / 4a| <= FOLD_MAX_CANCEL
+    (ValueError otherwise).  Returns new (weights, biases) lists (FP64); the network
     W_L(... (W_1 x + b_1)^2 ...) + b_L with them equals the original one."""
     Ws = [np.array(W, dtype=np.float64) for W in weights]
     bs = [np.array(b, dtype=np.float64) for b in biases]
@@ -163,6 +175,10 @@ def fold_quadratic_activations(weights, biases, acts):
         if np.any(a == 0):
             raise ValueError("a quadratic activation with a = 0 cannot be folded into a square")
         d = b / (2.0 * a)
+        if np.max(np.abs(d)) > FOLD_MAX_SHIFT or np.max(np.abs(a * d * d)) > FOLD_MAX_CANCEL:
+            raise ValueError(f"activation {i}: a too small for its b (|b / 2a| up to {np.max(np.abs(d)):.3g}, "
+                             f"|b^2 / 4a| up to {np.max(np.abs(a * d * d)):.3g}; the fold allows "
+                             f"{FOLD_MAX_SHIFT} and {FOLD_MAX_CANCEL})")
         e = c - a * d * d
         bs[i] = bs[i] + d
         bs[i + 1] = bs[i + 1] + Ws[i + 1] @ e

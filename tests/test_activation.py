@@ -38,6 +38,42 @@ def test_fold_identity_and_rejection():
         netplan.fold_quadratic_activations(Ws, bs, [(np.array([1.0, 0.0, 1.0, 1.0]), ones, zeros)])
 
 
+def test_fold_bounds_small_a():
+    """A small |a| against its b is refused (shift b / 2a or cancelled constant
+    b^2 / 4a beyond the bounds), also for a negative a; the largest allowed
+    shift folds and still equals the direct FP64 network."""
+    layers = [(4, 8, 2), (2, 4, 2)]
+    Ws, bs = synth.network_weights(layers, 0.1)
+    ones, zeros = np.ones(4), np.zeros(4)
+    for a in (1e-3, -1e-3, 0.02):
+        with pytest.raises(ValueError):
+            netplan.fold_quadratic_activations(Ws, bs, [(np.full(4, a), np.full(4, 0.5), zeros)])
+    a, b = 0.05, 0.79                      # shift 7.9, cancelled constant 3.12: inside the bounds
+    acts = [(np.full(4, a), np.full(4, b), np.full(4, 0.1))]
+    Wf, bf = netplan.fold_quadratic_activations(Ws, bs, acts)
+    x = synth.request_input(8, 0)
+    want = plainnet.forward(x, Ws, bs, acts)
+    assert np.max(np.abs(plainnet.forward(x, Wf, bf) - want)) <= 1e-12
+
+
+def test_network_cfg1_quadratic_oracle_at_fold_bound(oracle_lib):
+    """The cfg1 network with every activation at the largest allowed shift
+    (a = 0.05, b = 0.79: shift 7.9): the CPU oracle's RNS-CKKS evaluation of
+    the folded network is within 2^-12 of the FP64 quadratic network."""
+    pr = params.preset("cfg1")
+    o = ckks.Oracle(pr)
+    Ws, bs = synth.network_weights(pr.layers, pr.sigma_w)
+    m1 = pr.layers[0][0]
+    acts = [(np.full(m1, 0.05), np.full(m1, 0.79), np.full(m1, 0.1))]
+    Wf, bf = netplan.fold_quadratic_activations(Ws, bs, acts)
+    keys = o.keygen(synth.SEED_KEYS, ckks.network_steps(pr.layers))
+    lays = o.prepare_network(Wf, bf, [l[2] for l in pr.layers])
+    x = synth.request_input(pr.layers[0][1], 0)
+    ct = o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(0))
+    y = o.decrypt_decode(o.eval_network(ct, lays, keys), keys.sk).real[:2]
+    assert np.max(np.abs(y - plainnet.forward(x, Ws, bs, acts))) <= 2.0 ** -12
+
+
 def test_network_cfg1_quadratic_oracle(oracle_lib):
     """RNS-CKKS evaluation (CPU oracle) of the folded network: logits within
     2^-12 of the FP64 network with the quadratic activation, same class."""
