@@ -73,6 +73,10 @@ PrimeConst make_pc(u64 q, u32 N) {
   p.mu = ~(u64)0 / q;
   p.rmod = (u64)(((u128)1 << 64) % q);
   p.rmod_sh = shoup_of(p.rmod, q);
+  p.t28 = (u64)(((u128)1 << 28) % q);
+  p.t28_sh = shoup_of(p.t28, q);
+  p.t56 = (u64)(((u128)1 << 56) % q);
+  p.t56_sh = shoup_of(p.t56, q);
   p.ninv = inv_mod(N, q);
   p.ninv_sh = shoup_of(p.ninv, q);
   p.nq = (u64)0 - q;

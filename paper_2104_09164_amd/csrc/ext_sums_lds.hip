@@ -23,6 +23,7 @@ namespace {
 // wave moves (W waves: wave w moves kind w mod 4 of the digits j = w / 4,
 // w / 4 + W / 4, ...) and plaintext rows each wave moves.
 constexpr int lds_nw(int beta, int jc) { return 4 * beta + 2 * jc; }
+constexpr u64 kLow28 = (1ull << 28) - 1;
 constexpr int lds_kr(int beta, int w) { return (beta + w / 4 - 1) / (w / 4); }
 constexpr int lds_pr(int jc, int w) { return (2 * jc + w - 1) / w; }
 constexpr int lds_st(int beta, int jc, int w) { return lds_kr(beta, w) + lds_pr(jc, w); }
@@ -31,7 +32,7 @@ constexpr int lds_st(int beta, int jc, int w) { return lds_kr(beta, w) + lds_pr(
 // b, 1: b companion, 2: a, 3: a companion); row 4 beta + 2 jj + {0, 1} the
 // plaintext word and companion of giant sum jj.  The wave index is read into
 // a scalar register, so every branch on a row is uniform over the wave.
-template <int BETA, int JC, int W>
+template <int BETA, int JC, int W, int MODE>
 __device__ __forceinline__ void lds_tile_load(u64 (&st)[lds_st(BETA, JC, W)], u32 w, u32 i,
                                               const u64* __restrict__ key, const u64* __restrict__ pts,
                                               const PrimeConst& P, u32 N, u32 ne, u32 nt, u32 pr, u32 t, u32 n1,
@@ -51,8 +52,15 @@ __device__ __forceinline__ void lds_tile_load(u64 (&st)[lds_st(BETA, JC, W)], u3
     const u32 pw = w + W * r;                          // plaintext row (of 2 JC)
     if (pw < 2 * JC) {
       const u32 jj = pw >> 1;
-      if (!pts) st[KR + r] = pw & 1 ? P.mu : 1;       // no plaintexts: a plain sum (x 1, companion mu)
-      else st[KR + r] = pts[(pw & 1 ? comp : 0) + (((size_t)n1 * jj + i) * ne + t) * N + x];
+      if (MODE == 3) {
+        // 28-bit columns of the plaintext word: low 28 bits (row 2 jj), the rest (row 2 jj + 1)
+        const u64 v = pts ? pts[(((size_t)n1 * jj + i) * ne + t) * N + x] : 1;
+        st[KR + r] = pw & 1 ? v >> 28 : v & kLow28;
+      } else if (!pts) {
+        st[KR + r] = pw & 1 ? P.mu : 1;                // no plaintexts: a plain sum (x 1, companion mu)
+      } else {
+        st[KR + r] = pts[(pw & 1 ? comp : 0) + (((size_t)n1 * jj + i) * ne + t) * N + x];
+      }
     }
   }
 }
@@ -75,9 +83,33 @@ __device__ __forceinline__ void lds_tile_store(const u64 (&st)[lds_st(BETA, JC, 
   }
 }
 
+// One product r b of the MODE 3 column sums (b given as its 28-bit columns
+// b0, b1): four 32 x 32 -> 64-bit multiply-adds.
+__device__ __forceinline__ void col_mad(u64 (&c)[3], u64 r, u64 b0, u64 b1) {
+  const u32 a0 = (u32)(r & kLow28), a1 = (u32)(r >> 28);
+  c[0] = (u64)a0 * (u32)b0 + c[0];
+  c[1] = (u64)a0 * (u32)b1 + c[1];
+  c[1] = (u64)a1 * (u32)b0 + c[1];
+  c[2] = (u64)a1 * (u32)b1 + c[2];
+}
+// C0 + C1 2^28 + C2 2^56 mod q, in [0, q).
+__device__ __forceinline__ u64 col_final(const u64 (&c)[3], const PrimeConst& P) {
+  u64 v = reduce_lazy(c[0], P.q, P.mu) + shoup_lazy4(c[1], P.t28, P.t28_sh, P.q) +
+          shoup_lazy4(c[2], P.t56, P.t56_sh, P.q);                 // below 11 q
+  v = reduce_lazy(v, P.q, P.mu);
+  return csub_neg(csub_neg(v, P.nq2), P.nq);
+}
+constexpr u64 kWideQ = 1ull << 50;
+
 // MODE 0: q < 2^55 (key sums lazy, inner sums lazy); 1: q < 2^60 with at
 // most 4 digits (ks_dot_mid, mp_add_mid); 2: any other prime (every sum kept
-// below 4q after each term).
+// below 4q after each term); 3: q < 2^50, inner sums as exact integer column
+// sums: r (lazy key sum plus lift, below 34 q < 2^55.1) and the plaintext word
+// (below 2^50) split into 28-bit columns, r = a1 2^28 + a0, pt = b1 2^28 +
+// b0; per product four multiply-adds into C0 += a0 b0 (< 2^56 per term),
+// C1 += a0 b1 + a1 b0 (< 2^55.2), C2 += a1 b1 (< 2^49.1), each below 2^63
+// over at most 65 terms; at the end C0 + C1 2^28 + C2 2^56 reduced mod q.
+// The inner sum is the same integer as the modular one, so the words agree.
 template <int BETA, int JC, int W, int MODE>
 __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, const OwnMap& own,
                                                 const StepKeys& keys, const Items& in, const u64* __restrict__ pts,
@@ -97,13 +129,33 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
   u64 a0[JC], a1[JC];
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) a0[jj] = a1[jj] = 0;
+  u64 w0[MODE == 3 ? JC : 1][3], w1[MODE == 3 ? JC : 1][3];   // MODE 3 column sums
+#pragma unroll
+  for (int jj = 0; jj < (MODE == 3 ? JC : 1); ++jj)
+    w0[jj][0] = w0[jj][1] = w0[jj][2] = w1[jj][0] = w1[jj][1] = w1[jj][2] = 0;
   u64 st[lds_st(BETA, JC, W)];
-  lds_tile_load<BETA, JC, W>(st, w, 0, nullptr, pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
+  lds_tile_load<BETA, JC, W, MODE>(st, w, 0, nullptr, pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
   lds_tile_store<BETA, JC, W>(st, w, 0, sh[0], p);
+  // gathered words of the next baby step (digits at its automorphism of x,
+  // and c0 there), issued one step ahead so that their latency hides behind
+  // the current step's products
+  const u64* e_base = ext + ((size_t)b * dstride * ne + t) * N;
+  const u64* own_base = active ? own.ptr[b] + (size_t)t * N : nullptr;
+  const u64* c0_base = active ? in.p[b] + (size_t)t * N : nullptr;
+  u64 dn[BETA], cn = 0;
   for (u32 i = 0; i < n1; ++i) {
     __syncthreads();                                  // step i's tile is in sh[i & 1]; sh[(i + 1) & 1] is free
+    u64 d[BETA], c0y = cn;
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) d[j] = dn[j];
+    if (active && i + 1 < n1) {
+      const u32 yn = galois_perm(x, keys.galois[i], logn);
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) dn[j] = (u32)j == own_digit ? own_base[yn] : e_base[(size_t)j * ne * N + yn];
+      if (qlimb) cn = c0_base[yn];
+    }
     if (i + 1 < n1)
-      lds_tile_load<BETA, JC, W>(st, w, i + 1, keys.key[i], pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
+      lds_tile_load<BETA, JC, W, MODE>(st, w, i + 1, keys.key[i], pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
     const u64 (*cur)[64] = sh[i & 1];
     if (active) {
       if (i == 0) {
@@ -113,7 +165,10 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
 #pragma unroll
           for (int jj = 0; jj < JC; ++jj) {
             const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
-            if (MODE == 1) {
+            if (MODE == 3) {
+              col_mad(w0[jj], r0, pt, ps);
+              col_mad(w1[jj], r1, pt, ps);
+            } else if (MODE == 1) {
               a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, false);
               a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, false);
             } else {
@@ -123,13 +178,9 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
           }
         }
       } else {
-        const u32 y = galois_perm(x, keys.galois[i - 1], logn);
-        const u64* e = ext + ((size_t)b * dstride * ne + t) * N + y;
-        const u64* src = own.ptr[b];
-        u64 d[BETA], kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
+        u64 kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
-          d[j] = (u32)j == own_digit ? src[(size_t)t * N + y] : e[(size_t)j * ne * N];
           kb[j] = cur[4 * j][p];
           kbs[j] = cur[4 * j + 1][p];
           ka[j] = cur[4 * j + 2][p];
@@ -139,14 +190,17 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
         if (MODE == 1) {
           if constexpr (BETA <= 4) ks_dot_mid<BETA>(d, kb, kbs, ka, kas, P, r0, r1);
         } else {
-          ks_dot<BETA, MODE == 0>(d, kb, kbs, ka, kas, P, false, r0, r1);
+          ks_dot<BETA, MODE == 0 || MODE == 3>(d, kb, kbs, ka, kas, P, false, r0, r1);
         }
-        if (qlimb) r0 += shoup_lazy(in.p[b][(size_t)t * N + y], pw, pws, q);
+        if (qlimb) r0 += shoup_lazy(c0y, pw, pws, q);
         const bool red = i % 3 == 0;                  // the inner sums of MODE 1: reduced before every third product
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
           const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
-          if (MODE == 1) {
+          if (MODE == 3) {
+            col_mad(w0[jj], r0, pt, ps);
+            col_mad(w1[jj], r1, pt, ps);
+          } else if (MODE == 1) {
             a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, red);
             a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, red);
           } else {
@@ -162,8 +216,13 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
     u64* o = sqp + ((size_t)jj * B + b) * 2 * ne * N;
-    o[(size_t)t * N + x] = mp_final<MODE != 2>(a0[jj], P);
-    o[(size_t)(ne + t) * N + x] = mp_final<MODE != 2>(a1[jj], P);
+    if (MODE == 3) {
+      o[(size_t)t * N + x] = col_final(w0[jj], P);
+      o[(size_t)(ne + t) * N + x] = col_final(w1[jj], P);
+    } else {
+      o[(size_t)t * N + x] = mp_final<MODE != 2>(a0[jj], P);
+      o[(size_t)(ne + t) * N + x] = mp_final<MODE != 2>(a1[jj], P);
+    }
   }
 }
 
@@ -185,7 +244,10 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
   const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
   const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
   const u32 b0 = grp * W;
-  if (P.q < kLazyMP)
+  if (P.q < kWideQ)
+    ks_ext_lds_body<BETA, JC, W, 3>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
+                                    alpha, n1, b0, x0, t, sh);
+  else if (P.q < kLazyMP)
     ks_ext_lds_body<BETA, JC, W, 0>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
                                     alpha, n1, b0, x0, t, sh);
   else if (BETA <= 4 && P.q < kMidQ)
@@ -199,10 +261,9 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
 }  // namespace
 
 int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
-                      const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u32 beta, u32 ne,
+                      const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u32 beta, u32 ne, u32 W,
                       TraceScope& ts) {
-  // the LDS-shared form: W = ks_fuse_lds requests (waves) per workgroup, 64 positions
-  const u32 W = (u32)c->ks_fuse_lds;
+  // the LDS-shared form: W requests (waves) per workgroup, 64 positions
   dim3 grid_l(((B + W - 1) / W) * (c->N / 64) * ne);
 #define HE_LAUNCH_LX(BT, J, WW)                                                                                   \
   HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW>), grid_l, dim3(64 * WW), c->stream, ext, own, keys, in, pts, sqp,         \

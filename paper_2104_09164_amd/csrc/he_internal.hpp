@@ -24,6 +24,8 @@ struct PrimeConst {
   u64 w0ni, w0ni_sh;   // inverse stage-0 twiddle psi^{-N/2} times N^{-1}, and its companion
   u64 rmod, rmod_sh;   // 2^64 mod q and its Shoup companion (to Montgomery form)
   u64 nq, nq2, nq4;    // 2^64 - q, 2^64 - 2q, 2^64 - 4q
+  u64 t28, t28_sh;     // 2^28 mod q and its Shoup companion (28-bit column sums)
+  u64 t56, t56_sh;     // 2^56 mod q and its Shoup companion
 };
 
 // Twiddle tables of prime i at tw + i * 4N, as (w, Shoup companion) pairs:

@@ -91,6 +91,7 @@ class Scheduler:
         self.used_bytes = 0
         self.done: list = []
         self.batches: list = []                                 # (backend, stage, size) history
+        self.dispatch_cpu_s = 0.0                               # host time spent enqueuing dispatches
 
     # ---------------------------------------------------------------- api
     def submit(self, req: Request) -> None:
@@ -161,12 +162,14 @@ class Scheduler:
         stage = best.stage
         group = [r for r in self.active[best.net] if r.stage == stage and not self._busy(r)][: be.max_batch]
         now = self.clock()
+        c0 = time.perf_counter()
         try:
             h = be.run(stage, [r.slot for r in group])
         except Exception as e:
             for r in group:
                 self._fail(r, e)
             return None
+        self.dispatch_cpu_s += time.perf_counter() - c0
         self.batches.append((best.net, stage, len(group)))
         for r in group:
             if r.start is None:
@@ -239,6 +242,8 @@ class Scheduler:
             sizes = [s for n, _, s in self.batches if n == name]
             if sizes:
                 out[f"{name}_mean_batch"] = float(np.mean(sizes))
+        out["dispatches"] = len(self.batches)
+        out["dispatch_host_ms_mean"] = 1e3 * self.dispatch_cpu_s / max(1, len(self.batches))
         return out
 
 
@@ -293,11 +298,33 @@ def check_payload(plan, payload) -> None:
         raise ValueError(f"input scale {scale!r}, the network expects {plan.scale!r}")
 
 
+def bucket_sizes(max_batch: int) -> list[int]:
+    """Batch sizes that have a captured graph per stage: 1, 2, 3, 4, 6, 8, 12,
+    16, 24, 32, ... up to max_batch (a dispatch of g requests replays the
+    smallest one >= g; the padding items are computed and discarded)."""
+    out, b = [], 1
+    while b < max_batch:
+        out.append(b)
+        if b >= 2 and b + b // 2 < max_batch:
+            out.append(b + b // 2)
+        b *= 2
+    out.append(max_batch)
+    return sorted(set(out))
+
+
 class NetBackend(Backend):
     """One encrypted network on the HIP library: slot pool of device
-    ciphertext buffers for every stage, batched launches, async import/export."""
+    ciphertext buffers for every stage, batched launches, async import/export.
 
-    def __init__(self, name: str, ctx, plan, layers: list, max_batch: int, slots: int, own_stream: bool = False):
+    graphs=True: every (stage, bucket size) is captured once as a HIP graph
+    over per-stage staging ciphertexts; a dispatch copies its requests' stage
+    inputs into the staging inputs (device to device), replays the graph of
+    the smallest bucket that holds them, and copies the staging outputs into
+    the requests' slots.  The arithmetic is the batched calls' (bit for bit);
+    one graph launch replaces the stage's dozens of kernel launches."""
+
+    def __init__(self, name: str, ctx, plan, layers: list, max_batch: int, slots: int, own_stream: bool = False,
+                 graphs: bool = True):
         import torch
         from . import he
         self.torch, self.he = torch, he
@@ -332,6 +359,56 @@ class NetBackend(Backend):
             self.bufs.append(s)
         self.slot_bytes = sum(ctx.ct_bytes(l) for l in levels) + ctx.ct_bytes(L) + \
             8 * 2 * (L + 1) * N + 8 * 2 * (self.out_level + 1) * N
+        self.levels = levels
+        self.graphs = None
+        if graphs:
+            self._capture(L)
+
+    def _stage_call(self, stage, ins, outs):
+        kind, li = self.stages[stage]
+        if kind == "dense":
+            self.ctx.eval_dense_batch(ins, self.layers[li], outs)
+        elif kind == "rescale":
+            self.ctx.rescale_batch(ins, outs)
+        else:
+            self.ctx.square_batch(ins, outs)
+
+    def _capture(self, L):
+        """Staging ciphertexts per stage and one graph per (stage, bucket)."""
+        torch, ctx = self.torch, self.ctx
+        in_levels = [L] + self.levels[:-1]
+        self.buckets = bucket_sizes(self.max_batch)
+        self.stage_in = [[ctx.new_ct(lv, self.plan.scale) for _ in range(self.max_batch)] for lv in in_levels]
+        self.stage_out = [[ctx.new_ct(lv) for _ in range(self.max_batch)] for lv in self.levels]
+        for c in [c for row in self.stage_in for c in row]:
+            c.buf.zero_()                    # valid residues until the first dispatch overwrites them
+        # staging inputs carry the levels and scales the stages expect
+        scale = self.plan.scale
+        for st, (kind, li) in enumerate(self.stages):
+            for c in self.stage_in[st]:
+                c.scale = scale
+            self._stage_call(st, self.stage_in[st][:1], self.stage_out[st][:1])
+            scale = self.stage_out[st][0].scale
+        torch.cuda.synchronize(ctx.device)
+        self.graphs = {}
+        side = torch.cuda.Stream(device=ctx.device)
+        side.wait_stream(torch.cuda.current_stream(ctx.device))
+        with torch.cuda.stream(side):
+            for st in range(len(self.stages)):
+                for c in self.stage_in[st]:
+                    c.level, c.scale = in_levels[st], self.stage_in[st][0].scale
+                for b in self.buckets:
+                    ctx.use_current_stream()
+                    self._stage_call(st, self.stage_in[st][:b], self.stage_out[st][:b])   # warm-up
+                    side.synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=side):
+                        ctx.use_current_stream()
+                        self._stage_call(st, self.stage_in[st][:b], self.stage_out[st][:b])
+                    self.graphs[(st, b)] = g
+        torch.cuda.current_stream(ctx.device).wait_stream(side)
+        with torch.cuda.stream(self.stream):
+            ctx.use_current_stream()
 
     def _event(self):
         e = self.torch.cuda.Event()
@@ -375,15 +452,18 @@ class NetBackend(Backend):
         return self.bufs[slot]["in"] if stage == 0 else self.bufs[slot]["stage"][stage - 1]
 
     def _run(self, stage, slots):
-        kind, li = self.stages[stage]
         ins = [self._src(s, stage) for s in slots]
         outs = [self.bufs[s]["stage"][stage] for s in slots]
-        if kind == "dense":
-            self.ctx.eval_dense_batch(ins, self.layers[li], outs)
-        elif kind == "rescale":
-            self.ctx.rescale_batch(ins, outs)
-        else:
-            self.ctx.square_batch(ins, outs)
+        if self.graphs is None:
+            self._stage_call(stage, ins, outs)
+            return self._event()
+        b = next(x for x in self.buckets if x >= len(slots))
+        for c, st in zip(ins, self.stage_in[stage]):
+            st.buf.copy_(c.buf, non_blocking=True)
+        self.graphs[(stage, b)].replay()
+        for c, st in zip(outs, self.stage_out[stage]):
+            c.buf.copy_(st.buf, non_blocking=True)
+            c.level, c.scale = st.level, st.scale
         return self._event()
 
     def _export(self, slot):

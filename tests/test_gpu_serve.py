@@ -1,5 +1,7 @@
 """Serving on the GPU: each result is the same alone and in the mix (bit for bit),
-and equals the oracle's evaluation of that request."""
+and equals the oracle's evaluation of that request, with the stages replayed
+from graphs (the default) and launched eagerly; a request with a bad scale
+fails alone."""
 import numpy as np
 import pytest
 
@@ -9,7 +11,7 @@ from paper_2104_09164_amd import netplan, serve, synth
 pytestmark = pytest.mark.gpu
 
 
-def build(pr, shapes, scale_bits, max_batch, slots):
+def build(pr, shapes, scale_bits, max_batch, slots, graphs=True):
     from paper_2104_09164_amd import he
     o = ckks.Oracle(pr)
     keys = o.keygen(1, ckks.network_steps(shapes))
@@ -22,14 +24,16 @@ def build(pr, shapes, scale_bits, max_batch, slots):
     ctx.bind(max_batch, npl.max_n1(), npl.max_n2())
     ctx.load_keys(keys.rlk, keys.rot)
     dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale) for l in lays]
-    be = serve.NetBackend("small", ctx, npl, dls, max_batch=max_batch, slots=slots)
+    be = serve.NetBackend("small", ctx, npl, dls, max_batch=max_batch, slots=slots, graphs=graphs)
     return o, keys, lays, be
 
 
-def test_serving_mix_equals_alone_and_oracle():
+@pytest.mark.parametrize("graphs", [True, False])
+def test_serving_mix_equals_alone_and_oracle(graphs):
+    """Stages replayed from per-(stage, bucket) graphs, and launched eagerly."""
     pr = params.make(12, [50, 40, 40, 40, 40], [50, 50], 2, 30)
     shapes = [(8, 64, 4), (2, 8, 2)]
-    o, keys, lays, be = build(pr, shapes, 30, max_batch=4, slots=6)
+    o, keys, lays, be = build(pr, shapes, 30, max_batch=4, slots=6, graphs=graphs)
     count = 12
     cts = []
     for r in range(count):

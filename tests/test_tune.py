@@ -62,18 +62,19 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
     """The fused lazy-ModDown inner sums (n2 = 1, 2, 4, 8 giant sums) under
     every setting of ks_fuse_g (requests per thread) and ks_fuse_waves (the
     three-waves-per-SIMD build), and in the LDS-shared form (ks_fuse_lds):
-    three requests (a partial last group of requests per thread, an idle wave
-    in the LDS form), each equal to the oracle bit for bit."""
+    nine requests (partial last groups: one request in the last workgroup of
+    four or eight waves, the others idle), each equal to the oracle bit for
+    bit."""
     from oracle import ckks, params, plan
     from paper_2104_09164_amd import he, synth
     pr = params.make(12, [60, 45, 45, 45, 45], [60, 60, 60], 3, 40)
     o = ckks.Oracle(pr)
     keys = o.keygen(1, plan.rotation_steps(m, n, n1, rs))
     ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
-    ctx.bind(3, n1, m // n1)
+    ctx.bind(9, n1, m // n1)
     ctx.load_keys(keys.rlk, keys.rot)
     W, b = synth.network_weights([(m, n, n1)], 0.05)
-    cts = [o.encrypt(plan.input_slots(synth.request_input(n, r), pr.slots), keys.pk, 70 + r) for r in range(3)]
+    cts = [o.encrypt(plan.input_slots(synth.request_input(n, r), pr.slots), keys.pk, 70 + r) for r in range(9)]
     lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale, qp=True, rs_bits=rs)
     d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True, rs_bits=rs)
     want = [o.dense(c, lay, keys).data for c in cts]
