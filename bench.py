@@ -560,10 +560,16 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # folded into a running sum (add_shoup4: 2 v_mul_hi_u32, 3 v_mad_u64_u32,
 # 4 v_mul_lo_u32, 2 v_add3_u32) 11; a plaintext product and its 64-bit
 # accumulation (shoup_lazy4 + add) 14; the lift of c0 by P (Shoup product) 8.
+# Primes below 2^50 in the LDS-shared form (batches of 4 or more) take the
+# inner sums as exact 28-bit column sums: a plaintext product is 4
+# v_mad_u64_u32 (OPS_COL), a plain sum 2 adds (OPS_COL_PLAIN), and splitting
+# each step's value into its two columns 2 (OPS_SPLIT, per value).
 OPS_KEY, OPS_PT, OPS_LIFT = 11, 14, 8
+OPS_COL, OPS_COL_PLAIN, OPS_SPLIT = 4, 2, 2
+WIDE_Q = 1 << 50
 # Kernel classes bound by VALU issue rather than HBM (rocprofv3 SQ counters:
-# VALU instructions issued in about two thirds of the kernel's cycles, HBM
-# traffic a fraction of the copy rate): their roofline is the integer VALU peak.
+# VALU instructions issued in most of the kernel's cycles, HBM traffic a
+# fraction of the copy rate): their roofline is the integer VALU peak.
 ALU_CLASSES = ("ks_inner_ext_multplain",)
 
 
@@ -573,25 +579,35 @@ def fused_ops(plan, batch) -> int:
     coefficient, 2 beta key products and 2 n2 plaintext products on every limb
     of Q_l u P plus the lift of c0 on the Q-limbs; the unrotated term adds 2
     lifts and 2 n2 plaintext products per Q-limb.  Hoisted rotate-and-sum
-    groups of b bits: the same with 2^b - 1 steps, n2 = 1 and the plaintext
-    product replaced by the reduction of each term (a Shoup product by 1)."""
+    groups of b bits: the same with 2^b - 1 steps, n2 = 1 and plain sums.
+    Limbs below 2^50 in batches of 4 or more count the column form of the
+    inner sums (OPS_COL per product, OPS_COL_PLAIN per plain sum, OPS_SPLIT
+    per summed value); the others a Shoup product per term (OPS_PT)."""
     N, K = 1 << plan.log_n, len(plan.p)
     total = 0
     for lay in plan.layers:
         l1 = lay.level + 1
-        ne, beta = l1 + K, -(-l1 // plan.alpha)
+        beta = -(-l1 // plan.alpha)
+        limbs = [(plan.q[t], t < l1) for t in range(l1)] + [(p, False) for p in plan.p]
 
-        def per_item(steps, n2):
-            per_step = ne * (2 * beta * OPS_KEY + 2 * n2 * OPS_PT) + l1 * OPS_LIFT
-            return steps * per_step + l1 * (2 * OPS_LIFT + 2 * n2 * OPS_PT)
+        def per_item(steps, n2, plain):
+            ops = 0
+            for q, qlimb in limbs:
+                col = batch >= 4 and q < WIDE_Q
+                prod = (OPS_COL_PLAIN if plain else OPS_COL) if col else OPS_PT
+                split = 2 * OPS_SPLIT if col else 0
+                ops += steps * (2 * beta * OPS_KEY + 2 * n2 * prod + split + (OPS_LIFT if qlimb else 0))
+                if qlimb:
+                    ops += 2 * OPS_LIFT + 2 * n2 * prod + split
+            return ops
         if lay.qp and lay.n1 > 1 and lay.n2 <= 8:
-            total += batch * N * per_item(lay.n1 - 1, lay.n2)
+            total += batch * N * per_item(lay.n1 - 1, lay.n2, False)
         if lay.rs_bits > 0:
             left = (lay.n // lay.m).bit_length() - 1
             while left > 0:
                 b = min(lay.rs_bits, left)
                 left -= b
-                total += batch * N * per_item((1 << b) - 1, 1)
+                total += batch * N * per_item((1 << b) - 1, 1, True)
     return total
 
 
@@ -611,7 +627,8 @@ def step_roofline(tab, steps, alu_ops_per_step=0, workload="cfg4"):
         head = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                 "unit": "TOP/s (32-bit integer VALU lane ops)", "frac": achieved / VALU_PEAK_TOPS,
                 "alg_ops_per_launch": ops / n,
-                "ops_per_product": {"key": OPS_KEY, "plaintext": OPS_PT, "lift": OPS_LIFT},
+                "ops_per_product": {"key": OPS_KEY, "plaintext": OPS_PT, "lift": OPS_LIFT, "column_product": OPS_COL,
+                                    "column_plain_sum": OPS_COL_PLAIN, "column_split": OPS_SPLIT},
                 "hbm_view": {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}}
     else:
         head = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}

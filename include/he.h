@@ -359,9 +359,10 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   form that shares each baby step's key and plaintext words
  *                   through LDS among that many requests per workgroup (a
  *                   wave per request, one position per thread; halved down to
- *                   4 while a batch does not fill it, batches below 4 take the
- *                   register form); 0 = the register form (requests per
- *                   thread: ks_fuse_g)
+ *                   4 while a batch does not fill it); 0 = the register form
+ *                   (requests per thread: ks_fuse_g)
+ *   "ks_fuse_min_batch"  smallest batch that takes the LDS-shared form
+ *                   (1..64, default 2; smaller batches the register form)
  *   "trace"         1 = bracket every kernel launch with HIP events on the
  *                   context stream (not while the stream is being captured
  *                   into a graph); read with he_trace_read.  0 = off.

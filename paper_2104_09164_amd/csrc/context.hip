@@ -600,6 +600,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse_waves = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_min_batch")) {
+    if (value < 1 || value > HE_MAXB) return HE_EINVAL;
+    c->ks_fuse_min_batch = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "ks_fuse_lds")) {
     if (value != 0 && value != 4 && value != 8 && value != 16) return HE_EINVAL;
     c->ks_fuse_lds = value;
@@ -646,6 +651,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ks_fuse_g")) { *value = c->ks_fuse_g; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_waves")) { *value = c->ks_fuse_waves; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_lds")) { *value = c->ks_fuse_lds; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_min_batch")) { *value = c->ks_fuse_min_batch; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

@@ -155,10 +155,12 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
                 ((double)S * 4.0 * beta * ne + (double)B * (beta * ne + 2.0 * (l + 1) + 2.0 * n2 * ne) +
                  (pts ? 2.0 * n1 * n2 * ne : 0.0)) * (8.0 * (double)c->N));
   // the LDS-shared form with W requests per workgroup, W halved (down to 4)
-  // while the batch does not fill it; batches below 4 take the register form
+  // while the batch does not fill it (idle waves still share the tile
+  // loads); batches below ks_fuse_min_batch take the register form
   u32 W = (u32)c->ks_fuse_lds;
   while (W > 4 && B < W) W /= 2;
-  if (W && B >= W) return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, ts);
+  if (W && B >= (u32)c->ks_fuse_min_batch)
+    return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, ts);
   // items per thread: by default G n2 <= 16 accumulator pairs (each key and
   // plaintext word loaded is used G times); knob ks_fuse_g halves G
   // (fewer registers), knob ks_fuse_waves = 3 compiles for 3 waves per SIMD.

@@ -107,6 +107,7 @@ struct he_ctx {
   int64_t ks_fuse = 1;          // lazy-ModDown baby steps: inner product fused into the inner sums
   int64_t ks_fuse_g = 0;        // fused extended sums: 1 = half the items per thread
   int64_t ks_fuse_waves = 0;    // fused extended sums: 3 = compiled for 3 waves per SIMD
+  int64_t ks_fuse_min_batch = 2;  // fused extended sums: smallest batch that takes the LDS-shared form
   int64_t ks_fuse_lds = 8;      // fused extended sums: 4, 8 or 16 = LDS-shared form with that many requests per
                                 // workgroup (8 measured fastest), 0 = the register form
 

@@ -86,12 +86,18 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
         out = ctx.eval_dense_batch(gs, d)
         for i, (x, y) in enumerate(zip(out, want)):
             assert np.array_equal(ctx.export_ct(x), y), (g, w, lds, i)
+    # one request alone in a workgroup of four (three idle waves), and the register form for it
+    for mb in (1, 2):
+        ctx.set_knob("ks_fuse_lds", 8)
+        ctx.set_knob("ks_fuse_min_batch", mb)
+        g1 = ctx.eval_dense_batch([ctx.import_ct(cts[4].data, cts[4].level, cts[4].scale)], d)
+        assert np.array_equal(ctx.export_ct(g1[0]), want[4]), mb
 
 
 def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
     assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse",
-                                    "ks_fuse_g", "ks_fuse_waves", "ks_fuse_lds"}
+                                    "ks_fuse_g", "ks_fuse_waves", "ks_fuse_lds", "ks_fuse_min_batch"}
     assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
     assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
     assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
@@ -103,11 +109,11 @@ def test_knob_api_validation():
     q, p = he.prime_chain(12, [50, 40], [50])
     ctx = he.Context(12, q, p, 1)
     defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
-                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "trace": 0}
+                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "ks_fuse_min_batch": 2, "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
     for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
-                   ("ks_fuse_g", 2), ("ks_fuse_waves", 2), ("ks_fuse_lds", 2),
+                   ("ks_fuse_g", 2), ("ks_fuse_waves", 2), ("ks_fuse_lds", 2), ("ks_fuse_min_batch", 0),
                    ("ntt_chunk_mb", -1),
                    ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
