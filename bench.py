@@ -780,10 +780,11 @@ def plain_request_leg(reps=50):
     return plan, res
 
 
-def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False):
+def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False, policy="largest"):
     """Poisson arrivals (total rate lambda, the superposition of 256 camera
     streams), 70% small-net / 30% large-net requests, keys and plaintexts
-    resident, admission by device-memory footprint, continuous batching."""
+    resident, admission by device-memory footprint, continuous batching
+    (largest ready stage group first, oldest first past 20 ms of waiting)."""
     import torch
     from paper_2104_09164_amd import serve
     backends = {}
@@ -800,7 +801,7 @@ def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False):
         times = serve.poisson_arrivals(rate, count, seed + int(rate))
         kinds = np.where(rng.random(count) < 0.7, "small", "large")
         reqs = [serve.Request(i, str(kinds[i]), payloads[str(kinds[i])][i % 4], float(times[i])) for i in range(count)]
-        sched = serve.Scheduler(backends, budget_bytes=budget, window=window, per_network=per_network)
+        sched = serve.Scheduler(backends, budget_bytes=budget, window=window, per_network=per_network, policy=policy)
         log(f"serving: {count} requests at {rate} req/s")
         serve.run_arrivals(sched, reqs, timeout_s=120)
         torch.cuda.synchronize()
@@ -814,6 +815,7 @@ def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False):
         m["requests"] = count
         m["p99_tail_samples"] = max(1, int(round(0.01 * m.get("completed", 0))))
         out[str(rate)] = m
+    out["scheduler"] = {"policy": policy, "max_wait_ms": 20.0, "window": window, "per_network": per_network}
     return out
 
 

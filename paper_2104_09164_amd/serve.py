@@ -75,14 +75,20 @@ class Dispatch:
 
 class Scheduler:
     def __init__(self, backends: dict, budget_bytes: int, window: int = 3, clock=time.perf_counter,
-                 per_network: bool = False):
+                 per_network: bool = False, policy: str = "oldest", max_wait_s: float = 0.02):
         """window: dispatches in flight, over all networks, or per network
         when per_network is set (networks on their own streams then never
-        wait for a slot held by another network's batch)."""
+        wait for a slot held by another network's batch).  policy "oldest":
+        the stage of the oldest ready request goes first; "largest": the
+        stage with the most ready requests goes first (larger batches, more
+        throughput under load) unless the oldest ready request has waited
+        longer than max_wait_s since its arrival."""
         self.backends = backends
         self.budget = budget_bytes
         self.window = window
         self.per_network = per_network
+        self.policy = policy
+        self.max_wait_s = max_wait_s
         self.clock = clock
         self.queue: collections.deque = collections.deque()     # arrived, not admitted
         self.active: dict = {k: [] for k in backends}           # admitted, unfinished
@@ -158,6 +164,18 @@ class Scheduler:
                     break
         if best is None:
             return None
+        if self.policy == "largest" and self.clock() - best.arrival <= self.max_wait_s:
+            # the stage group with the most ready requests (ties: the oldest)
+            count = {}
+            for name, reqs in self.active.items():
+                if self.per_network and sum(d.backend == name for d in self.inflight) >= self.window:
+                    continue
+                for r in reqs:
+                    if r.stage < len(self.backends[name].stages) and not self._busy(r):
+                        key = (name, r.stage)
+                        n, first = count.get(key, (0, r))
+                        count[key] = (n + 1, first)
+            best = max(count.values(), key=lambda v: (min(v[0], self.backends[v[1].net].max_batch), -v[1].arrival))[1]
         be = self.backends[best.net]
         stage = best.stage
         group = [r for r in self.active[best.net] if r.stage == stage and not self._busy(r)][: be.max_batch]

@@ -273,3 +273,32 @@ def test_check_payload_rejects_what_fails_a_batch():
     for b in bad:
         with pytest.raises(ValueError):
             serve.check_payload(npl, b)
+
+
+@pytest.mark.parametrize("policy,max_wait,size", [("oldest", 1.0, 1), ("largest", 1.0, 3), ("largest", 0.0, 1)])
+def test_policy_largest_group_first(net, policy, max_wait, size):
+    """One request is a stage ahead of three newer ones.  Oldest-first runs
+    its stage alone; largest-first runs the three together, unless the older
+    request has waited longer than the cap.  Results bit for bit either way."""
+    clock = SimClock()
+    pr, o, keys, layers, _ = net
+    be = OracleBackend("small", o, keys, layers, clock, per_item=0.0)
+    sched = serve.Scheduler({"small": be}, budget_bytes=10 ** 9, window=1, clock=clock.now,
+                            policy=policy, max_wait_s=max_wait)
+    reqs = requests(net, 4, [0.0] * 4)
+    inputs = {r.rid: r.payload.copy() for r in reqs}
+    sched.submit(reqs[0])
+    sched.step()                        # admitted, its import in flight
+    clock.sleep(0.002)
+    assert sched.step() == 1 and sched.batches[-1] == ("small", 0, 1)
+    for r in reqs[1:]:
+        sched.submit(r)
+    sched.step()                        # admitted behind the in-flight stage
+    clock.sleep(0.01)
+    assert sched.step() == 1
+    assert sched.batches[-1][2] == size
+    serve.run_arrivals(sched, [], clock=clock.now, sleep=clock.sleep, timeout_s=5.0)
+    assert sorted(r.rid for r in sched.done) == [0, 1, 2, 3]
+    for r in sched.done:
+        assert r.error is None
+        assert np.array_equal(r.result.data, expected(net, inputs[r.rid]).data)
