@@ -560,13 +560,17 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # folded into a running sum (add_shoup4: 2 v_mul_hi_u32, 3 v_mad_u64_u32,
 # 4 v_mul_lo_u32, 2 v_add3_u32) 11; a plaintext product and its 64-bit
 # accumulation (shoup_lazy4 + add) 14; the lift of c0 by P (Shoup product) 8.
-# Primes below 2^50 in the LDS-shared form (batches of 4 or more) take the
+# Primes below 2^50 in the LDS-shared form (batches of 2 or more) take the
 # inner sums as exact 28-bit column sums: a plaintext product is 4
 # v_mad_u64_u32 (OPS_COL), a plain sum 2 adds (OPS_COL_PLAIN), and splitting
-# each step's value into its two columns 2 (OPS_SPLIT, per value).
+# each step's value into its two columns 2 (OPS_SPLIT, per value).  The
+# LDS-shared form reads the lift P c0 formed once per coefficient (the
+# lift_c0 kernel, a class of its own): one 64-bit add per step (OPS_LIFT_ADD).
 OPS_KEY, OPS_PT, OPS_LIFT = 11, 14, 8
 OPS_COL, OPS_COL_PLAIN, OPS_SPLIT = 4, 2, 2
+OPS_LIFT_ADD = 1
 WIDE_Q = 1 << 50
+LDS_MIN_BATCH = 2
 # Kernel classes bound by VALU issue rather than HBM (rocprofv3 SQ counters:
 # VALU instructions issued in most of the kernel's cycles, HBM traffic a
 # fraction of the copy rate): their roofline is the integer VALU peak.
@@ -580,9 +584,11 @@ def fused_ops(plan, batch) -> int:
     of Q_l u P plus the lift of c0 on the Q-limbs; the unrotated term adds 2
     lifts and 2 n2 plaintext products per Q-limb.  Hoisted rotate-and-sum
     groups of b bits: the same with 2^b - 1 steps, n2 = 1 and plain sums.
-    Limbs below 2^50 in batches of 4 or more count the column form of the
-    inner sums (OPS_COL per product, OPS_COL_PLAIN per plain sum, OPS_SPLIT
-    per summed value); the others a Shoup product per term (OPS_PT)."""
+    Limbs below 2^50 in batches of 2 or more (the LDS-shared form) count the
+    column form of the inner sums (OPS_COL per product, OPS_COL_PLAIN per
+    plain sum, OPS_SPLIT per summed value); the others a Shoup product per
+    term (OPS_PT).  In that form the lift is read (OPS_LIFT_ADD per step, the
+    unrotated term's P c0 free)."""
     N, K = 1 << plan.log_n, len(plan.p)
     total = 0
     for lay in plan.layers:
@@ -592,13 +598,15 @@ def fused_ops(plan, batch) -> int:
 
         def per_item(steps, n2, plain):
             ops = 0
+            lds = batch >= LDS_MIN_BATCH
             for q, qlimb in limbs:
-                col = batch >= 4 and q < WIDE_Q
+                col = lds and q < WIDE_Q
                 prod = (OPS_COL_PLAIN if plain else OPS_COL) if col else OPS_PT
                 split = 2 * OPS_SPLIT if col else 0
-                ops += steps * (2 * beta * OPS_KEY + 2 * n2 * prod + split + (OPS_LIFT if qlimb else 0))
+                lift = (OPS_LIFT_ADD if lds else OPS_LIFT) if qlimb else 0
+                ops += steps * (2 * beta * OPS_KEY + 2 * n2 * prod + split + lift)
                 if qlimb:
-                    ops += 2 * OPS_LIFT + 2 * n2 * prod + split
+                    ops += (1 if lds else 2) * OPS_LIFT + 2 * n2 * prod + split
             return ops
         if lay.qp and lay.n1 > 1 and lay.n2 <= 8:
             total += batch * N * per_item(lay.n1 - 1, lay.n2, False)
@@ -628,7 +636,8 @@ def step_roofline(tab, steps, alu_ops_per_step=0, workload="cfg4"):
                 "unit": "TOP/s (32-bit integer VALU lane ops)", "frac": achieved / VALU_PEAK_TOPS,
                 "alg_ops_per_launch": ops / n,
                 "ops_per_product": {"key": OPS_KEY, "plaintext": OPS_PT, "lift": OPS_LIFT, "column_product": OPS_COL,
-                                    "column_plain_sum": OPS_COL_PLAIN, "column_split": OPS_SPLIT},
+                                    "column_plain_sum": OPS_COL_PLAIN, "column_split": OPS_SPLIT,
+                                    "lift_read": OPS_LIFT_ADD},
                 "hbm_view": {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}}
     else:
         head = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}

@@ -218,7 +218,7 @@ static const char* kTraceNames[TK_COUNT] = {
     "ntt_fwd_phaseA", "ntt_fwd_phaseB", "ntt_inv_phaseB", "ntt_inv_phaseA", "ntt_fwd_onepass", "ntt_inv_onepass",
     "ntt15_fwd", "ntt15_inv", "modup_conv", "ks_inner_steps", "moddown_conv", "ks_final", "ks_final_steps",
     "ks_final_multplain", "ks_final_sum", "ext_multplain", "ks_inner_ext_multplain", "moddown_final", "multplain_accumulate", "multplain", "tensor", "rescale_reduce", "rescale_final", "add",
-    "add_plain", "copy_polys", "shoup_companion", "client_fft", "client_elementwise"};
+    "add_plain", "copy_polys", "shoup_companion", "lift_c0", "client_fft", "client_elementwise"};
 
 const char* trace_name(int kind) { return kind >= 0 && kind < TK_COUNT ? kTraceNames[kind] : "?"; }
 

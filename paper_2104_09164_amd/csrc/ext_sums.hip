@@ -146,7 +146,7 @@ k_ks_ext_fused(const u64* __restrict__ ext, OwnMap own, StepKeys keys,
 }  // namespace
 
 int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
-                        const StepKeys& keys, const Items& in, const u64* pts, u64* sqp) {
+                        const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u64* lift) {
   const u32 beta = digits_at(c, l), ne = l + 1 + c->np, S = n1 - 1;
   if (n1 < 2 || S > HE_MAX_STEPS || !(n2 == 1 || n2 == 2 || n2 == 4 || n2 == 8) || B != in.n || (!pts && n2 != 1))
     return HE_EINVAL;
@@ -160,7 +160,7 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
   u32 W = (u32)c->ks_fuse_lds;
   while (W > 4 && B < W) W /= 2;
   if (W && B >= (u32)c->ks_fuse_min_batch)
-    return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, ts);
+    return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, lift, ts);
   // items per thread: by default G n2 <= 16 accumulator pairs (each key and
   // plaintext word loaded is used G times); knob ks_fuse_g halves G
   // (fewer registers), knob ks_fuse_waves = 3 compiles for 3 waves per SIMD.

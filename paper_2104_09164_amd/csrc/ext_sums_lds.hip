@@ -15,9 +15,12 @@ namespace {
 // key words and 2 JC plaintext words per position) are loaded once per
 // workgroup into an LDS buffer, double-buffered: the loads of step i + 1 are
 // issued before step i is computed and stored to LDS after it, with one
-// barrier per step that every thread reaches.  Digits and c0 are gathered at
-// y = perm_{g_i}(x) per request as in the register form, and every product
-// and sum is the register form's, in the same order: the same words.
+// barrier per step that every thread reaches.  Digits are gathered at y =
+// perm_{g_i}(x) per request as in the register form, and so is the lift P c0
+// mod q, formed once per position by k_lift_c0 (the register form multiplies
+// c0(y) by P at every step); the sums are the register form's up to the
+// representative of each lazy term, and the words written (in [0, q)) are
+// the same.
 // Words per position per step (4 per digit: key b, its companion, key a,
 // its companion; 2 per giant sum: plaintext and companion), key rows each
 // wave moves (W waves: wave w moves kind w mod 4 of the digits j = w / 4,
@@ -104,7 +107,7 @@ constexpr u64 kWideQ = 1ull << 50;
 // MODE 0: q < 2^55 (key sums lazy, inner sums lazy); 1: q < 2^60 with at
 // most 4 digits (ks_dot_mid, mp_add_mid); 2: any other prime (every sum kept
 // below 4q after each term); 3: q < 2^50, inner sums as exact integer column
-// sums: r (lazy key sum plus lift, below 34 q < 2^55.1) and the plaintext word
+// sums: r (lazy key sum plus lift, below 33 q < 2^55.1) and the plaintext word
 // (below 2^50) split into 28-bit columns, r = a1 2^28 + a0, pt = b1 2^28 +
 // b0; per product four multiply-adds into C0 += a0 b0 (< 2^56 per term),
 // C1 += a0 b1 + a1 b0 (< 2^55.2), C2 += a1 b1 (< 2^49.1), each below 2^63
@@ -115,7 +118,8 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
                                                 const StepKeys& keys, const Items& in, const u64* __restrict__ pts,
                                                 u64* __restrict__ sqp, const PrimeConst& P, u64 pw, u64 pws, u32 N,
                                                 u32 logn, u32 l, u32 nt, u32 ne, u32 pr, u32 dstride, u32 alpha,
-                                                u32 n1, u32 b0, u32 x0, u32 t, u64 (*sh)[lds_nw(BETA, JC)][64]) {
+                                                u32 n1, u32 b0, u32 x0, u32 t, u64 (*sh)[lds_nw(BETA, JC)][64],
+                                                const u64* __restrict__ c0p) {
   const u32 B = in.n;
   const u32 p = threadIdx.x & 63;
   const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // the wave: request b0 + w
@@ -129,9 +133,10 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
   u64 a0[JC], a1[JC];
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) a0[jj] = a1[jj] = 0;
-  u64 w0[MODE == 3 ? JC : 1][3], w1[MODE == 3 ? JC : 1][3];   // MODE 3 column sums
+  constexpr bool COLS = MODE == 3;
+  u64 w0[COLS ? JC : 1][3], w1[COLS ? JC : 1][3];   // MODE 3 column sums
 #pragma unroll
-  for (int jj = 0; jj < (MODE == 3 ? JC : 1); ++jj)
+  for (int jj = 0; jj < (COLS ? JC : 1); ++jj)
     w0[jj][0] = w0[jj][1] = w0[jj][2] = w1[jj][0] = w1[jj][1] = w1[jj][2] = 0;
   u64 st[lds_st(BETA, JC, W)];
   lds_tile_load<BETA, JC, W, MODE>(st, w, 0, nullptr, pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
@@ -141,13 +146,13 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
   // the current step's products
   const u64* e_base = ext + ((size_t)b * dstride * ne + t) * N;
   const u64* own_base = active ? own.ptr[b] + (size_t)t * N : nullptr;
-  const u64* c0_base = active ? in.p[b] + (size_t)t * N : nullptr;
+  // the lift P c0 mod q of the request, formed for every position by k_lift_c0
+  const u64* c0_base = active && qlimb ? c0p + ((size_t)b * (l + 1) + t) * N : nullptr;
   u64 dn[BETA], cn = 0;
-  for (u32 i = 0; i < n1; ++i) {
-    __syncthreads();                                  // step i's tile is in sh[i & 1]; sh[(i + 1) & 1] is free
-    u64 d[BETA], c0y = cn;
-#pragma unroll
-    for (int j = 0; j < BETA; ++j) d[j] = dn[j];
+  // with step i's tile in sh[i & 1]: issue the gathers and the tile loads of
+  // step i + 1 (before step i is computed), then store that tile to the other
+  // buffer (after)
+  auto issue = [&](u32 i) {
     if (active && i + 1 < n1) {
       const u32 yn = galois_perm(x, keys.galois[i], logn);
 #pragma unroll
@@ -156,28 +161,43 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
     }
     if (i + 1 < n1)
       lds_tile_load<BETA, JC, W, MODE>(st, w, i + 1, keys.key[i], pts, P, N, ne, nt, pr, t, n1, kw, comp, x);
+  };
+  auto retire = [&](u32 i) {
+    if (i + 1 < n1) lds_tile_store<BETA, JC, W>(st, w, i + 1, sh[(i + 1) & 1], p);
+  };
+  // step 0 (kept out of the loop, so that the compiler never merges its
+  // operands with the later steps'): the unrotated term (P c0, P c1) on the
+  // Q-limbs
+  __syncthreads();
+  issue(0);
+  if (active && qlimb) {
+    const u64 (*cur)[64] = sh[0];
+    const u64 r0 = c0_base[x], r1 = shoup(in.p[b][(size_t)(l + 1 + t) * N + x], pw, pws, q);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
+      if (COLS) {
+        col_mad(w0[jj], r0, pt, ps);
+        col_mad(w1[jj], r1, pt, ps);
+      } else if (MODE == 1) {
+        a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, false);
+        a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, false);
+      } else {
+        a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
+        a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);
+      }
+    }
+  }
+  retire(0);
+  for (u32 i = 1; i < n1; ++i) {
+    __syncthreads();                                  // step i's tile is in sh[i & 1]; sh[(i + 1) & 1] is free
+    u64 d[BETA], c0y = cn;
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) d[j] = dn[j];
+    issue(i);
     const u64 (*cur)[64] = sh[i & 1];
     if (active) {
-      if (i == 0) {
-        if (qlimb) {
-          const u64* c = in.p[b];
-          const u64 r0 = shoup(c[(size_t)t * N + x], pw, pws, q), r1 = shoup(c[(size_t)(l + 1 + t) * N + x], pw, pws, q);
-#pragma unroll
-          for (int jj = 0; jj < JC; ++jj) {
-            const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
-            if (MODE == 3) {
-              col_mad(w0[jj], r0, pt, ps);
-              col_mad(w1[jj], r1, pt, ps);
-            } else if (MODE == 1) {
-              a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, false);
-              a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, false);
-            } else {
-              a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
-              a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);
-            }
-          }
-        }
-      } else {
+      {
         u64 kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
@@ -192,7 +212,7 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
         } else {
           ks_dot<BETA, MODE == 0 || MODE == 3>(d, kb, kbs, ka, kas, P, false, r0, r1);
         }
-        if (qlimb) r0 += shoup_lazy(c0y, pw, pws, q);
+        if (qlimb) r0 += c0y;                          // below q, read for this step's automorphism
         const bool red = i % 3 == 0;                  // the inner sums of MODE 1: reduced before every third product
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
@@ -210,13 +230,13 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
         }
       }
     }
-    if (i + 1 < n1) lds_tile_store<BETA, JC, W>(st, w, i + 1, sh[(i + 1) & 1], p);
+    retire(i);
   }
   if (!active) return;
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
     u64* o = sqp + ((size_t)jj * B + b) * 2 * ne * N;
-    if (MODE == 3) {
+    if (COLS) {
       o[(size_t)t * N + x] = col_final(w0[jj], P);
       o[(size_t)(ne + t) * N + x] = col_final(w1[jj], P);
     } else {
@@ -232,7 +252,7 @@ template <int BETA, int JC, int W>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
 k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, const u64* __restrict__ pts,
              u64* __restrict__ sqp, const PrimeConst* __restrict__ pc, const u64* __restrict__ md, u32 N, u32 logn,
-             u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1) {
+             u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1, const u64* __restrict__ c0p) {
   __shared__ u64 sh[2][lds_nw(BETA, JC)][64];
   const u32 npb = N / 64, ne = l + 1 + np, nt = nq + np;
   const u32 ngroups = (in.n + W - 1) / W;
@@ -244,30 +264,50 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
   const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
   const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
   const u32 b0 = grp * W;
+#define HE_LDS_BODY(M)                                                                                              \
+  ks_ext_lds_body<BETA, JC, W, M>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride, alpha, \
+                                  n1, b0, x0, t, sh, c0p)
   if (P.q < kWideQ)
-    ks_ext_lds_body<BETA, JC, W, 3>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
-                                    alpha, n1, b0, x0, t, sh);
+    HE_LDS_BODY(3);
   else if (P.q < kLazyMP)
-    ks_ext_lds_body<BETA, JC, W, 0>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
-                                    alpha, n1, b0, x0, t, sh);
+    HE_LDS_BODY(0);
   else if (BETA <= 4 && P.q < kMidQ)
-    ks_ext_lds_body<BETA, JC, W, 1>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
-                                    alpha, n1, b0, x0, t, sh);
+    HE_LDS_BODY(1);
   else
-    ks_ext_lds_body<BETA, JC, W, 2>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride,
-                                    alpha, n1, b0, x0, t, sh);
+    HE_LDS_BODY(2);
+#undef HE_LDS_BODY
+}
+
+// The lift of c0 by P on the Q-limbs, P c0 mod q_t in [0, q_t), for every
+// request b, limb t <= l and position x, at lift + (b (l + 1) + t) N + x:
+// each baby step reads it at its automorphism of x, where the inner sums
+// would otherwise form the product there once per step.  Grid (N / 256,
+// l + 1, B).
+__global__ void __launch_bounds__(256) k_lift_c0(Items in, u64* __restrict__ lift,
+                                                 const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                 u32 N, u32 l, u32 nq, u32 np) {
+  const u32 x = blockIdx.x * 256 + threadIdx.x, t = blockIdx.y, b = blockIdx.z;
+  const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
+  lift[((size_t)b * (l + 1) + t) * N + x] = shoup(in.p[b][(size_t)t * N + x], pmod[2 * t], pmod[2 * t + 1], pc[t].q);
 }
 
 }  // namespace
 
 int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
                       const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u32 beta, u32 ne, u32 W,
-                      TraceScope& ts) {
+                      u64* lift, TraceScope& ts) {
+  if (!lift) return HE_EINVAL;
+  {
+    TraceScope tl(c, TK_LIFT_C0, (double)B * (l + 1) * 16.0 * (double)c->N);
+    HE_LAUNCH(tl, k_lift_c0, dim3(c->N / 256, l + 1, B), dim3(256), c->stream, in, lift, c->d_pc, c->d_moddown,
+              c->N, l, c->nq, c->np);
+  }
+  const u64* c0p = lift;
   // the LDS-shared form: W requests (waves) per workgroup, 64 positions
   dim3 grid_l(((B + W - 1) / W) * (c->N / 64) * ne);
 #define HE_LAUNCH_LX(BT, J, WW)                                                                                   \
   HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW>), grid_l, dim3(64 * WW), c->stream, ext, own, keys, in, pts, sqp,         \
-            c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)
+            c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1, c0p)
 #define HE_LX_W(BT, J)                                                                      \
   do {                                                                                      \
     if (W == 16) HE_LAUNCH_LX(BT, J, 16);                                                   \

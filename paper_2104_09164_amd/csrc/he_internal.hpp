@@ -51,7 +51,7 @@ struct PolyBatch {
 enum TraceKind {
   TK_NTT_FWD_A, TK_NTT_FWD_B, TK_NTT_INV_B, TK_NTT_INV_A, TK_NTT_ONE_FWD, TK_NTT_ONE_INV, TK_NTT15_FWD, TK_NTT15_INV,
   TK_MODUP_CONV, TK_KS_INNER_STEPS, TK_MODDOWN_CONV, TK_KS_FINAL, TK_KS_FINAL_STEPS, TK_KS_FINAL_MP, TK_KS_FINAL_SUM,
-  TK_EXT_MP, TK_KS_EXT_FUSED, TK_MODDOWN_FINAL, TK_MP_ACC, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION,
+  TK_EXT_MP, TK_KS_EXT_FUSED, TK_MODDOWN_FINAL, TK_MP_ACC, TK_MULTPLAIN, TK_TENSOR, TK_RESCALE_REDUCE, TK_RESCALE_FINAL, TK_ADD, TK_ADD_PLAIN, TK_COPY, TK_SHOUP_COMPANION, TK_LIFT_C0,
   TK_CLIENT_FFT, TK_CLIENT_ELEM,
   TK_COUNT
 };

@@ -596,7 +596,8 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       u64* sqp = w.ext;
       if (c->ks_fuse && n2 <= 8) {
         sqp = w.u;
-        if ((rc = launch_ks_ext_fused(c, l, n, n1, n2, w.ext, own_of(n, c1in), sk, inI, d->pts, sqp))) return rc;
+        if ((rc = launch_ks_ext_fused(c, l, n, n1, n2, w.ext, own_of(n, c1in), sk, inI, d->pts, sqp, w.conv)))
+          return rc;
       } else {
         if ((rc = launch_ks_inner_steps(c, l, n, S, w.ext, 0, own_of(n, c1in), sk, w.u))) return rc;
         if ((rc = launch_ext_multplain(c, l, n, n1, n2, w.u, sk, inI, d->pts, w.ext))) return rc;
@@ -712,7 +713,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
     }
     if ((rc = modup(c, l, n, c1, w))) return rc;
     if ((rc = launch_ks_ext_fused(c, l, n, 1u << grp_bits[g], 1, w.ext, own_of(n, c1), grp_keys[g], ci, nullptr,
-                                  w.u)))
+                                  w.u, w.conv)))
       return rc;
     OutMap om;
     std::memset(&om, 0, sizeof(om));

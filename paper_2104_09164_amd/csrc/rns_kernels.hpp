@@ -111,13 +111,15 @@ int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, 
 // from own.ptr[b]): one launch, no per-step products in memory.  n1 >= 2,
 // n2 in {1, 2, 4, 8}, keys = the n1 - 1 baby steps.  pts = null (n2 = 1): the
 // plain sum sqp[b] = sum_{i < n1} r_i(b) (a hoisted rotate-and-sum group).
+// lift: B (l + 1) N words of scratch, free during the call, that the
+// LDS-shared form fills with P c0 mod q on the Q-limbs (required there).
 // The LDS-shared form of launch_ks_ext_fused (ext_sums_lds.hip) with W
 // requests per workgroup (4, 8 or 16), launched inside its trace scope.
 int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
                       const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u32 beta, u32 ne, u32 W,
-                      TraceScope& ts);
+                      u64* lift, TraceScope& ts);
 int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
-                        const StepKeys& keys, const Items& in, const u64* pts, u64* sqp);
+                        const StepKeys& keys, const Items& in, const u64* pts, u64* sqp, u64* lift);
 
 
 // Inner sums of a multi-input linear transform for R requests: term t < T of

@@ -94,6 +94,33 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
         assert np.array_equal(ctx.export_ct(g1[0]), want[4]), mb
 
 
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("qbits,alpha", [(48, 1), (50, 2), (51, 3), (36, 1)])
+def test_fused_lds_at_prime_bounds(qbits, alpha):
+    """The LDS-shared fused inner sums on primes at the bounds of their
+    forms: just below 2^50 (the last primes of the 28-bit column sums), just
+    above it (51-bit primes: the lazy integer sums), 48-bit primes with five
+    digits (the widest key sum here), and 36-bit primes; five requests, each
+    equal to the oracle bit for bit."""
+    from oracle import ckks, params, plan
+    from paper_2104_09164_amd import he, synth
+    m, n, n1 = 8, 64, 4
+    pr = params.make(12, [60] + [qbits] * 4, [60] * 3, alpha, qbits - 5)
+    o = ckks.Oracle(pr)
+    keys = o.keygen(1, plan.rotation_steps(m, n, n1, 0))
+    ctx = he.Context(pr.log_n, pr.q, pr.p, pr.alpha)
+    ctx.bind(5, n1, m // n1)
+    ctx.load_keys(keys.rlk, keys.rot)
+    W, b = synth.network_weights([(m, n, n1)], 0.05)
+    cts = [o.encrypt(plan.input_slots(synth.request_input(n, r), pr.slots), keys.pk, 90 + r) for r in range(5)]
+    lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale, qp=True)
+    d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True)
+    want = [o.dense(c, lay, keys).data for c in cts]
+    out = ctx.eval_dense_batch([ctx.import_ct(c.data, c.level, c.scale) for c in cts], d)
+    for i, (x, y) in enumerate(zip(out, want)):
+        assert np.array_equal(ctx.export_ct(x), y), (qbits, alpha, i)
+
 def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
     assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse",
