@@ -363,6 +363,11 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   (requests per thread: ks_fuse_g)
  *   "ks_fuse_min_batch"  smallest batch that takes the LDS-shared form
  *                   (1..64, default 2; smaller batches the register form)
+ *   "ks_fuse_pair"  LDS-shared form with 4 or 8 requests: 1 = each
+ *                   workgroup serves two position blocks, X and the block X
+ *                   reads at the first step, so that one block's gathers are
+ *                   the other's of the step before (found in L2: about half
+ *                   the HBM traffic); 0 (default) = one block per workgroup
  *   "trace"         1 = bracket every kernel launch with HIP events on the
  *                   context stream (not while the stream is being captured
  *                   into a graph); read with he_trace_read.  0 = off.

@@ -198,6 +198,43 @@ void free_tables(he_ctx* c) {
   hipFree(c->d_modup_hatmod);
   hipFree(c->d_moddown);
   hipFree(c->d_rescale);
+  hipFree(c->d_pairs);
+  c->d_pairs = nullptr;
+}
+
+// Position map of the NTT-domain automorphism X -> X^g (output position k
+// reads input position perm(k)), on the host.
+u32 host_galois_perm(u32 k, u32 g, u32 logn) {
+  auto brev = [logn](u32 v) {
+    u32 r = 0;
+    for (u32 i = 0; i < logn; ++i) r |= ((v >> i) & 1u) << (logn - 1 - i);
+    return r;
+  };
+  const u64 two_n = 2ull << logn;
+  const u64 e = (2ull * brev(k) + 1) * g % two_n;
+  return brev((u32)((e - 1) >> 1));
+}
+
+// Block pairs (X, P(X)) along the cycles of the block map P of the
+// automorphism g (64-position blocks map to blocks), covering every block
+// once; false when a cycle has odd length.
+bool block_pairs(u32 logn, u32 g, std::vector<uint16_t>& out) {
+  const u32 npb = (1u << logn) / 64;
+  std::vector<u32> P(npb);
+  for (u32 b = 0; b < npb; ++b) P[b] = host_galois_perm(b * 64, g, logn) / 64;
+  std::vector<char> seen(npb, 0);
+  out.clear();
+  for (u32 b = 0; b < npb; ++b) {
+    if (seen[b]) continue;
+    std::vector<u32> cyc;
+    for (u32 x = b; !seen[x]; x = P[x]) {
+      seen[x] = 1;
+      cyc.push_back(x);
+    }
+    if (cyc.size() % 2) return false;
+    for (size_t i = 0; i < cyc.size(); i += 2) out.push_back((uint16_t)cyc[i]);
+  }
+  return true;
 }
 
 PolyBatch one_item(u64* p, u32 npoly, u32 period, u32 first_prime) {
@@ -399,7 +436,25 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
     const u64 r = (u64)(((steps[u] % half) + half) % half);
     c->rot.push_back({steps[u], (u32)pow_mod(5, r, two_n), dst});
   }
-  return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+  // the block-pair tables of the keys' automorphisms, for the paired form of
+  // the fused extended sums (a key that starts a run of baby steps)
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
+  hipFree(c->d_pairs);
+  c->d_pairs = nullptr;
+  std::vector<uint16_t> all, one;
+  std::vector<long> at(c->rot.size(), -1);
+  for (size_t u = 0; u < c->rot.size(); ++u)
+    if (c->N >= 128 && block_pairs(c->log_n, c->rot[u].galois, one)) {
+      at[u] = (long)all.size();
+      all.insert(all.end(), one.begin(), one.end());
+    }
+  if (!all.empty()) {
+    HE_HIP(hipMalloc((void**)&c->d_pairs, all.size() * sizeof(uint16_t)));
+    HE_HIP(hipMemcpy(c->d_pairs, all.data(), all.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    for (size_t u = 0; u < c->rot.size(); ++u)
+      if (at[u] >= 0) c->rot[u].pairs = c->d_pairs + at[u];
+  }
+  return HE_OK;
 }
 
 int he_dense_load_ex(he_ctx* c, uint32_t level, uint32_t m, uint32_t n, uint32_t n1, const uint64_t* pt_diag,
@@ -605,6 +660,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse_min_batch = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_pair")) {
+    if (value > 1) return HE_EINVAL;
+    c->ks_fuse_pair = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "ks_fuse_lds")) {
     if (value != 0 && value != 4 && value != 8 && value != 16) return HE_EINVAL;
     c->ks_fuse_lds = value;
@@ -652,6 +712,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ks_fuse_waves")) { *value = c->ks_fuse_waves; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_lds")) { *value = c->ks_fuse_lds; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_min_batch")) { *value = c->ks_fuse_min_batch; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_pair")) { *value = c->ks_fuse_pair; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

@@ -119,10 +119,10 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
                                                 u64* __restrict__ sqp, const PrimeConst& P, u64 pw, u64 pws, u32 N,
                                                 u32 logn, u32 l, u32 nt, u32 ne, u32 pr, u32 dstride, u32 alpha,
                                                 u32 n1, u32 b0, u32 x0, u32 t, u64 (*sh)[lds_nw(BETA, JC)][64],
-                                                const u64* __restrict__ c0p) {
+                                                const u64* __restrict__ c0p, u32 w) {
+  // w: the wave within its block's W (uniform), serving request b0 + w
   const u32 B = in.n;
   const u32 p = threadIdx.x & 63;
-  const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // the wave: request b0 + w
   const u32 x = x0 + p, b = b0 + w;
   const bool active = b < B;                          // idle waves still move tiles and reach barriers
   const bool qlimb = t <= l;
@@ -246,19 +246,33 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
   }
 }
 
-// 1-D grid over request groups of W x (N/64, ne) tiles (xcd_decode: the
-// groups of a tile run back to back on one XCD and share its words in L2).
-template <int BETA, int JC, int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
+// 1-D grid over request groups of W x (tiles, ne) (xcd_decode: the groups of
+// a tile run back to back on one XCD and share its words in L2).  H = 1: a
+// tile is one 64-position block.  H = 2: a tile is a pair of blocks (X, P(X))
+// from `pairs`, P the block map of galois[0] (the block step 1 reads), each
+// served by its own W waves with its own LDS tiles; since galois[s] =
+// galois[0]^(s+1), the block that P(X) reads at step i is the one X reads at
+// step i + 1, so X's gathers find the other half's of the step before in L2
+// and every digit block reaches the workgroup from HBM about once per two
+// steps instead of once per step.
+template <int BETA, int JC, int W, int H>
+__global__ void __launch_bounds__(64 * W * H) __attribute__((amdgpu_waves_per_eu(4)))
 k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, const u64* __restrict__ pts,
              u64* __restrict__ sqp, const PrimeConst* __restrict__ pc, const u64* __restrict__ md, u32 N, u32 logn,
              u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1, const u64* __restrict__ c0p) {
-  __shared__ u64 sh[2][lds_nw(BETA, JC)][64];
-  const u32 npb = N / 64, ne = l + 1 + np, nt = nq + np;
+  __shared__ u64 sh[H][2][lds_nw(BETA, JC)][64];
+  const u32 npb = N / 64, ntile = npb / H, ne = l + 1 + np, nt = nq + np;
   const u32 ngroups = (in.n + W - 1) / W;
   u32 grp, tile;
-  xcd_decode(blockIdx.x, ngroups, npb * ne, grp, tile);
-  const u32 x0 = (tile % npb) * 64, t = tile / npb;
+  xcd_decode(blockIdx.x, ngroups, ntile * ne, grp, tile);
+  const u32 wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const u32 h = wv / W, w = wv % W;                   // block h of the tile, wave w of its W
+  u32 blk = tile % ntile;
+  if (H == 2) {
+    blk = keys.pairs[blk];
+    if (h) blk = galois_perm(blk * 64, keys.galois[0], logn) / 64;
+  }
+  const u32 x0 = blk * 64, t = tile / ntile;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
   const PrimeConst P = pc[pr];
   const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
@@ -266,7 +280,7 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
   const u32 b0 = grp * W;
 #define HE_LDS_BODY(M)                                                                                              \
   ks_ext_lds_body<BETA, JC, W, M>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride, alpha, \
-                                  n1, b0, x0, t, sh, c0p)
+                                  n1, b0, x0, t, sh[h], c0p, w)
   if (P.q < kWideQ)
     HE_LDS_BODY(3);
   else if (P.q < kLazyMP)
@@ -303,16 +317,21 @@ int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, c
               c->N, l, c->nq, c->np);
   }
   const u64* c0p = lift;
-  // the LDS-shared form: W requests (waves) per workgroup, 64 positions
-  dim3 grid_l(((B + W - 1) / W) * (c->N / 64) * ne);
-#define HE_LAUNCH_LX(BT, J, WW)                                                                                   \
-  HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW>), grid_l, dim3(64 * WW), c->stream, ext, own, keys, in, pts, sqp,         \
-            c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1, c0p)
+  // the LDS-shared form: W requests (waves) per block, 64 positions, one
+  // block per workgroup or (knob ks_fuse_pair, W <= 8, a run of powers of one
+  // automorphism) a pair of blocks
+  const u32 H = c->ks_fuse_pair && keys.pairs && W <= 8 ? 2 : 1;
+  dim3 grid_l(((B + W - 1) / W) * (c->N / 64 / H) * ne);
+#define HE_LAUNCH_LX(BT, J, WW, HH)                                                                               \
+  HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW, HH>), grid_l, dim3(64 * WW * HH), c->stream, ext, own, keys, in, pts,    \
+            sqp, c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1, c0p)
 #define HE_LX_W(BT, J)                                                                      \
   do {                                                                                      \
-    if (W == 16) HE_LAUNCH_LX(BT, J, 16);                                                   \
-    else if (W == 8) HE_LAUNCH_LX(BT, J, 8);                                                \
-    else HE_LAUNCH_LX(BT, J, 4);                                                            \
+    if (W == 16) HE_LAUNCH_LX(BT, J, 16, 1);                                                \
+    else if (W == 8 && H == 2) HE_LAUNCH_LX(BT, J, 8, 2);                                   \
+    else if (W == 8) HE_LAUNCH_LX(BT, J, 8, 1);                                             \
+    else if (H == 2) HE_LAUNCH_LX(BT, J, 4, 2);                                             \
+    else HE_LAUNCH_LX(BT, J, 4, 1);                                                         \
   } while (0)
 #define HE_LX_J(BT)                                                                         \
   switch (n2) {                                                                             \

@@ -75,6 +75,11 @@ struct KeySlot {
   int32_t step;
   u32 galois;
   u64* dev;         // [dnum][2][L+1+K][N] NTT form, then their Shoup companions (same shape)
+  // Pairs of 64-position blocks (X, P(X)), P the block map of this key's
+  // automorphism (the block step 1 reads), covering every block once: N/128
+  // first blocks, device memory; null when P has a cycle of odd length (the
+  // identity on blocks, for rotations by multiples of N/128 slots).
+  const uint16_t* pairs = nullptr;
 };
 
 struct he_ctx {
@@ -97,6 +102,7 @@ struct he_ctx {
   u64* d_moddown = nullptr;        // [np][2] | [np][nq] | [nq][2]
   // Rescale: qlinv[l][i] (+shoup) = q_l^{-1} mod q_i, i < l
   u64* d_rescale = nullptr;        // [nq][nq][2]
+  uint16_t* d_pairs = nullptr;     // block-pair tables of the rotation keys (KeySlot::pairs)
   std::vector<PrimeConst> h_pc;
 
   // execution knobs (bit-preserving)
@@ -108,6 +114,7 @@ struct he_ctx {
   int64_t ks_fuse_g = 0;        // fused extended sums: 1 = half the items per thread
   int64_t ks_fuse_waves = 0;    // fused extended sums: 3 = compiled for 3 waves per SIMD
   int64_t ks_fuse_min_batch = 2;  // fused extended sums: smallest batch that takes the LDS-shared form
+  int64_t ks_fuse_pair = 0;       // LDS-shared form: pairs of blocks along the automorphism per workgroup
   int64_t ks_fuse_lds = 8;      // fused extended sums: 4, 8 or 16 = LDS-shared form with that many requests per
                                 // workgroup (8 measured fastest), 0 = the register form
 

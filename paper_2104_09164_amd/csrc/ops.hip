@@ -554,6 +554,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
         sk.key[k - 1] = ks->dev;
         sk.galois[k - 1] = ks->galois;
         sk.galois_inv[k - 1] = galois_inverse(c, ks->galois);
+        if (k == 1) sk.pairs = ks->pairs;          // step k rotates by k t: galois[k-1] = galois[0]^k
       }
       grp_bits.push_back(b);
       grp_shift.push_back(t);
@@ -587,6 +588,7 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       sk.galois[i] = baby[i + 1]->galois;
       sk.galois_inv[i] = galois_inverse(c, baby[i + 1]->galois);
     }
+    sk.pairs = baby[1]->pairs;                     // baby step i rotates by i: galois[i] = galois[0]^(i+1)
     if (d->pl > l + 1) {
       // lazy ModDown: the inner products stay over Q_l u P; the inner sums
       // are formed there (the extended rotations only in registers) into

@@ -45,6 +45,10 @@ struct StepKeys {
   const u64* key[HE_MAX_STEPS];   // key of step s ([dnum][2][L+1+K][N] NTT form, then Shoup companions)
   u32 galois[HE_MAX_STEPS];       // its Galois element g
   u32 galois_inv[HE_MAX_STEPS];   // g^{-1} mod 2N
+  // When galois[s] = galois[0]^(s+1) for every s (a run of baby steps or a
+  // hoisted rotate-and-sum group): the block pairs of galois[0]'s key
+  // (KeySlot::pairs), else null.
+  const uint16_t* pairs = nullptr;
 };
 // Source c1 (NTT form) of item (s, b), whose digits' own limbs the inner
 // product reads: base + s os + b ob when base is set, else ptr[b] (same for every s).
