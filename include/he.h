@@ -363,11 +363,16 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   (requests per thread: ks_fuse_g)
  *   "ks_fuse_min_batch"  smallest batch that takes the LDS-shared form
  *                   (1..64, default 2; smaller batches the register form)
+ *   "ks_fuse_orbit" LDS-shared form: 1 (default) = the position blocks
+ *                   dealt to each XCD in the order of the cycles of the first
+ *                   step's automorphism on blocks (block X reads block P(X)),
+ *                   so that the workgroups running together read each
+ *                   other's gathers of the step before from L2; 0 = in
+ *                   address order
  *   "ks_fuse_pair"  LDS-shared form with 4 or 8 requests: 1 = each
- *                   workgroup serves two position blocks, X and the block X
- *                   reads at the first step, so that one block's gathers are
- *                   the other's of the step before (found in L2: about half
- *                   the HBM traffic); 0 (default) = one block per workgroup
+ *                   workgroup serves two position blocks, X and P(X), so that
+ *                   one block's gathers are the other's of the step before;
+ *                   0 (default) = one block per workgroup
  *   "trace"         1 = bracket every kernel launch with HIP events on the
  *                   context stream (not while the stream is being captured
  *                   into a graph); read with he_trace_read.  0 = off.

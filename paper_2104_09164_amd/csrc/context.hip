@@ -198,8 +198,8 @@ void free_tables(he_ctx* c) {
   hipFree(c->d_modup_hatmod);
   hipFree(c->d_moddown);
   hipFree(c->d_rescale);
-  hipFree(c->d_pairs);
-  c->d_pairs = nullptr;
+  hipFree(c->d_orbits);
+  c->d_orbits = nullptr;
 }
 
 // Position map of the NTT-domain automorphism X -> X^g (output position k
@@ -215,26 +215,26 @@ u32 host_galois_perm(u32 k, u32 g, u32 logn) {
   return brev((u32)((e - 1) >> 1));
 }
 
-// Block pairs (X, P(X)) along the cycles of the block map P of the
-// automorphism g (64-position blocks map to blocks), covering every block
-// once; false when a cycle has odd length.
-bool block_pairs(u32 logn, u32 g, std::vector<uint16_t>& out) {
+// The blocks of 64 positions in the order of the cycles of the block map P
+// of the automorphism g (blocks map to blocks: X reads P(X)), each cycle X,
+// P(X), P^2(X), ... in turn; returns whether every cycle has even length.
+bool block_orbits(u32 logn, u32 g, std::vector<uint16_t>& out) {
   const u32 npb = (1u << logn) / 64;
   std::vector<u32> P(npb);
   for (u32 b = 0; b < npb; ++b) P[b] = host_galois_perm(b * 64, g, logn) / 64;
   std::vector<char> seen(npb, 0);
   out.clear();
+  bool even = true;
   for (u32 b = 0; b < npb; ++b) {
     if (seen[b]) continue;
-    std::vector<u32> cyc;
-    for (u32 x = b; !seen[x]; x = P[x]) {
+    size_t len = 0;
+    for (u32 x = b; !seen[x]; x = P[x], ++len) {
       seen[x] = 1;
-      cyc.push_back(x);
+      out.push_back((uint16_t)x);
     }
-    if (cyc.size() % 2) return false;
-    for (size_t i = 0; i < cyc.size(); i += 2) out.push_back((uint16_t)cyc[i]);
+    even = even && len % 2 == 0;
   }
-  return true;
+  return even;
 }
 
 PolyBatch one_item(u64* p, u32 npoly, u32 period, u32 first_prime) {
@@ -436,23 +436,25 @@ int he_load_keys(he_ctx* c, const uint64_t* relin, uint32_t n_rot, const int32_t
     const u64 r = (u64)(((steps[u] % half) + half) % half);
     c->rot.push_back({steps[u], (u32)pow_mod(5, r, two_n), dst});
   }
-  // the block-pair tables of the keys' automorphisms, for the paired form of
-  // the fused extended sums (a key that starts a run of baby steps)
+  // the block-orbit tables of the keys' automorphisms, for the block order
+  // of the fused extended sums (a key that starts a run of baby steps)
   if (hipStreamSynchronize(c->stream) != hipSuccess) return HE_EDEVICE;
-  hipFree(c->d_pairs);
-  c->d_pairs = nullptr;
-  std::vector<uint16_t> all, one;
-  std::vector<long> at(c->rot.size(), -1);
-  for (size_t u = 0; u < c->rot.size(); ++u)
-    if (c->N >= 128 && block_pairs(c->log_n, c->rot[u].galois, one)) {
-      at[u] = (long)all.size();
-      all.insert(all.end(), one.begin(), one.end());
+  hipFree(c->d_orbits);
+  c->d_orbits = nullptr;
+  const size_t npb = c->N / 64;
+  if (npb >= 16 && !c->rot.empty()) {
+    std::vector<uint16_t> all(c->rot.size() * npb), one;
+    std::vector<char> even(c->rot.size());
+    for (size_t u = 0; u < c->rot.size(); ++u) {
+      even[u] = block_orbits(c->log_n, c->rot[u].galois, one);
+      std::copy(one.begin(), one.end(), all.begin() + u * npb);
     }
-  if (!all.empty()) {
-    HE_HIP(hipMalloc((void**)&c->d_pairs, all.size() * sizeof(uint16_t)));
-    HE_HIP(hipMemcpy(c->d_pairs, all.data(), all.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-    for (size_t u = 0; u < c->rot.size(); ++u)
-      if (at[u] >= 0) c->rot[u].pairs = c->d_pairs + at[u];
+    HE_HIP(hipMalloc((void**)&c->d_orbits, all.size() * sizeof(uint16_t)));
+    HE_HIP(hipMemcpy(c->d_orbits, all.data(), all.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    for (size_t u = 0; u < c->rot.size(); ++u) {
+      c->rot[u].orbit = c->d_orbits + u * npb;
+      c->rot[u].orbit_even = even[u] != 0;
+    }
   }
   return HE_OK;
 }
@@ -665,6 +667,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse_pair = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_orbit")) {
+    if (value > 1) return HE_EINVAL;
+    c->ks_fuse_orbit = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "ks_fuse_lds")) {
     if (value != 0 && value != 4 && value != 8 && value != 16) return HE_EINVAL;
     c->ks_fuse_lds = value;
@@ -713,6 +720,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ks_fuse_lds")) { *value = c->ks_fuse_lds; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_min_batch")) { *value = c->ks_fuse_min_batch; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_pair")) { *value = c->ks_fuse_pair; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_orbit")) { *value = c->ks_fuse_orbit; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

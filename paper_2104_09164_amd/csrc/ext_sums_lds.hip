@@ -247,19 +247,23 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
 }
 
 // 1-D grid over request groups of W x (tiles, ne) (xcd_decode: the groups of
-// a tile run back to back on one XCD and share its words in L2).  H = 1: a
-// tile is one 64-position block.  H = 2: a tile is a pair of blocks (X, P(X))
-// from `pairs`, P the block map of galois[0] (the block step 1 reads), each
-// served by its own W waves with its own LDS tiles; since galois[s] =
-// galois[0]^(s+1), the block that P(X) reads at step i is the one X reads at
-// step i + 1, so X's gathers find the other half's of the step before in L2
-// and every digit block reaches the workgroup from HBM about once per two
-// steps instead of once per step.
+// a tile run back to back on one XCD and share its words in L2).  A tile is
+// one 64-position block (H = 1) or two (H = 2), each served by its own W
+// waves with its own LDS tiles.  With `orbit` (the blocks in the order of the
+// cycles of P, the block map of galois[0]: block X reads P(X) at the first
+// step) the tiles run on one XCD, in order, follow those cycles: since
+// galois[s] = galois[0]^(s+1), block P(X) reads at step i the block X reads
+// at step i + 1, so the workgroups running together on an XCD read each
+// other's gathers of the step before from L2, and a digit block comes from
+// HBM about once per run of tiles instead of once per step.  H = 2 pairs X
+// with P(X) in one workgroup (entries 2k, 2k + 1 of an orbit table whose
+// cycles all have even length).
 template <int BETA, int JC, int W, int H>
 __global__ void __launch_bounds__(64 * W * H) __attribute__((amdgpu_waves_per_eu(4)))
 k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, const u64* __restrict__ pts,
              u64* __restrict__ sqp, const PrimeConst* __restrict__ pc, const u64* __restrict__ md, u32 N, u32 logn,
-             u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1, const u64* __restrict__ c0p) {
+             u32 l, u32 nq, u32 np, u32 dstride, u32 alpha, u32 n1, const u64* __restrict__ c0p,
+             const uint16_t* __restrict__ orbit) {
   __shared__ u64 sh[H][2][lds_nw(BETA, JC)][64];
   const u32 npb = N / 64, ntile = npb / H, ne = l + 1 + np, nt = nq + np;
   const u32 ngroups = (in.n + W - 1) / W;
@@ -268,9 +272,11 @@ k_ks_ext_lds(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in, c
   const u32 wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const u32 h = wv / W, w = wv % W;                   // block h of the tile, wave w of its W
   u32 blk = tile % ntile;
-  if (H == 2) {
-    blk = keys.pairs[blk];
-    if (h) blk = galois_perm(blk * 64, keys.galois[0], logn) / 64;
+  if (orbit) {
+    // tile u of a limb runs on XCD u mod 8 as its (u / 8)-th: XCD x takes the
+    // x-th eighth of the orbit order
+    const u32 idx = (blk % 8) * (ntile / 8) + blk / 8;
+    blk = orbit[H * idx + h];
   }
   const u32 x0 = blk * 64, t = tile / ntile;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
@@ -319,12 +325,15 @@ int launch_ks_ext_lds(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, c
   const u64* c0p = lift;
   // the LDS-shared form: W requests (waves) per block, 64 positions, one
   // block per workgroup or (knob ks_fuse_pair, W <= 8, a run of powers of one
-  // automorphism) a pair of blocks
-  const u32 H = c->ks_fuse_pair && keys.pairs && W <= 8 ? 2 : 1;
+  // automorphism whose block cycles have even length) a pair of blocks; the
+  // blocks dealt to the XCDs along the automorphism's cycles (knob
+  // ks_fuse_orbit, a run of powers of one automorphism)
+  const u32 H = c->ks_fuse_pair && keys.orbit && keys.orbit_even && W <= 8 ? 2 : 1;
+  const uint16_t* orbit = keys.orbit && (c->ks_fuse_orbit || H == 2) ? keys.orbit : nullptr;
   dim3 grid_l(((B + W - 1) / W) * (c->N / 64 / H) * ne);
 #define HE_LAUNCH_LX(BT, J, WW, HH)                                                                               \
   HE_LAUNCH(ts, (k_ks_ext_lds<BT, J, WW, HH>), grid_l, dim3(64 * WW * HH), c->stream, ext, own, keys, in, pts,    \
-            sqp, c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1, c0p)
+            sqp, c->d_pc, c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1, c0p, orbit)
 #define HE_LX_W(BT, J)                                                                      \
   do {                                                                                      \
     if (W == 16) HE_LAUNCH_LX(BT, J, 16, 1);                                                \

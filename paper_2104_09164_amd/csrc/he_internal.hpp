@@ -75,11 +75,12 @@ struct KeySlot {
   int32_t step;
   u32 galois;
   u64* dev;         // [dnum][2][L+1+K][N] NTT form, then their Shoup companions (same shape)
-  // Pairs of 64-position blocks (X, P(X)), P the block map of this key's
-  // automorphism (the block step 1 reads), covering every block once: N/128
-  // first blocks, device memory; null when P has a cycle of odd length (the
-  // identity on blocks, for rotations by multiples of N/128 slots).
-  const uint16_t* pairs = nullptr;
+  // The N/64 blocks of 64 positions in the order of the cycles of P, the
+  // block map of this key's automorphism (block X reads block P(X)): each
+  // cycle X, P(X), P^2(X), ... in turn (device memory).  orbit_even: every
+  // cycle has even length, so that entries 2k, 2k + 1 are a pair (X, P(X)).
+  const uint16_t* orbit = nullptr;
+  bool orbit_even = false;
 };
 
 struct he_ctx {
@@ -102,7 +103,7 @@ struct he_ctx {
   u64* d_moddown = nullptr;        // [np][2] | [np][nq] | [nq][2]
   // Rescale: qlinv[l][i] (+shoup) = q_l^{-1} mod q_i, i < l
   u64* d_rescale = nullptr;        // [nq][nq][2]
-  uint16_t* d_pairs = nullptr;     // block-pair tables of the rotation keys (KeySlot::pairs)
+  uint16_t* d_orbits = nullptr;    // block-orbit tables of the rotation keys (KeySlot::orbit)
   std::vector<PrimeConst> h_pc;
 
   // execution knobs (bit-preserving)
@@ -115,6 +116,7 @@ struct he_ctx {
   int64_t ks_fuse_waves = 0;    // fused extended sums: 3 = compiled for 3 waves per SIMD
   int64_t ks_fuse_min_batch = 2;  // fused extended sums: smallest batch that takes the LDS-shared form
   int64_t ks_fuse_pair = 0;       // LDS-shared form: pairs of blocks along the automorphism per workgroup
+  int64_t ks_fuse_orbit = 1;      // LDS-shared form: blocks dealt to each XCD along the automorphism's cycles
   int64_t ks_fuse_lds = 8;      // fused extended sums: 4, 8 or 16 = LDS-shared form with that many requests per
                                 // workgroup (8 measured fastest), 0 = the register form
 

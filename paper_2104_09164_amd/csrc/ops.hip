@@ -554,7 +554,10 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
         sk.key[k - 1] = ks->dev;
         sk.galois[k - 1] = ks->galois;
         sk.galois_inv[k - 1] = galois_inverse(c, ks->galois);
-        if (k == 1) sk.pairs = ks->pairs;          // step k rotates by k t: galois[k-1] = galois[0]^k
+        if (k == 1) {                              // step k rotates by k t: galois[k-1] = galois[0]^k
+          sk.orbit = ks->orbit;
+          sk.orbit_even = ks->orbit_even;
+        }
       }
       grp_bits.push_back(b);
       grp_shift.push_back(t);
@@ -588,7 +591,8 @@ int he_eval_dense_batch(he_ctx* c, uint32_t n, const he_ct* in, const he_dense* 
       sk.galois[i] = baby[i + 1]->galois;
       sk.galois_inv[i] = galois_inverse(c, baby[i + 1]->galois);
     }
-    sk.pairs = baby[1]->pairs;                     // baby step i rotates by i: galois[i] = galois[0]^(i+1)
+    sk.orbit = baby[1]->orbit;                     // baby step i rotates by i: galois[i] = galois[0]^(i+1)
+    sk.orbit_even = baby[1]->orbit_even;
     if (d->pl > l + 1) {
       // lazy ModDown: the inner products stay over Q_l u P; the inner sums
       // are formed there (the extended rotations only in registers) into

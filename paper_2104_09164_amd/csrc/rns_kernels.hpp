@@ -46,9 +46,10 @@ struct StepKeys {
   u32 galois[HE_MAX_STEPS];       // its Galois element g
   u32 galois_inv[HE_MAX_STEPS];   // g^{-1} mod 2N
   // When galois[s] = galois[0]^(s+1) for every s (a run of baby steps or a
-  // hoisted rotate-and-sum group): the block pairs of galois[0]'s key
-  // (KeySlot::pairs), else null.
-  const uint16_t* pairs = nullptr;
+  // hoisted rotate-and-sum group): the block orbits of galois[0]'s key
+  // (KeySlot::orbit, orbit_even), else null.
+  const uint16_t* orbit = nullptr;
+  u32 orbit_even = 0;
 };
 // Source c1 (NTT form) of item (s, b), whose digits' own limbs the inner
 // product reads: base + s os + b ob when base is set, else ptr[b] (same for every s).

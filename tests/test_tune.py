@@ -62,7 +62,8 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
     """The fused lazy-ModDown inner sums (n2 = 1, 2, 4, 8 giant sums) under
     every setting of ks_fuse_g (requests per thread) and ks_fuse_waves (the
     three-waves-per-SIMD build), and in the LDS-shared form (ks_fuse_lds)
-    with one or two position blocks per workgroup (ks_fuse_pair):
+    with one or two position blocks per workgroup (ks_fuse_pair), the
+    blocks in address order or along the automorphism (ks_fuse_orbit):
     nine requests (partial last groups: one request in the last workgroup of
     four or eight waves, the others idle), each equal to the oracle bit for
     bit."""
@@ -79,17 +80,20 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
     lay = o.prepare_dense(W[0], b[0], n1, pr.L, pr.scale, qp=True, rs_bits=rs)
     d = ctx.dense_load(lay.level, m, n, n1, lay.pts, lay.bias, lay.pt_scale, lay.bias_scale, qp=True, rs_bits=rs)
     want = [o.dense(c, lay, keys).data for c in cts]
-    for g, w, lds, pair in [(0, 0, 0, 1), (1, 0, 0, 1), (0, 3, 0, 1), (1, 3, 0, 1), (0, 0, 4, 1), (0, 0, 8, 1),
-                            (0, 0, 16, 1), (0, 0, 4, 0), (0, 0, 8, 0)]:
+    for g, w, lds, pair, orb in [(0, 0, 0, 0, 1), (1, 0, 0, 0, 1), (0, 3, 0, 0, 1), (1, 3, 0, 0, 1), (0, 0, 4, 0, 1),
+                                 (0, 0, 8, 0, 1), (0, 0, 16, 0, 1), (0, 0, 8, 0, 0), (0, 0, 16, 0, 0),
+                                 (0, 0, 4, 1, 1), (0, 0, 8, 1, 0)]:
         ctx.set_knob("ks_fuse_g", g)
         ctx.set_knob("ks_fuse_waves", w)
         ctx.set_knob("ks_fuse_lds", lds)
         ctx.set_knob("ks_fuse_pair", pair)
+        ctx.set_knob("ks_fuse_orbit", orb)
         gs = [ctx.import_ct(c.data, c.level, c.scale) for c in cts]
         out = ctx.eval_dense_batch(gs, d)
         for i, (x, y) in enumerate(zip(out, want)):
-            assert np.array_equal(ctx.export_ct(x), y), (g, w, lds, pair, i)
+            assert np.array_equal(ctx.export_ct(x), y), (g, w, lds, pair, orb, i)
     ctx.set_knob("ks_fuse_pair", 0)
+    ctx.set_knob("ks_fuse_orbit", 1)
     # one request alone in a workgroup of four (three idle waves), and the register form for it
     for mb in (1, 2):
         ctx.set_knob("ks_fuse_lds", 8)
@@ -129,7 +133,7 @@ def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
     assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse",
                                     "ks_fuse_g", "ks_fuse_waves", "ks_fuse_lds", "ks_fuse_min_batch",
-                                    "ks_fuse_pair"}
+                                    "ks_fuse_pair", "ks_fuse_orbit"}
     assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
     assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
     assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
@@ -142,12 +146,13 @@ def test_knob_api_validation():
     ctx = he.Context(12, q, p, 1)
     defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
                 "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "ks_fuse_min_batch": 2, "ks_fuse_pair": 0,
+                "ks_fuse_orbit": 1,
                 "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
     for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
                    ("ks_fuse_g", 2), ("ks_fuse_waves", 2), ("ks_fuse_lds", 2), ("ks_fuse_min_batch", 0),
-                   ("ks_fuse_pair", 2),
+                   ("ks_fuse_pair", 2), ("ks_fuse_orbit", 2),
                    ("ntt_chunk_mb", -1),
                    ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
