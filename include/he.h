@@ -369,6 +369,11 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   so that the workgroups running together read each
  *                   other's gathers of the step before from L2; 0 = in
  *                   address order
+ *   "ks_fuse_one"   a batch of one below ks_fuse_min_batch: 1 (default) = its
+ *                   own kernel (one position per thread; on primes below 2^50
+ *                   the key and plaintext words read without their Shoup
+ *                   companions, the key sums as exact column sums), 0 = the
+ *                   register form
  *   "ks_fuse_pair"  LDS-shared form with 4 or 8 requests: 1 = each
  *                   workgroup serves two position blocks, X and P(X), so that
  *                   one block's gathers are the other's of the step before;

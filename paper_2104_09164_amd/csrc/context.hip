@@ -672,6 +672,11 @@ int he_ctx_set_knob(he_ctx* c, const char* key, int64_t value) {
     c->ks_fuse_orbit = value;
     return HE_OK;
   }
+  if (!std::strcmp(key, "ks_fuse_one")) {
+    if (value > 1) return HE_EINVAL;
+    c->ks_fuse_one = value;
+    return HE_OK;
+  }
   if (!std::strcmp(key, "ks_fuse_lds")) {
     if (value != 0 && value != 4 && value != 8 && value != 16) return HE_EINVAL;
     c->ks_fuse_lds = value;
@@ -721,6 +726,7 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   if (!std::strcmp(key, "ks_fuse_min_batch")) { *value = c->ks_fuse_min_batch; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_pair")) { *value = c->ks_fuse_pair; return HE_OK; }
   if (!std::strcmp(key, "ks_fuse_orbit")) { *value = c->ks_fuse_orbit; return HE_OK; }
+  if (!std::strcmp(key, "ks_fuse_one")) { *value = c->ks_fuse_one; return HE_OK; }
   if (!std::strcmp(key, "trace")) { *value = c->tr.on ? 1 : 0; return HE_OK; }
   return HE_EINVAL;
 }

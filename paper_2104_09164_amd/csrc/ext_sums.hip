@@ -143,6 +143,135 @@ k_ks_ext_fused(const u64* __restrict__ ext, OwnMap own, StepKeys keys,
 }
 
 
+// One request (a batch of one): the same sums with one position per thread
+// and nothing shared between requests, so the register budget allows a high
+// occupancy.  A batch of one is bound by the key and plaintext streams (read
+// once per request), so on the primes below 2^50 (COL) they are read as
+// values only, without their Shoup companions (half the bytes), and both the
+// key sums and the inner sums are exact 28-bit column sums: digit d and key
+// word k (both below q < 2^50) split into 28-bit columns, four multiply-adds
+// per product into K0 < 8 2^56, K1 < 8 2^51, K2 < 8 2^44 over at most 8
+// digits, reduced lazily (col_lazy, below 11 q; with the lift of c0, below
+// 2q, r < 13 q < 2^54) and multiplied into the inner column sums as in the
+// LDS-shared form.  Other primes take the register form's Shoup products.
+// The words written are in [0, q): the same words as every other form.
+template <int BETA, int JC, bool COL, bool LKS, bool LMP>
+__device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, const OwnMap& own, const StepKeys& keys,
+                                                const Items& in, const u64* __restrict__ pts, u64* __restrict__ sqp,
+                                                const PrimeConst& P, u64 pw, u64 pws, u32 N, u32 logn, u32 l, u32 nt,
+                                                u32 ne, u32 pr, u32 dstride, u32 alpha, u32 n1, u32 x, u32 t) {
+  const bool qlimb = t <= l;
+  const u64 q = P.q;
+  const size_t comp = (size_t)n1 * JC * ne * N;    // plaintext companions follow the m = n1 JC diagonals
+  const size_t kw = (size_t)dstride * 2 * nt * N;  // key companions follow the key words
+  const u32 own_digit = qlimb ? t / alpha : 0xFFFFFFFFu;
+  u64 a0[JC], a1[JC];                              // Shoup inner sums
+  u64 w0[COL ? JC : 1][3], w1[COL ? JC : 1][3];    // column inner sums
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) a0[jj] = a1[jj] = 0;
+#pragma unroll
+  for (int jj = 0; jj < (COL ? JC : 1); ++jj)
+    w0[jj][0] = w0[jj][1] = w0[jj][2] = w1[jj][0] = w1[jj][1] = w1[jj][2] = 0;
+  // plaintext word of giant sum jj at step i (value; companion unless COL)
+  auto pt_of = [&](int jj, u32 i, u64& v, u64& c) {
+    const size_t o = (((size_t)n1 * jj + i) * ne + t) * N + x;
+    v = pts ? pts[o] : 1;                          // no plaintexts: a plain sum (x 1, companion mu)
+    c = COL ? 0 : (pts ? pts[comp + o] : P.mu);
+  };
+  auto inner = [&](int jj, u64 r0, u64 r1, u64 pt, u64 ps) {
+    if (COL) {
+      col_mad(w0[jj], r0, pt & kLow28, pt >> 28);
+      col_mad(w1[jj], r1, pt & kLow28, pt >> 28);
+    } else {
+      a0[jj] = mp_add<LMP>(a0[jj], r0, pt, ps, P);
+      a1[jj] = mp_add<LMP>(a1[jj], r1, pt, ps, P);
+    }
+  };
+  if (qlimb) {
+    const u64* c = in.p[0];
+    const u64 r0 = shoup(c[(size_t)t * N + x], pw, pws, q), r1 = shoup(c[(size_t)(l + 1 + t) * N + x], pw, pws, q);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      u64 pt, ps;
+      pt_of(jj, 0, pt, ps);
+      inner(jj, r0, r1, pt, ps);
+    }
+  }
+  const u64* e = ext + (size_t)t * N;
+  const u64* src = own.ptr[0] + (size_t)t * N;
+  for (u32 i = 1; i < n1; ++i) {
+    const u32 y = galois_perm(x, keys.galois[i - 1], logn);
+    const u64* key = keys.key[i - 1];
+    u64 d[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) d[j] = (u32)j == own_digit ? src[y] : e[(size_t)j * ne * N + y];
+    u64 r0, r1;
+    if (COL) {
+      u64 kb[3] = {0, 0, 0}, ka[3] = {0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+        const u64 vb = key[(((size_t)j * 2 + 0) * nt + pr) * N + x], va = key[(((size_t)j * 2 + 1) * nt + pr) * N + x];
+        col_mad(kb, d[j], vb & kLow28, vb >> 28);
+        col_mad(ka, d[j], va & kLow28, va >> 28);
+      }
+      r0 = col_lazy(kb, P);
+      r1 = col_lazy(ka, P);
+    } else {
+      u64 kb[BETA], kbs[BETA], ka[BETA], kas[BETA];
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+        const size_t ob = (((size_t)j * 2 + 0) * nt + pr) * N + x, oa = (((size_t)j * 2 + 1) * nt + pr) * N + x;
+        kb[j] = key[ob];
+        kbs[j] = key[kw + ob];
+        ka[j] = key[oa];
+        kas[j] = key[kw + oa];
+      }
+      ks_dot<BETA, LKS>(d, kb, kbs, ka, kas, P, !qlimb, r0, r1);
+    }
+    if (qlimb) r0 += shoup_lazy(in.p[0][(size_t)t * N + y], pw, pws, q);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) {
+      u64 pt, ps;
+      pt_of(jj, i, pt, ps);
+      inner(jj, r0, r1, pt, ps);
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JC; ++jj) {
+    u64* o = sqp + (size_t)jj * 2 * ne * N;
+    o[(size_t)t * N + x] = COL ? col_final(w0[jj], P) : mp_final<LMP>(a0[jj], P);
+    o[(size_t)(ne + t) * N + x] = COL ? col_final(w1[jj], P) : mp_final<LMP>(a1[jj], P);
+  }
+}
+
+// Grid (N / BS) x ne tiles, one request.
+template <int BETA, int JC>
+__global__ void __launch_bounds__(BS) k_ks_ext_one(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in,
+                                                   const u64* __restrict__ pts, u64* __restrict__ sqp,
+                                                   const PrimeConst* __restrict__ pc, const u64* __restrict__ md,
+                                                   u32 N, u32 logn, u32 l, u32 nq, u32 np, u32 dstride, u32 alpha,
+                                                   u32 n1) {
+  const u32 nkb = N / BS, ne = l + 1 + np, nt = nq + np;
+  const u32 tile = blockIdx.x;
+  const u32 x = (tile % nkb) * BS + threadIdx.x, t = tile / nkb;
+  const u32 pr = t <= l ? t : nq + (t - l - 1);
+  const PrimeConst P = pc[pr];
+  const u64* pmod = md + 2 * np + 2 * (size_t)np * nq + 2 * (size_t)nq;   // [nq][2] P mod q_i
+  const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
+#define HE_ONE_BODY(C, K, M)                                                                                    \
+  ks_ext_one_body<BETA, JC, C, K, M>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride, \
+                                     alpha, n1, x, t)
+  if (P.q < kWideQ)
+    HE_ONE_BODY(true, true, true);
+  else if (P.q < kLazyMP)
+    HE_ONE_BODY(false, true, true);
+  else if (P.q < kLazyKS)
+    HE_ONE_BODY(false, true, false);
+  else
+    HE_ONE_BODY(false, false, false);
+#undef HE_ONE_BODY
+}
+
 }  // namespace
 
 int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext, const OwnMap& own,
@@ -161,6 +290,34 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
   while (W > 4 && B < W) W /= 2;
   if (W && B >= (u32)c->ks_fuse_min_batch)
     return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, lift, ts);
+  if (B == 1 && c->ks_fuse_one) {
+    // a batch of one: one position per thread, values-only streams below 2^50
+    dim3 grid1((c->N / BS) * ne);
+#define HE_LAUNCH_ONE(BT, J)                                                                                      \
+  HE_LAUNCH(ts, (k_ks_ext_one<BT, J>), grid1, dim3(BS), c->stream, ext, own, keys, in, pts, sqp, c->d_pc,        \
+            c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)
+#define HE_ONE_J(BT)                                                                        \
+  switch (n2) {                                                                             \
+    case 8: HE_LAUNCH_ONE(BT, 8); break;                                                    \
+    case 4: HE_LAUNCH_ONE(BT, 4); break;                                                    \
+    case 2: HE_LAUNCH_ONE(BT, 2); break;                                                    \
+    default: HE_LAUNCH_ONE(BT, 1); break;                                                   \
+  }
+    switch (beta) {
+      case 1: HE_ONE_J(1); break;
+      case 2: HE_ONE_J(2); break;
+      case 3: HE_ONE_J(3); break;
+      case 4: HE_ONE_J(4); break;
+      case 5: HE_ONE_J(5); break;
+      case 6: HE_ONE_J(6); break;
+      case 7: HE_ONE_J(7); break;
+      case 8: HE_ONE_J(8); break;
+      default: return HE_EPARAM;
+    }
+#undef HE_ONE_J
+#undef HE_LAUNCH_ONE
+    return ok();
+  }
   // items per thread: by default G n2 <= 16 accumulator pairs (each key and
   // plaintext word loaded is used G times); knob ks_fuse_g halves G
   // (fewer registers), knob ks_fuse_waves = 3 compiles for 3 waves per SIMD.

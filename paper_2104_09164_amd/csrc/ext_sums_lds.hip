@@ -26,7 +26,6 @@ namespace {
 // wave moves (W waves: wave w moves kind w mod 4 of the digits j = w / 4,
 // w / 4 + W / 4, ...) and plaintext rows each wave moves.
 constexpr int lds_nw(int beta, int jc) { return 4 * beta + 2 * jc; }
-constexpr u64 kLow28 = (1ull << 28) - 1;
 constexpr int lds_kr(int beta, int w) { return (beta + w / 4 - 1) / (w / 4); }
 constexpr int lds_pr(int jc, int w) { return (2 * jc + w - 1) / w; }
 constexpr int lds_st(int beta, int jc, int w) { return lds_kr(beta, w) + lds_pr(jc, w); }
@@ -86,23 +85,6 @@ __device__ __forceinline__ void lds_tile_store(const u64 (&st)[lds_st(BETA, JC, 
   }
 }
 
-// One product r b of the MODE 3 column sums (b given as its 28-bit columns
-// b0, b1): four 32 x 32 -> 64-bit multiply-adds.
-__device__ __forceinline__ void col_mad(u64 (&c)[3], u64 r, u64 b0, u64 b1) {
-  const u32 a0 = (u32)(r & kLow28), a1 = (u32)(r >> 28);
-  c[0] = (u64)a0 * (u32)b0 + c[0];
-  c[1] = (u64)a0 * (u32)b1 + c[1];
-  c[1] = (u64)a1 * (u32)b0 + c[1];
-  c[2] = (u64)a1 * (u32)b1 + c[2];
-}
-// C0 + C1 2^28 + C2 2^56 mod q, in [0, q).
-__device__ __forceinline__ u64 col_final(const u64 (&c)[3], const PrimeConst& P) {
-  u64 v = reduce_lazy(c[0], P.q, P.mu) + shoup_lazy4(c[1], P.t28, P.t28_sh, P.q) +
-          shoup_lazy4(c[2], P.t56, P.t56_sh, P.q);                 // below 11 q
-  v = reduce_lazy(v, P.q, P.mu);
-  return csub_neg(csub_neg(v, P.nq2), P.nq);
-}
-constexpr u64 kWideQ = 1ull << 50;
 
 // MODE 0: q < 2^55 (key sums lazy, inner sums lazy); 1: q < 2^60 with at
 // most 4 digits (ks_dot_mid, mp_add_mid); 2: any other prime (every sum kept

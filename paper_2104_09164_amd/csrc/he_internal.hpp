@@ -117,6 +117,7 @@ struct he_ctx {
   int64_t ks_fuse_min_batch = 2;  // fused extended sums: smallest batch that takes the LDS-shared form
   int64_t ks_fuse_pair = 0;       // LDS-shared form: pairs of blocks along the automorphism per workgroup
   int64_t ks_fuse_orbit = 1;      // LDS-shared form: blocks dealt to each XCD along the automorphism's cycles
+  int64_t ks_fuse_one = 1;        // a batch of one: its own kernel (values-only streams below 2^50)
   int64_t ks_fuse_lds = 8;      // fused extended sums: 4, 8 or 16 = LDS-shared form with that many requests per
                                 // workgroup (8 measured fastest), 0 = the register form
 

@@ -111,6 +111,31 @@ __device__ __forceinline__ u64 mp_add_mid(u64 acc, u64 x, u64 pt, u64 ps, const 
   return acc + shoup_lazy4(x, pt, ps, k.q);
 }
 
+// Exact column sums for primes below 2^50 (the fused kernels): a value r
+// (below 2^56) and a word b (below 2^50, given as its 28-bit columns b0, b1)
+// are multiplied as r = a1 2^28 + a0 by four 32 x 32 -> 64-bit multiply-adds
+// into column sums C0 += a0 b0, C1 += a0 b1 + a1 b0, C2 += a1 b1; the sum
+// C0 + C1 2^28 + C2 2^56 is reduced mod q once at the end.
+constexpr u64 kLow28 = (1ull << 28) - 1;
+constexpr u64 kWideQ = 1ull << 50;
+__device__ __forceinline__ void col_mad(u64 (&c)[3], u64 r, u64 b0, u64 b1) {
+  const u32 a0 = (u32)(r & kLow28), a1 = (u32)(r >> 28);
+  c[0] = (u64)a0 * (u32)b0 + c[0];
+  c[1] = (u64)a0 * (u32)b1 + c[1];
+  c[1] = (u64)a1 * (u32)b0 + c[1];
+  c[2] = (u64)a1 * (u32)b1 + c[2];
+}
+// C0 + C1 2^28 + C2 2^56 mod q, lazily: below 11 q (any 64-bit columns).
+__device__ __forceinline__ u64 col_lazy(const u64 (&c)[3], const PrimeConst& P) {
+  return reduce_lazy(c[0], P.q, P.mu) + shoup_lazy4(c[1], P.t28, P.t28_sh, P.q) +
+         shoup_lazy4(c[2], P.t56, P.t56_sh, P.q);
+}
+// The same in [0, q).
+__device__ __forceinline__ u64 col_final(const u64 (&c)[3], const PrimeConst& P) {
+  const u64 v = reduce_lazy(col_lazy(c, P), P.q, P.mu);
+  return csub_neg(csub_neg(v, P.nq2), P.nq);
+}
+
 inline int ok() { return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE; }
 
 }  // namespace

@@ -94,20 +94,22 @@ def test_fused_knobs_preserve_bits(m, n, n1, rs):
             assert np.array_equal(ctx.export_ct(x), y), (g, w, lds, pair, orb, i)
     ctx.set_knob("ks_fuse_pair", 0)
     ctx.set_knob("ks_fuse_orbit", 1)
-    # one request alone in a workgroup of four (three idle waves), and the register form for it
-    for mb in (1, 2):
+    # one request alone in a workgroup of four (three idle waves), the register form for it, and
+    # the single-request kernel (values-only streams on the 45-bit primes)
+    for mb, one in ((1, 1), (2, 0), (2, 1)):
         ctx.set_knob("ks_fuse_lds", 8)
         ctx.set_knob("ks_fuse_min_batch", mb)
+        ctx.set_knob("ks_fuse_one", one)
         g1 = ctx.eval_dense_batch([ctx.import_ct(cts[4].data, cts[4].level, cts[4].scale)], d)
-        assert np.array_equal(ctx.export_ct(g1[0]), want[4]), mb
+        assert np.array_equal(ctx.export_ct(g1[0]), want[4]), (mb, one)
 
 
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("qbits,alpha", [(48, 1), (50, 2), (51, 3), (36, 1)])
 def test_fused_lds_at_prime_bounds(qbits, alpha):
-    """The LDS-shared fused inner sums on primes at the bounds of their
-    forms: just below 2^50 (the last primes of the 28-bit column sums), just
+    """The LDS-shared fused inner sums, and the single-request kernel, on
+    primes at the bounds of their forms: just below 2^50 (the last primes of the 28-bit column sums), just
     above it (51-bit primes: the lazy integer sums), 48-bit primes with five
     digits (the widest key sum here), and 36-bit primes; five requests, each
     equal to the oracle bit for bit."""
@@ -128,12 +130,16 @@ def test_fused_lds_at_prime_bounds(qbits, alpha):
     out = ctx.eval_dense_batch([ctx.import_ct(c.data, c.level, c.scale) for c in cts], d)
     for i, (x, y) in enumerate(zip(out, want)):
         assert np.array_equal(ctx.export_ct(x), y), (qbits, alpha, i)
+    # one request: the single-request kernel (column key sums below 2^50)
+    for i in (0, 3):
+        g1 = ctx.eval_dense_batch([ctx.import_ct(cts[i].data, cts[i].level, cts[i].scale)], d)
+        assert np.array_equal(ctx.export_ct(g1[0]), want[i]), (qbits, alpha, "one", i)
 
 def test_knob_space_is_bit_preserving_and_valid():
     # every tuned key is a documented knob and every value one the library accepts
     assert set(tune.KNOB_SPACE) <= {"ntt_chunk_mb", "ntt_cols", "ntt_cols_b", "ntt_single_pass", "ks_fuse",
                                     "ks_fuse_g", "ks_fuse_waves", "ks_fuse_lds", "ks_fuse_min_batch",
-                                    "ks_fuse_pair", "ks_fuse_orbit"}
+                                    "ks_fuse_pair", "ks_fuse_orbit", "ks_fuse_one"}
     assert set(tune.KNOB_SPACE["ntt_cols"]) <= {8, 16, 32}
     assert set(tune.KNOB_SPACE["ntt_cols_b"]) <= {0, 8, 16, 32}
     assert all(v >= 0 for v in tune.KNOB_SPACE["ntt_chunk_mb"])
@@ -146,13 +152,13 @@ def test_knob_api_validation():
     ctx = he.Context(12, q, p, 1)
     defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
                 "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "ks_fuse_min_batch": 2, "ks_fuse_pair": 0,
-                "ks_fuse_orbit": 1,
+                "ks_fuse_orbit": 1, "ks_fuse_one": 1,
                 "trace": 0}
     for k, v in defaults.items():
         assert ctx.get_knob(k) == v
     for k, bad in [("ntt_cols", 12), ("ntt_cols_b", 4), ("ntt_single_pass", 2), ("ks_fuse", 2), ("trace", 3),
                    ("ks_fuse_g", 2), ("ks_fuse_waves", 2), ("ks_fuse_lds", 2), ("ks_fuse_min_batch", 0),
-                   ("ks_fuse_pair", 2), ("ks_fuse_orbit", 2),
+                   ("ks_fuse_pair", 2), ("ks_fuse_orbit", 2), ("ks_fuse_one", 2),
                    ("ntt_chunk_mb", -1),
                    ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
