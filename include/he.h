@@ -111,6 +111,26 @@ int he_ctx_create(const he_params* params, void* hip_stream, he_ctx** out);
 int he_ctx_destroy(he_ctx* ctx);
 int he_ctx_set_stream(he_ctx* ctx, void* hip_stream);
 
+/* Graph capture of a sequence of calls (the batching of the method's
+ * Discussion, many requests per launch sequence, replayed at one launch per
+ * sequence).  he_graph_begin starts capturing the context's stream
+ * (thread-local capture mode): every later call on this context until
+ * he_graph_end records its kernels and copies into a HIP graph instead of
+ * running them; he_graph_end ends the capture and instantiates the graph
+ * into *out (caller-owned, freed with he_graph_free).  he_graph_launch runs
+ * it on the context's current stream; it reads and writes the same device
+ * buffers as the captured calls did, which the caller keeps allocated and
+ * at the same levels and scales.  The captured calls must allocate nothing
+ * (workspace bound before) and issue no memset; the tracer is inactive while
+ * capturing.  HE_ESTATE when the context uses the legacy default stream
+ * (which cannot be captured), HE_EDEVICE when the runtime refuses the capture
+ * or a captured call failed (the capture is then discarded). */
+typedef struct he_graph he_graph;
+int he_graph_begin(he_ctx* ctx);
+int he_graph_end(he_ctx* ctx, he_graph** out);
+int he_graph_launch(he_ctx* ctx, const he_graph* graph);
+int he_graph_free(he_graph* graph);
+
 /* Sizes in bytes of caller-owned device buffers. */
 size_t he_ct_bytes(const he_ctx* ctx, uint32_t level);
 /* Key storage for the relinearisation key plus n_rot rotation keys. */

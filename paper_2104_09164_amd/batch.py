@@ -4,8 +4,9 @@ One call evaluates the network for up to B independent ciphertexts (requests):
 every layer is one set of batched launches (he_eval_dense_batch,
 he_rescale_batch, he_square_batch), so keys and plaintext diagonals are read
 once per batch instead of once per request.  All stage buffers are
-preallocated; a captured HIP graph of the whole sequence (through
-torch.cuda.CUDAGraph on a side stream) replays it with one launch call.
+preallocated; a HIP graph of the whole sequence, captured by the library
+(he_graph_begin / he_graph_end) on a side stream, replays it with one launch
+call.
 
 Results are bit-identical to one-request-at-a-time evaluation: batching only
 changes which launch a ciphertext rides in, never its arithmetic.
@@ -61,10 +62,7 @@ class NetworkRunner:
             self.ctx.use_current_stream()
             self.run(b)                      # warm-up on the capture stream
             side.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=side):
-                self.ctx.use_current_stream()
-                self.run(b)
+            g = self.ctx.capture(lambda: self.run(b))
         torch.cuda.current_stream(self.ctx.device).wait_stream(side)
         self.ctx.use_current_stream()
         self.graphs[b] = g

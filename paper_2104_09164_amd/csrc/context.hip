@@ -731,6 +731,50 @@ int he_ctx_get_knob(const he_ctx* c, const char* key, int64_t* value) {
   return HE_EINVAL;
 }
 
+struct he_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int he_graph_begin(he_ctx* c) {
+  if (!c) return HE_EINVAL;
+  if (!c->stream) return HE_ESTATE;
+  return hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+int he_graph_end(he_ctx* c, he_graph** out) {
+  if (!c || !out) return HE_EINVAL;
+  *out = nullptr;
+  if (!c->stream) return HE_ESTATE;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(c->stream, &g) != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return HE_EDEVICE;
+  }
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return HE_EDEVICE;
+  }
+  *out = new he_graph{g, e};
+  return HE_OK;
+}
+
+int he_graph_launch(he_ctx* c, const he_graph* g) {
+  if (!c || !g) return HE_EINVAL;
+  return hipGraphLaunch(g->exec, c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+int he_graph_free(he_graph* g) {
+  if (!g) return HE_EINVAL;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  delete g;
+  return HE_OK;
+}
+
 int he_sync(he_ctx* c) {
   if (!c) return HE_EINVAL;
   return hipStreamSynchronize(c->stream) == hipSuccess ? HE_OK : HE_EDEVICE;

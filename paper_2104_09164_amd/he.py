@@ -107,6 +107,10 @@ def lib() -> C.CDLL:
             "he_encrypt": (C.c_int, [vp, u32, vp, vp, u32, dbl, ctp]),
             "he_decrypt": (C.c_int, [vp, u32, ctp, vp]),
             "he_decode": (C.c_int, [vp, u32, vp, u32, dbl, vp]),
+            "he_graph_begin": (C.c_int, [vp]),
+            "he_graph_end": (C.c_int, [vp, C.POINTER(vp)]),
+            "he_graph_launch": (C.c_int, [vp, vp]),
+            "he_graph_free": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -124,7 +128,8 @@ EXPORTED = ("he_strerror", "he_last_error", "he_gen_primes", "he_ctx_create", "h
             "he_sync", "he_ctx_set_knob", "he_ctx_get_knob", "he_trace_read", "he_dense_bytes_ex",
             "he_dense_load_ex", "he_linear_bytes", "he_linear_load", "he_linear_free", "he_linear_scratch_bytes",
             "he_eval_linear", "he_eval_linear_batch", "he_client_create", "he_client_destroy", "he_encode",
-            "he_encrypt", "he_decrypt", "he_decode", "he_rescale_batch_noalloc")
+            "he_encrypt", "he_decrypt", "he_decode", "he_rescale_batch_noalloc", "he_graph_begin",
+            "he_graph_end", "he_graph_launch", "he_graph_free")
 
 HE_DENSE_QP = 1
 HE_DENSE_RS_SHIFT = 8
@@ -261,6 +266,22 @@ class Client:
         return z
 
 
+class Graph:
+    """A captured sequence of library calls (he_graph_*); replay() launches it
+    on its context's current stream."""
+
+    def __init__(self, ctx, handle):
+        self.ctx, self.h = ctx, handle
+
+    def replay(self) -> None:
+        _check(lib().he_graph_launch(self.ctx.h, self.h), "he_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().he_graph_free(self.h)
+            self.h = None
+
+
 class Context:
     def __init__(self, log_n: int, q, p, alpha: int, device: str = "cuda:0"):
         torch = _torch()
@@ -293,6 +314,20 @@ class Context:
         torch = _torch()
         _check(lib().he_ctx_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)),
                "he_ctx_set_stream")
+
+    # ------------------------------------------------------------ graphs
+    def capture(self, fn) -> "Graph":
+        """Record the library calls fn() makes on this context's stream into a
+        HIP graph (he_graph_begin / he_graph_end) instead of running them;
+        the capture is ended even when fn raises."""
+        _check(lib().he_graph_begin(self.h), "he_graph_begin")
+        try:
+            fn()
+        finally:
+            g = C.c_void_p()
+            rc = lib().he_graph_end(self.h, C.byref(g))
+        _check(rc, "he_graph_end")
+        return Graph(self, g)
 
     # ------------------------------------------------------------ memory
     def _alloc(self, nbytes: int):

@@ -419,10 +419,7 @@ class NetBackend(Backend):
                     ctx.use_current_stream()
                     self._stage_call(st, self.stage_in[st][:b], self.stage_out[st][:b])   # warm-up
                     side.synchronize()
-                    g = torch.cuda.CUDAGraph()
-                    with torch.cuda.graph(g, stream=side):
-                        ctx.use_current_stream()
-                        self._stage_call(st, self.stage_in[st][:b], self.stage_out[st][:b])
+                    g = ctx.capture(lambda: self._stage_call(st, self.stage_in[st][:b], self.stage_out[st][:b]))
                     self.graphs[(st, b)] = g
         torch.cuda.current_stream(ctx.device).wait_stream(side)
         with torch.cuda.stream(self.stream):

@@ -409,3 +409,36 @@ def test_network_cfg1_end_to_end():
         yr = plainnet.forward(x, Ws, bs)
         assert np.max(np.abs(y - yr)) <= 2.0 ** -12
         assert plainnet.predict(y) == plainnet.predict(yr) or abs(yr[0] - yr[1]) < 2.0 ** -11
+
+
+def test_library_graph_replays():
+    """A whole cfg1 network for 3 requests captured by the library
+    (he_graph_begin / he_graph_end) and replayed three times, with eager work
+    on the same context and new inputs between the replays: every replay
+    equals the oracle bit for bit, and the eager work is undisturbed."""
+    import torch
+    from paper_2104_09164_amd.batch import NetworkRunner
+    from paper_2104_09164_amd import netplan
+    pr = params.preset("cfg1")
+    steps = ckks.network_steps(pr.layers)
+    o, keys, ctx = make_setup(pr, steps, max_batch=3, max_n1=8, max_n2=8)
+    Ws, bs = synth.network_weights(pr.layers, pr.sigma_w)
+    lays = o.prepare_network(Ws, bs, [l[2] for l in pr.layers])
+    npl = netplan.plan_network(pr.log_n, pr.q, pr.p, pr.alpha, pr.scale_bits, pr.layers)
+    dls = [ctx.dense_load(l.level, l.m, l.n, l.n1, l.pts, l.bias, l.pt_scale, l.bias_scale) for l in lays]
+    runner = NetworkRunner(ctx, npl, dls, 3)
+    g = runner.capture(3)
+    for rep in range(3):
+        cts = [encrypt(o, keys, pr, 10 * rep + i, width=pr.layers[0][1])[1] for i in range(3)]
+        for i, ct in enumerate(cts):
+            runner.inputs[i].buf.copy_(ctx.import_ct(ct.data, ct.level, ct.scale).buf)
+        g.replay()
+        torch.cuda.synchronize()
+        # eager work on the same context between replays
+        e = ctx.rescale(ctx.import_ct(cts[0].data, cts[0].level, cts[0].scale))
+        assert np.array_equal(ctx.export_ct(e), o.rescale(cts[0]).data)
+        for i, ct in enumerate(cts):
+            want = o.eval_network(ct, lays, keys)
+            out = runner.outputs(3)[i]
+            assert out.level == want.level and out.scale == want.scale
+            assert np.array_equal(ctx.export_ct(out), want.data), (rep, i)

@@ -39,7 +39,7 @@ def test_serving_mix_equals_alone_and_oracle(graphs):
     for r in range(count):
         x = synth.request_input(shapes[0][1], r)
         cts.append(o.encrypt(plan.input_slots(x, pr.slots), keys.pk, synth.request_seed(r)))
-    times = serve.poisson_arrivals(rate=3000.0, count=count, seed=3)
+    times = serve.poisson_arrivals(rate=100000.0, count=count, seed=3)   # bursts: requests share stages
     sched = serve.Scheduler({"small": be}, budget_bytes=4 * be.slot_bytes, window=3)
     reqs = [serve.Request(r, "small", (cts[r].data, cts[r].level, cts[r].scale), float(times[r]))
             for r in range(count)]
