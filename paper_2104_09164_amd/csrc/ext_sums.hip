@@ -1,9 +1,10 @@
 // Fused lazy-ModDown inner sums (the baby steps' key inner products and the
 // MultPlain inner sums over Q_l u P in one pass; also the plain sums of the
-// hoisted rotate-and-sum groups), in two forms: every request's sums in
-// registers of one thread (k_ks_ext_fused), or the key and plaintext words of
-// a tile shared through LDS by the threads of several requests
-// (k_ks_ext_lds).  Both compute the same words.
+// hoisted rotate-and-sum groups), in three forms: every request's sums in
+// registers of one thread (k_ks_ext_fused), a single request with
+// values-only key and plaintext streams (k_ks_ext_one), or the key and
+// plaintext words of a tile shared through LDS by the threads of several
+// requests (k_ks_ext_lds, ext_sums_lds.hip).  All compute the same words.
 #include "rns_kernels.hpp"
 #include "modarith.hpp"
 #include "rns_device.hpp"
