@@ -789,11 +789,13 @@ def plain_request_leg(reps=50):
     return plan, res
 
 
-def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False, policy="largest"):
+def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False, policy="largest", weights=None,
+                chain=()):
     """Poisson arrivals (total rate lambda, the superposition of 256 camera
     streams), 70% small-net / 30% large-net requests, keys and plaintexts
     resident, admission by device-memory footprint, continuous batching
-    (largest ready stage group first, oldest first past 20 ms of waiting)."""
+    (largest ready stage group first, oldest first past 20 ms of waiting;
+    the networks in `chain` run a group's stages from one dispatch)."""
     import torch
     from paper_2104_09164_amd import serve
     backends = {}
@@ -801,6 +803,9 @@ def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False, polic
     for name, (plan, ctx, max_batch) in nets.items():
         backends[name] = serve.NetBackend(name, ctx, plan, runner_layers[name], max_batch=max_batch,
                                           slots=2 * max_batch + 8, own_stream=True)
+        if weights and name in weights:
+            backends[name].weight = weights[name]
+        backends[name].chain = name in chain
         N = 1 << plan.log_n
         payloads[name] = [(residues(plan.q, N, (2,), seed + 50 + k), plan.L, plan.scale) for k in range(4)]
     budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
@@ -824,7 +829,8 @@ def serving_leg(nets, rates, counts, seed=21, window=4, per_network=False, polic
         m["requests"] = count
         m["p99_tail_samples"] = max(1, int(round(0.01 * m.get("completed", 0))))
         out[str(rate)] = m
-    out["scheduler"] = {"policy": policy, "max_wait_ms": 20.0, "window": window, "per_network": per_network}
+    out["scheduler"] = {"policy": policy, "max_wait_ms": 20.0, "window": window, "per_network": per_network,
+                        "weights": weights or {}, "chained": sorted(chain)}
     return out
 
 
@@ -961,7 +967,7 @@ def main():
     if not args.no_serve and not args.no_small:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         counts = [args.serve_requests_top if r == max(rates) else args.serve_requests for r in rates]
-        out["serving"] = serving_leg(nets, rates, counts)
+        out["serving"] = serving_leg(nets, rates, counts, window=2, chain=("large",))
     del nets
     torch.cuda.synchronize()
     if not args.no_ntt:

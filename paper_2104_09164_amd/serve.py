@@ -55,6 +55,8 @@ class Backend:
     stages: list = []               # stage names, executed in order
     max_batch: int = 1
     slot_bytes: int = 0             # device footprint of one admitted request
+    weight: float = 1.0             # the "largest" policy's weight of one ready request
+    chain: bool = False             # dispatch a group's remaining stages back to back
 
     def acquire_slot(self) -> int | None: ...
     def release_slot(self, slot: int) -> None: ...
@@ -82,7 +84,10 @@ class Scheduler:
         the stage of the oldest ready request goes first; "largest": the
         stage with the most ready requests goes first (larger batches, more
         throughput under load) unless the oldest ready request has waited
-        longer than max_wait_s since its arrival."""
+        longer than max_wait_s since its arrival; a group counts its requests
+        times its backend's `weight` (1 by default), so that a network whose
+        requests take longer can be served first.  A backend with `chain` set
+        runs a group's remaining stages from one dispatch."""
         self.backends = backends
         self.budget = budget_bytes
         self.window = window
@@ -175,26 +180,34 @@ class Scheduler:
                         key = (name, r.stage)
                         n, first = count.get(key, (0, r))
                         count[key] = (n + 1, first)
-            best = max(count.values(), key=lambda v: (min(v[0], self.backends[v[1].net].max_batch), -v[1].arrival))[1]
+            def score(v):
+                be = self.backends[v[1].net]
+                return (min(v[0], be.max_batch) * getattr(be, "weight", 1.0), -v[1].arrival)
+            best = max(count.values(), key=score)[1]
         be = self.backends[best.net]
         stage = best.stage
         group = [r for r in self.active[best.net] if r.stage == stage and not self._busy(r)][: be.max_batch]
         now = self.clock()
         c0 = time.perf_counter()
+        # a chained backend's group runs all its remaining stages from one
+        # dispatch (enqueued in order on the backend's stream; no regrouping
+        # between stages, no scheduling wait per stage)
+        last = len(be.stages) - 1 if be.chain else stage
         try:
-            h = be.run(stage, [r.slot for r in group])
+            for st in range(stage, last + 1):
+                h = be.run(st, [r.slot for r in group])
+                self.batches.append((best.net, st, len(group)))
         except Exception as e:
             for r in group:
                 self._fail(r, e)
             return None
         self.dispatch_cpu_s += time.perf_counter() - c0
-        self.batches.append((best.net, stage, len(group)))
         for r in group:
             if r.start is None:
                 r.start = now
-            r.stage += 1
+            r.stage = last + 1
             r.pending = h
-        return Dispatch(best.net, stage, group, h)
+        return Dispatch(best.net, last, group, h)
 
     def _busy(self, r: Request) -> bool:
         """A request's next stage is dispatched only once its previous work
@@ -373,7 +386,11 @@ class NetBackend(Backend):
         for _ in range(slots):
             s = {"in": ctx.new_ct(L, plan.scale), "stage": [ctx.new_ct(l) for l in levels],
                  "coef_in": torch.empty(2 * (L + 1) * N, dtype=torch.int64, device=ctx.device),
-                 "coef_out": torch.empty(2 * (self.out_level + 1) * N, dtype=torch.int64, device=ctx.device)}
+                 "coef_out": torch.empty(2 * (self.out_level + 1) * N, dtype=torch.int64, device=ctx.device),
+                 # pinned host staging, allocated once per slot (a slot's buffers are
+                 # reused only after its request has finished)
+                 "host_in": torch.empty(2 * (L + 1) * N, dtype=torch.int64, pin_memory=True),
+                 "host_out": torch.empty(2 * (self.out_level + 1) * N, dtype=torch.int64, pin_memory=True)}
             self.bufs.append(s)
         self.slot_bytes = sum(ctx.ct_bytes(l) for l in levels) + ctx.ct_bytes(L) + \
             8 * 2 * (L + 1) * N + 8 * 2 * (self.out_level + 1) * N
@@ -452,13 +469,14 @@ class NetBackend(Backend):
         check_payload(self.plan, payload)
         coeff, level, scale = payload
         b = self.bufs[slot]
-        host = self.torch.from_numpy(np.ascontiguousarray(coeff).view(np.int64).reshape(-1))
-        b["coef_in"].copy_(host.pin_memory(), non_blocking=True)
+        b["host_in"].numpy()[:] = np.ascontiguousarray(coeff).view(np.int64).reshape(-1)
+        b["coef_in"].copy_(b["host_in"], non_blocking=True)
         ct = b["in"]
         c = ct._c()
         rc = self.he.lib().he_ct_from_coeff_dev(self.ctx.h, self.he.C.c_void_p(b["coef_in"].data_ptr()), level,
                                                 scale, self.he.C.byref(c))
         if rc:
+            self.stream.synchronize()            # the slot's staging copy has landed before the slot is reused
             raise self.he.HeError(rc, "he_ct_from_coeff_dev")
         ct.level, ct.scale = level, scale
         return self._event()
@@ -489,7 +507,7 @@ class NetBackend(Backend):
                                               self.he.C.c_void_p(b["coef_out"].data_ptr()))
         if rc:
             raise self.he.HeError(rc, "he_ct_to_coeff_dev")
-        host = self.torch.empty(b["coef_out"].numel(), dtype=self.torch.int64, pin_memory=True)
+        host = b["host_out"]
         host.copy_(b["coef_out"], non_blocking=True)
         return (self._event(), host, ct.level, ct.scale)
 

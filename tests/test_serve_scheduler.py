@@ -302,3 +302,35 @@ def test_policy_largest_group_first(net, policy, max_wait, size):
     for r in sched.done:
         assert r.error is None
         assert np.array_equal(r.result.data, expected(net, inputs[r.rid]).data)
+
+
+def test_chained_backend_runs_all_stages_per_dispatch(net):
+    """A chained backend runs each group's stages back to back from one
+    dispatch: every request is dispatched once (its group at stage 0 runs to
+    the end), the batches record every stage, and the results are the
+    oracle's bit for bit."""
+    clock = SimClock()
+    pr, o, keys, layers, _ = net
+    be = OracleBackend("small", o, keys, layers, clock)
+    be.chain = True
+    sched = serve.Scheduler({"small": be}, budget_bytes=10 ** 9, clock=clock.now, policy="largest")
+    times = serve.poisson_arrivals(rate=2000.0, count=8, seed=7)
+    reqs = requests(net, 8, times)
+    inputs = {r.rid: r.payload.copy() for r in reqs}
+    started = []
+    pick = sched._pick
+
+    def recording_pick():
+        d = pick()
+        if d is not None:
+            started.append((d.stage, len(d.reqs)))
+        return d
+    sched._pick = recording_pick
+    serve.run_arrivals(sched, reqs, clock=clock.now, sleep=clock.sleep)
+    assert len(sched.done) == 8 and all(r.error is None for r in sched.done)
+    for r in sched.done:
+        assert np.array_equal(r.result.data, expected(net, inputs[r.rid]).data)
+    nst = len(be.stages)
+    assert all(st == nst - 1 for st, _ in started)               # one dispatch per group, to the last stage
+    assert sum(n for _, n in started) == 8
+    assert len(sched.batches) == nst * len(started)
