@@ -560,7 +560,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # folded into a running sum (add_shoup4: 2 v_mul_hi_u32, 3 v_mad_u64_u32,
 # 4 v_mul_lo_u32, 2 v_add3_u32) 11; a plaintext product and its 64-bit
 # accumulation (shoup_lazy4 + add) 14; the lift of c0 by P (Shoup product) 8.
-# Primes below 2^50 in the LDS-shared form (batches of 2 or more) take the
+# Primes below 2^50 in the LDS-shared form (batches of 3 or more) take the
 # inner sums as exact 28-bit column sums: a plaintext product is 4
 # v_mad_u64_u32 (OPS_COL), a plain sum 2 adds (OPS_COL_PLAIN), and splitting
 # each step's value into its two columns 2 (OPS_SPLIT, per value).  The
@@ -570,7 +570,7 @@ OPS_KEY, OPS_PT, OPS_LIFT = 11, 14, 8
 OPS_COL, OPS_COL_PLAIN, OPS_SPLIT = 4, 2, 2
 OPS_LIFT_ADD = 1
 WIDE_Q = 1 << 50
-LDS_MIN_BATCH = 2
+LDS_MIN_BATCH = 3
 # Kernel classes bound by VALU issue rather than HBM (rocprofv3 SQ counters:
 # VALU instructions issued in most of the kernel's cycles, HBM traffic a
 # fraction of the copy rate): their roofline is the integer VALU peak.
@@ -584,7 +584,7 @@ def fused_ops(plan, batch) -> int:
     of Q_l u P plus the lift of c0 on the Q-limbs; the unrotated term adds 2
     lifts and 2 n2 plaintext products per Q-limb.  Hoisted rotate-and-sum
     groups of b bits: the same with 2^b - 1 steps, n2 = 1 and plain sums.
-    Limbs below 2^50 in batches of 2 or more (the LDS-shared form) count the
+    Limbs below 2^50 in batches of 3 or more (the LDS-shared form) count the
     column form of the inner sums (OPS_COL per product, OPS_COL_PLAIN per
     plain sum, OPS_SPLIT per summed value); the others a Shoup product per
     term (OPS_PT).  In that form the lift is read (OPS_LIFT_ADD per step, the

@@ -382,18 +382,19 @@ int he_ntt(he_ctx* ctx, uint32_t n_items, uint64_t* const* items, uint32_t first
  *                   4 while a batch does not fill it); 0 = the register form
  *                   (requests per thread: ks_fuse_g)
  *   "ks_fuse_min_batch"  smallest batch that takes the LDS-shared form
- *                   (1..64, default 2; smaller batches the register form)
+ *                   (1..64, default 3; smaller batches ks_fuse_one's kernel or
+ *                   the register form)
  *   "ks_fuse_orbit" LDS-shared form: 1 (default) = the position blocks
  *                   dealt to each XCD in the order of the cycles of the first
  *                   step's automorphism on blocks (block X reads block P(X)),
  *                   so that the workgroups running together read each
  *                   other's gathers of the step before from L2; 0 = in
  *                   address order
- *   "ks_fuse_one"   a batch of one below ks_fuse_min_batch: 1 (default) = its
- *                   own kernel (one position per thread; on primes below 2^50
- *                   the key and plaintext words read without their Shoup
- *                   companions, the key sums as exact column sums), 0 = the
- *                   register form
+ *   "ks_fuse_one"   batches below ks_fuse_min_batch (with ks_fuse_lds set):
+ *                   1 (default) = their own kernel (one request and position
+ *                   per thread; on primes below 2^50 the key and plaintext
+ *                   words read without their Shoup companions, the key sums
+ *                   as exact column sums), 0 = the register form
  *   "ks_fuse_pair"  LDS-shared form with 4 or 8 requests: 1 = each
  *                   workgroup serves two position blocks, X and P(X), so that
  *                   one block's gathers are the other's of the step before;

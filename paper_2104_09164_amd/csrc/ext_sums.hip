@@ -144,10 +144,11 @@ k_ks_ext_fused(const u64* __restrict__ ext, OwnMap own, StepKeys keys,
 }
 
 
-// One request (a batch of one): the same sums with one position per thread
-// and nothing shared between requests, so the register budget allows a high
-// occupancy.  A batch of one is bound by the key and plaintext streams (read
-// once per request), so on the primes below 2^50 (COL) they are read as
+// Small batches (below ks_fuse_min_batch): the same sums with one request and
+// position per thread, so the register budget allows a high occupancy.  A
+// small batch is bound by the key and plaintext streams (read once per
+// request from HBM, the other requests of a tile finding them in L2), so on
+// the primes below 2^50 (COL) they are read as
 // values only, without their Shoup companions (half the bytes), and both the
 // key sums and the inner sums are exact 28-bit column sums: digit d and key
 // word k (both below q < 2^50) split into 28-bit columns, four multiply-adds
@@ -160,7 +161,8 @@ template <int BETA, int JC, bool COL, bool LKS, bool LMP>
 __device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, const OwnMap& own, const StepKeys& keys,
                                                 const Items& in, const u64* __restrict__ pts, u64* __restrict__ sqp,
                                                 const PrimeConst& P, u64 pw, u64 pws, u32 N, u32 logn, u32 l, u32 nt,
-                                                u32 ne, u32 pr, u32 dstride, u32 alpha, u32 n1, u32 x, u32 t) {
+                                                u32 ne, u32 pr, u32 dstride, u32 alpha, u32 n1, u32 b, u32 x, u32 t) {
+  const u32 B = in.n;
   const bool qlimb = t <= l;
   const u64 q = P.q;
   const size_t comp = (size_t)n1 * JC * ne * N;    // plaintext companions follow the m = n1 JC diagonals
@@ -189,7 +191,7 @@ __device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, con
     }
   };
   if (qlimb) {
-    const u64* c = in.p[0];
+    const u64* c = in.p[b];
     const u64 r0 = shoup(c[(size_t)t * N + x], pw, pws, q), r1 = shoup(c[(size_t)(l + 1 + t) * N + x], pw, pws, q);
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) {
@@ -198,8 +200,8 @@ __device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, con
       inner(jj, r0, r1, pt, ps);
     }
   }
-  const u64* e = ext + (size_t)t * N;
-  const u64* src = own.ptr[0] + (size_t)t * N;
+  const u64* e = ext + ((size_t)b * dstride * ne + t) * N;
+  const u64* src = own.ptr[b] + (size_t)t * N;
   for (u32 i = 1; i < n1; ++i) {
     const u32 y = galois_perm(x, keys.galois[i - 1], logn);
     const u64* key = keys.key[i - 1];
@@ -229,7 +231,7 @@ __device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, con
       }
       ks_dot<BETA, LKS>(d, kb, kbs, ka, kas, P, !qlimb, r0, r1);
     }
-    if (qlimb) r0 += shoup_lazy(in.p[0][(size_t)t * N + y], pw, pws, q);
+    if (qlimb) r0 += shoup_lazy(in.p[b][(size_t)t * N + y], pw, pws, q);
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) {
       u64 pt, ps;
@@ -239,13 +241,15 @@ __device__ __forceinline__ void ks_ext_one_body(const u64* __restrict__ ext, con
   }
 #pragma unroll
   for (int jj = 0; jj < JC; ++jj) {
-    u64* o = sqp + (size_t)jj * 2 * ne * N;
+    u64* o = sqp + ((size_t)jj * B + b) * 2 * ne * N;
     o[(size_t)t * N + x] = COL ? col_final(w0[jj], P) : mp_final<LMP>(a0[jj], P);
     o[(size_t)(ne + t) * N + x] = COL ? col_final(w1[jj], P) : mp_final<LMP>(a1[jj], P);
   }
 }
 
-// Grid (N / BS) x ne tiles, one request.
+// 1-D grid of B requests x (N / BS, ne) tiles (xcd_decode: the requests of a
+// tile run back to back on one XCD and find its key and plaintext words in
+// L2).
 template <int BETA, int JC>
 __global__ void __launch_bounds__(BS) k_ks_ext_one(const u64* __restrict__ ext, OwnMap own, StepKeys keys, Items in,
                                                    const u64* __restrict__ pts, u64* __restrict__ sqp,
@@ -253,7 +257,8 @@ __global__ void __launch_bounds__(BS) k_ks_ext_one(const u64* __restrict__ ext, 
                                                    u32 N, u32 logn, u32 l, u32 nq, u32 np, u32 dstride, u32 alpha,
                                                    u32 n1) {
   const u32 nkb = N / BS, ne = l + 1 + np, nt = nq + np;
-  const u32 tile = blockIdx.x;
+  u32 b, tile;
+  xcd_decode(blockIdx.x, in.n, nkb * ne, b, tile);
   const u32 x = (tile % nkb) * BS + threadIdx.x, t = tile / nkb;
   const u32 pr = t <= l ? t : nq + (t - l - 1);
   const PrimeConst P = pc[pr];
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(BS) k_ks_ext_one(const u64* __restrict__ ext, 
   const u64 pw = t <= l ? pmod[2 * t] : 0, pws = t <= l ? pmod[2 * t + 1] : 0;
 #define HE_ONE_BODY(C, K, M)                                                                                    \
   ks_ext_one_body<BETA, JC, C, K, M>(ext, own, keys, in, pts, sqp, P, pw, pws, N, logn, l, nt, ne, pr, dstride, \
-                                     alpha, n1, x, t)
+                                     alpha, n1, b, x, t)
   if (P.q < kWideQ)
     HE_ONE_BODY(true, true, true);
   else if (P.q < kLazyMP)
@@ -286,14 +291,15 @@ int launch_ks_ext_fused(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* ext,
                  (pts ? 2.0 * n1 * n2 * ne : 0.0)) * (8.0 * (double)c->N));
   // the LDS-shared form with W requests per workgroup, W halved (down to 4)
   // while the batch does not fill it (idle waves still share the tile
-  // loads); batches below ks_fuse_min_batch take the register form
+  // loads); smaller batches the small-batch kernel or the register form
   u32 W = (u32)c->ks_fuse_lds;
   while (W > 4 && B < W) W /= 2;
   if (W && B >= (u32)c->ks_fuse_min_batch)
     return launch_ks_ext_lds(c, l, B, n1, n2, ext, own, keys, in, pts, sqp, beta, ne, W, lift, ts);
-  if (B == 1 && c->ks_fuse_one) {
-    // a batch of one: one position per thread, values-only streams below 2^50
-    dim3 grid1((c->N / BS) * ne);
+  if (W && c->ks_fuse_one) {
+    // batches below ks_fuse_min_batch: one request and position per thread,
+    // values-only streams below 2^50 (ks_fuse_lds = 0 keeps the register form)
+    dim3 grid1(B * (c->N / BS) * ne);
 #define HE_LAUNCH_ONE(BT, J)                                                                                      \
   HE_LAUNCH(ts, (k_ks_ext_one<BT, J>), grid1, dim3(BS), c->stream, ext, own, keys, in, pts, sqp, c->d_pc,        \
             c->d_moddown, c->N, c->log_n, l, c->nq, c->np, c->dnum, c->alpha, n1)

@@ -114,7 +114,7 @@ struct he_ctx {
   int64_t ks_fuse = 1;          // lazy-ModDown baby steps: inner product fused into the inner sums
   int64_t ks_fuse_g = 0;        // fused extended sums: 1 = half the items per thread
   int64_t ks_fuse_waves = 0;    // fused extended sums: 3 = compiled for 3 waves per SIMD
-  int64_t ks_fuse_min_batch = 2;  // fused extended sums: smallest batch that takes the LDS-shared form
+  int64_t ks_fuse_min_batch = 3;  // fused extended sums: smallest batch that takes the LDS-shared form
   int64_t ks_fuse_pair = 0;       // LDS-shared form: pairs of blocks along the automorphism per workgroup
   int64_t ks_fuse_orbit = 1;      // LDS-shared form: blocks dealt to each XCD along the automorphism's cycles
   int64_t ks_fuse_one = 1;        // a batch of one: its own kernel (values-only streams below 2^50)

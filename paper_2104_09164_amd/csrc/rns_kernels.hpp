@@ -116,8 +116,8 @@ int launch_ext_multplain(he_ctx* c, u32 l, u32 B, u32 n1, u32 n2, const u64* u, 
 // from own.ptr[b]): one launch, no per-step products in memory.  n1 >= 2,
 // n2 in {1, 2, 4, 8}, keys = the n1 - 1 baby steps.  pts = null (n2 = 1): the
 // plain sum sqp[b] = sum_{i < n1} r_i(b) (a hoisted rotate-and-sum group).
-// Batches of ks_fuse_min_batch or more take the LDS-shared form, a batch of
-// one the single-request kernel (knob ks_fuse_one), others the register form.
+// Batches of ks_fuse_min_batch or more take the LDS-shared form, smaller ones
+// the small-batch kernel (knob ks_fuse_one), else the register form.
 // lift: B (l + 1) N words of scratch, free during the call, that the
 // LDS-shared form fills with P c0 mod q on the Q-limbs (required there).
 // The LDS-shared form of launch_ks_ext_fused (ext_sums_lds.hip) with W

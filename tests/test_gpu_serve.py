@@ -28,12 +28,14 @@ def build(pr, shapes, scale_bits, max_batch, slots, graphs=True):
     return o, keys, lays, be
 
 
-@pytest.mark.parametrize("graphs", [True, False])
-def test_serving_mix_equals_alone_and_oracle(graphs):
-    """Stages replayed from per-(stage, bucket) graphs, and launched eagerly."""
+@pytest.mark.parametrize("graphs,chain", [(True, False), (False, False), (True, True)])
+def test_serving_mix_equals_alone_and_oracle(graphs, chain):
+    """Stages replayed from per-(stage, bucket) graphs, and launched eagerly;
+    and with a group's stages chained from one dispatch."""
     pr = params.make(12, [50, 40, 40, 40, 40], [50, 50], 2, 30)
     shapes = [(8, 64, 4), (2, 8, 2)]
     o, keys, lays, be = build(pr, shapes, 30, max_batch=4, slots=6, graphs=graphs)
+    be.chain = chain
     count = 12
     cts = []
     for r in range(count):

@@ -151,7 +151,7 @@ def test_knob_api_validation():
     q, p = he.prime_chain(12, [50, 40], [50])
     ctx = he.Context(12, q, p, 1)
     defaults = {"ntt_chunk_mb": 0, "ntt_cols": 16, "ntt_cols_b": 0, "ntt_single_pass": 0, "ks_fuse": 1,
-                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "ks_fuse_min_batch": 2, "ks_fuse_pair": 0,
+                "ks_fuse_g": 0, "ks_fuse_waves": 0, "ks_fuse_lds": 8, "ks_fuse_min_batch": 3, "ks_fuse_pair": 0,
                 "ks_fuse_orbit": 1, "ks_fuse_one": 1,
                 "trace": 0}
     for k, v in defaults.items():
