@@ -162,8 +162,8 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
         col_mad(w0[jj], r0, pt, ps);
         col_mad(w1[jj], r1, pt, ps);
       } else if (MODE == 1) {
-        a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, false);
-        a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, false);
+        a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P);
+        a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P);
       } else {
         a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
         a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);
@@ -195,7 +195,15 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
           ks_dot<BETA, MODE == 0 || MODE == 3>(d, kb, kbs, ka, kas, P, false, r0, r1);
         }
         if (qlimb) r0 += c0y;                          // below q, read for this step's automorphism
-        const bool red = i % 3 == 0;                  // the inner sums of MODE 1: reduced before every third product
+        if (MODE == 1 && i % 3 == 0) {
+          // the inner sums of MODE 1 (q >= 2^55): reduced before every third
+          // product, in one uniform branch per step
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) {
+            a0[jj] = reduce_lazy_wide(a0[jj], P.q, P.mu);
+            a1[jj] = reduce_lazy_wide(a1[jj], P.q, P.mu);
+          }
+        }
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
           const u64 pt = cur[4 * BETA + 2 * jj][p], ps = cur[4 * BETA + 2 * jj + 1][p];
@@ -203,8 +211,8 @@ __device__ __forceinline__ void ks_ext_lds_body(const u64* __restrict__ ext, con
             col_mad(w0[jj], r0, pt, ps);
             col_mad(w1[jj], r1, pt, ps);
           } else if (MODE == 1) {
-            a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P, red);
-            a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P, red);
+            a0[jj] = mp_add_mid(a0[jj], r0, pt, ps, P);
+            a1[jj] = mp_add_mid(a1[jj], r1, pt, ps, P);
           } else {
             a0[jj] = mp_add<MODE == 0>(a0[jj], r0, pt, ps, P);
             a1[jj] = mp_add<MODE == 0>(a1[jj], r1, pt, ps, P);

@@ -67,10 +67,15 @@ __device__ __forceinline__ u64 add_shoup4(u64 X, u64 x, u64 w, u64 wsh, u64 nq) 
 // bits and one 32-bit high product of the top word estimates the quotient:
 // qh = floor(x1 mu / 2^32) <= floor(x/q) <= qh + 2 (the dropped x0 mu / 2^64
 // and the rounding of mu each cost less than 1), so x - qh q is in [0, 3q).
-__device__ __forceinline__ u64 reduce_lazy(u64 x, u64 q, u64 mu) {
-  if (mu >> 32) return shoup_lazy4(x, 1, mu, q);
+// reduce_lazy's q > 2^32 path on its own, for callers whose primes are all
+// above 2^32 (no branch on mu in the loop).
+__device__ __forceinline__ u64 reduce_lazy_wide(u64 x, u64 q, u64 mu) {
   const u32 qh = __umulhi((u32)(x >> 32), (u32)mu);
   return x - (u64)qh * q;
+}
+__device__ __forceinline__ u64 reduce_lazy(u64 x, u64 q, u64 mu) {
+  if (mu >> 32) return shoup_lazy4(x, 1, mu, q);
+  return reduce_lazy_wide(x, q, mu);
 }
 
 // x < 2m (m <= 2^63): x - m if x >= m; negm = 2^64 - m supplied from memory so

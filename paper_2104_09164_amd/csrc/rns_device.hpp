@@ -102,12 +102,11 @@ __device__ __forceinline__ void ks_dot_mid(const u64 (&x)[BETA], const u64 (&kb)
   oa = csub_signed(sa, P.q << 3);
 }
 // Inner sums of the fused kernels for 2^55 <= q < 2^60: products (each below
-// 4q) added without reduction and the running sum brought below 3q by
-// reduce_lazy before every third product (at most 3q + 3 * 4q = 15q < 2^64);
-// closed by mp_final<true>.
+// 4q) added without reduction; the caller brings the running sum below 3q
+// by reduce_lazy_wide before every third product (at most 3q + 3 * 4q =
+// 15q < 2^64); closed by mp_final<true>.
 constexpr u64 kMidQ = 1ull << 60;
-__device__ __forceinline__ u64 mp_add_mid(u64 acc, u64 x, u64 pt, u64 ps, const PrimeConst& k, bool reduce) {
-  if (reduce) acc = reduce_lazy(acc, k.q, k.mu);
+__device__ __forceinline__ u64 mp_add_mid(u64 acc, u64 x, u64 pt, u64 ps, const PrimeConst& k) {
   return acc + shoup_lazy4(x, pt, ps, k.q);
 }
 
