@@ -398,9 +398,16 @@ def ntt_roofline(nt):
             traffic = prof["fetch_bytes_per_call"] + prof["write_bytes_per_call"]
     except (OSError, KeyError, ValueError):
         traffic = None
+    # the same launches against the integer VALU peak: logN / 2 butterflies per coefficient, and
+    # the final reduction of every coefficient
+    ops = polys * 65536 * (16 // 2 * OPS_BUTTERFLY + OPS_NTT_OUT)
+    tops = ops / t_call / 1e12
     return {"bound": "hbm", "kernel": f"forward NTT N=2^16, one call = phase-A + phase-B launch over {polys} limb-polys",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic, "alg_bytes": alg, "ms_per_call": t_call * 1e3}
+            "traffic": traffic, "alg_bytes": alg, "ms_per_call": t_call * 1e3,
+            "valu_view": {"achieved_tops": tops, "peak": VALU_PEAK_TOPS, "frac": tops / VALU_PEAK_TOPS,
+                          "alg_ops_per_call": ops, "ops_per_butterfly": OPS_BUTTERFLY,
+                          "ops_per_coefficient_out": OPS_NTT_OUT}}
 
 
 def cpu_model() -> str:
@@ -569,6 +576,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_KEY, OPS_PT, OPS_LIFT = 11, 14, 8
 OPS_COL, OPS_COL_PLAIN, OPS_SPLIT = 4, 2, 2
 OPS_LIFT_ADD = 1
+# Forward NTT on primes below 2^57 (no per-stage conditional subtraction): a
+# butterfly is add_shoup4 (11) plus the difference 2X + 4q - S (one
+# v_lshl_add_u64 and a 64-bit subtract, 3); each coefficient's final
+# reduction (reduce_lazy, then two conditional subtractions) about 14.
+OPS_BUTTERFLY, OPS_NTT_OUT = 14, 14
 WIDE_Q = 1 << 50
 LDS_MIN_BATCH = 3
 # Kernel classes bound by VALU issue rather than HBM (rocprofv3 SQ counters:
